@@ -1,0 +1,222 @@
+"""Benchmark of the level-scheduled L+U solve path on one MI355X.
+
+Workload (default): 3D 7-point Poisson on a 128^3 grid (n = 2,097,152, natural
+ordering, 382 levels per triangle), ILU(0) factors in FP64 stored as HEC with
+ELL width 3 per triangle, one right-hand side U[-1,1] (seed 2).  One step is
+one preconditioner application z = (LU)^{-1} r: the gather of r into level
+order, the level-scheduled L solve, the map into U's order, the U solve and
+the scatter of z (eq. (1), Algorithm 2).  Inputs are resident in HBM before
+timing starts.  The same factors then drive restarted GMRES(30) to a true
+relative residual of 1e-10, timed as a whole solve.
+
+value = counted L+U bytes per application / time per application (GB/s);
+counted bytes = off-diagonal values and column indices of L and U, U's
+diagonal, the two level permutations, and per RHS one read and one write of
+each of b, y, x (y twice); ELL padding excluded.
+
+The CPU baseline is the test oracle (serial C substitution on CSR, natural
+order) timed on a bounded number of full L+U applications of the same system.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def counted_bytes(n, nnz_l, nnz_u, nrhs, sv=8, unit_l=True):
+    """Algorithmic bytes of one L+U application (see module docstring)."""
+    diag = n * sv * (1 if unit_l else 2)
+    return (nnz_l + nnz_u) * (sv + 4) + diag + 2 * 4 * n + nrhs * 4 * n * sv
+
+
+def per_launch_bytes(n, nnz, nrhs, sv=8, diag=False):
+    """Algorithmic bytes of one triangular-solve launch: values + indices,
+    the diagonal if stored, one permutation, read b and write x per RHS."""
+    return nnz * (sv + 4) + (n * sv if diag else 0) + 4 * n + nrhs * 2 * n * sv
+
+
+def kernel_source_hash():
+    """Short hash of the triangular-solve kernel sources (to tie counter
+    readings to the code they were taken on)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("tri_kernels.hip", "hec_dev.h"):
+        with open(os.path.join(ROOT, "paper_1606_00541_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summaries
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings), or None
+    when no summary matches the current kernel sources."""
+    src = kernel_source_hash()
+    pdir = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(pdir):
+        return None
+    for fn in sorted(os.listdir(pdir)):
+        if not fn.endswith(".md"):
+            continue
+        for line in open(os.path.join(pdir, fn)):
+            if not line.startswith("TRAFFIC "):
+                continue
+            kv = dict(t.split("=", 1) for t in line.split()[1:])
+            if kv.get("kernel") == kernel and kv.get("workload") == workload and kv.get("src") == src:
+                return 1024.0 * (float(kv["fetch_kib"]) * float(kv["fetch_scale"]) +
+                                 float(kv["write_kib"]) * float(kv["write_scale"]))
+    return None
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--grid", type=int, default=128)
+    ap.add_argument("--schedule", default="owner_persistent",
+                    choices=["level_launch", "level_persistent", "owner_persistent"])
+    ap.add_argument("--no-krylov", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="also run one device copy of this size (for counter calibration)")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the level-scheduled solve of one system does not shard "
+              "(see DESIGN.md); run with --gpus 1", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1606_00541_amd as H
+    import synth
+
+    torch.cuda.set_device(0)
+    s = args.grid
+    A = synth.poisson3d(s)
+    n = A.n
+    t0 = time.time()
+    f = H.ilu_setup(A, "ilu0", tune=H.tune_default(schedule=args.schedule))
+    setup_s = time.time() - t0
+    pl, pu = H.ilu_plans(f)
+    stl, stu = H.tri_plan_stats(pl), H.tri_plan_stats(pu)
+    r = torch.from_numpy(synth.rhs(n, 1, 2)).cuda()
+    z = torch.empty_like(r)
+    stream = torch.cuda.current_stream()
+
+    B = counted_bytes(n, stl["nnz_offdiag"], stu["nnz_offdiag"], 1)
+    for _ in range(args.warmup):
+        H.ilu_apply(f, r, z)
+    torch.cuda.synchronize()
+    # HIP events on the stream the kernels are launched on (torch's current stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        H.ilu_apply(f, r, z)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    gbs = B / (ms * 1e-3) / 1e9
+
+    # dominant kernel: the triangular-solve kernel; L and U launches share it
+    bl = per_launch_bytes(n, stl["nnz_offdiag"], 1, diag=False)
+    bu = per_launch_bytes(n, stu["nnz_offdiag"], 1, diag=True)
+    if args.schedule == "level_launch":
+        kname = "k_level"
+        launches = stl["nlev"] + stu["nlev"]
+    else:
+        kname = "k_persistent"
+        launches = 2
+    per_launch = (bl + bu) / launches
+    kernel_ms = ms / launches
+    achieved = per_launch / (kernel_ms * 1e-3) / 1e9
+    sched_tag = {"owner_persistent": "owner", "level_persistent": "level", "level_launch": "launch"}[args.schedule]
+    traffic = measured_traffic(kname, "poisson%d_ilu0_f64_%s" % (s, sched_tag))
+    roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                "algorithmic_bytes_per_launch": int(per_launch),
+                "traffic": None if traffic is None else int(traffic)}
+
+    out = {
+        "metric": "L+U solve GB/s & solves/s, FP64 vs FP32+refine/batched, at 1e-10 rel resid",
+        "value": round(gbs, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "3D 7-point Poisson %d^3 (n=%d), ILU(0) FP64, HEC ELL width %d, 1 RHS U[-1,1] "
+                               "seed 2; step = one L+U preconditioner application" % (s, n, stl["ell_width"]),
+                   "n": n, "nnz_offdiag_L": stl["nnz_offdiag"], "nnz_offdiag_U": stu["nnz_offdiag"],
+                   "nlev_L": stl["nlev"], "nlev_U": stu["nlev"], "schedule": args.schedule,
+                   "workgroups": stl["num_groups"], "counted_bytes_per_step": int(B),
+                   "setup_s": round(setup_s, 3)},
+        "solves_per_s": round(1000.0 / ms, 2),
+        "roofline": roofline,
+    }
+
+    if args.calibrate_copy_mib > 0:
+        src = torch.empty(args.calibrate_copy_mib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+        src.fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = int(src.numel() * 8)
+
+    if not args.no_krylov:
+        M = H.hec_from_csr(A)
+        b = torch.from_numpy(synth.rhs(n, 1, 2)).cuda()
+        x = torch.zeros_like(b)
+        torch.cuda.synchronize()
+        t1 = time.time()
+        st, info = H.krylov_solve(M, f, b, x, method="gmres", m=30, rtol=1e-10)
+        torch.cuda.synchronize()
+        ks = time.time() - t1
+        out["krylov"] = {"method": "GMRES(30)+ILU(0)", "status": int(st), "iters": info[0].iters,
+                         "precond_applies": info[0].precond_applies, "relres": info[0].relres,
+                         "seconds": round(ks, 4), "systems_per_s": round(1.0 / ks, 4)}
+
+    if not args.no_cpu_baseline:
+        import oracle
+
+        L, U = oracle.ilu0(A)
+        rr = synth.rhs(n, 1, 2)
+        oracle.ilu_apply(L, U, rr)  # warm
+        reps, t2 = 0, time.time()
+        while time.time() - t2 < args.cpu_seconds:
+            oracle.ilu_apply(L, U, rr)
+            reps += 1
+        cs = (time.time() - t2) / reps
+        zr = oracle.ilu_apply(L, U, rr)
+        err = float(np.linalg.norm(z.cpu().numpy() - zr) / np.linalg.norm(zr))
+        out["cpu_baseline"] = {"value": round(B / cs / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+                               "sample": "%d full L+U applications of the same %d^3 system (serial C "
+                                         "substitution on CSR, natural order)" % (reps, s),
+                               "seconds_per_apply": round(cs, 5)}
+        out["parity_relerr_vs_oracle"] = err
+    out["paper_context"] = ("paper (Tesla C2050 vs Xeon X5570, FP64): triangular solves ~7x, "
+                            "linear solver ~10x; another machine, not a target")
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

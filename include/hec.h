@@ -1,0 +1,295 @@
+/*
+ * hec.h -- C ABI of the HEC level-scheduled triangular-solve library for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library implements the method of Chen, Liu and Yang, "Parallel
+ * Triangular Solvers on GPU": sparse lower and upper triangular solves on the
+ * HEC (hybrid ELL + CSR) format, scheduled by level sets, applied as ILU(0),
+ * ILU(k), ILUT and Restricted Additive Schwarz preconditioners inside
+ * restarted GMRES and BiCGSTAB.
+ *
+ * Conventions shared by every entry point:
+ *  - Indices are int32_t and 0-based.  Host CSR inputs (rowptr[n+1], col[nnz],
+ *    val[nnz]) must have each row sorted by strictly ascending column; they are
+ *    copied, and the caller keeps ownership.
+ *  - Vectors are caller-owned DEVICE pointers on the device that was current
+ *    when the handle was created, laid out [n][nrhs] with the right-hand-side
+ *    index fastest.  Input and output vectors must not overlap unless a
+ *    function says otherwise.
+ *  - Every device call takes a hipStream_t and is asynchronous on it, except
+ *    krylov_solve, which synchronizes the stream to return its info.
+ *  - Every function returns hec_status_t; on error the handle outputs are left
+ *    untouched and hec_last_error() returns a thread-local description.  No
+ *    C++ exception crosses this interface.
+ *  - Opaque handles are owned by the library until their *_destroy call.
+ *    Destroy functions accept NULL.
+ */
+#ifndef HEC_H
+#define HEC_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum hec_status {
+    HEC_OK = 0,
+    HEC_ERR_INVALID_ARG = 1,    /* bad size, NULL pointer, wrong handle kind */
+    HEC_ERR_NOT_TRIANGULAR = 2, /* an entry on the wrong side of the diagonal */
+    HEC_ERR_UNSORTED = 3,       /* a row not sorted by strictly ascending column */
+    HEC_ERR_MISSING_DIAG = 4,   /* a row without its diagonal (non-unit solve) */
+    HEC_ERR_ZERO_PIVOT = 5,     /* a zero or non-finite diagonal / pivot */
+    HEC_ERR_ALLOC = 6,          /* host or device allocation failed */
+    HEC_ERR_HIP = 7,            /* HIP runtime error; text kept in hec_last_error */
+    HEC_ERR_NOT_CONVERGED = 8,  /* Krylov solver hit maxit */
+    HEC_ERR_BREAKDOWN = 9,      /* Krylov breakdown (zero inner product) */
+    HEC_ERR_CAPACITY = 10,      /* persistent grid larger than co-residency */
+    HEC_ERR_TIMEOUT = 11,       /* a device-side wait exceeded its spin limit */
+    HEC_ERR_NO_DEVICE = 12      /* handle built host-only, or no GPU */
+} hec_status_t;
+
+typedef enum hec_dtype { HEC_F64 = 0, HEC_F32 = 1 } hec_dtype_t;
+typedef enum hec_uplo { HEC_LOWER = 0, HEC_UPPER = 1 } hec_uplo_t;
+
+/* How the level sets are executed on the device (all give bit-identical
+ * results for the same plan, since every row is computed the same way). */
+typedef enum hec_schedule {
+    HEC_SCHED_AUTO = 0,
+    HEC_SCHED_LEVEL_LAUNCH = 1,      /* one kernel launch per level (Algorithm 2 shape) */
+    HEC_SCHED_LEVEL_PERSISTENT = 2,  /* one persistent launch; each level split into
+                                        per-workgroup chunks, chunk-to-chunk waits */
+    HEC_SCHED_OWNER_PERSISTENT = 3   /* one persistent launch; each workgroup owns a
+                                        connected set of rows across all levels and
+                                        keeps their solution in LDS */
+} hec_schedule_t;
+
+typedef enum hec_ilu_kind { HEC_ILU0 = 0, HEC_ILUK = 1, HEC_ILUT = 2 } hec_ilu_kind_t;
+typedef enum hec_krylov { HEC_GMRES = 0, HEC_FGMRES = 1, HEC_BICGSTAB = 2 } hec_krylov_t;
+typedef enum hec_precond_kind {
+    HEC_PRECOND_NONE = 0, HEC_PRECOND_ILU = 1, HEC_PRECOND_RAS = 2
+} hec_precond_kind_t;
+
+/* Tuning knobs for the analysis / execution layout.  Fill with
+ * hec_tune_default() and override fields. */
+typedef struct hec_tune {
+    int32_t ell_width;      /* HEC ELL width w; -1 = smallest w with at most half the
+                               rows having more than w off-diagonals */
+    int32_t schedule;       /* hec_schedule_t */
+    int32_t num_groups;     /* persistent workgroups; 0 = the device's co-resident capacity */
+    int32_t merge_rows;     /* level-merge threshold: a level with fewer rows than this
+                               is not split across workgroups */
+    int32_t group_lanes;    /* lanes cooperating on one row when a step holds long
+                               CSR tails (1, 2, 4, 8, 16, 32 or 64); 0 = auto */
+    int32_t long_row;       /* CSR-tail length from which a step is run with
+                               group_lanes cooperating lanes per row */
+    int32_t part_rows;      /* owner schedule: target rows per owned part (0 = auto) */
+    int32_t host_only;      /* 1 = build the host plan only (no device upload) */
+    int32_t max_nrhs;       /* workspace is allocated for up to this many RHS (grows on demand) */
+    int32_t block_threads;  /* threads per workgroup (64..1024, multiple of 64) */
+} hec_tune_t;
+
+/* Per-RHS outcome of krylov_solve. */
+typedef struct hec_krylov_info {
+    int32_t status;          /* HEC_OK, HEC_ERR_NOT_CONVERGED or HEC_ERR_BREAKDOWN */
+    int32_t iters;           /* Krylov iterations (Arnoldi steps / BiCGSTAB steps) */
+    int32_t restarts;        /* completed restart cycles */
+    int32_t precond_applies; /* preconditioner applications */
+    double relres;           /* final true ||b - A x||_2 / ||b||_2, computed in FP64 */
+} hec_krylov_info_t;
+
+/* Statistics of a triangular plan. */
+typedef struct tri_stats {
+    int32_t n, nlev, ell_width, ld, num_groups, nsteps, nwaits, schedule;
+    int64_t nnz_offdiag;     /* stored off-diagonal entries */
+    int64_t nnz_tail;        /* off-diagonals in the CSR remainder */
+    int64_t lds_bytes;       /* LDS per workgroup used by the persistent kernel */
+    int32_t unit_diag, dtype;
+} tri_stats_t;
+
+typedef struct hec_matrix_s *hec_matrix_t;
+typedef struct tri_plan_s *tri_plan_t;
+typedef struct ilu_s *ilu_t;
+typedef struct ras_s *ras_t;
+typedef struct hec_graph_s *hec_graph_t;
+
+typedef struct hec_precond {
+    int32_t kind;   /* hec_precond_kind_t */
+    void *handle;   /* ilu_t or ras_t (borrowed) */
+} hec_precond_t;
+
+/* Thread-local text of the last error on this thread ("" if none). */
+const char *hec_last_error(void);
+
+/* Default tuning: ell_width -1, schedule AUTO, all other knobs auto. */
+hec_status_t hec_tune_default(hec_tune_t *tune);
+
+/* ---------------------------------------------------------------------------
+ * HEC matrix (Section 2.1): an ELL part of width w stored column-major with
+ * leading dimension ld (n rounded up to 64 rows, so each ELL column starts on
+ * a 256-byte boundary for the 4-byte indices), padded with value 0 and column
+ * n, plus a CSR remainder holding the entries past the first w of each row.
+ * This general form backs the Krylov residual b - A x.
+ * ell_width: -1 = median row length.  dt: storage type of the values; val
+ * points to double (HEC_F64) or float (HEC_F32).
+ * ------------------------------------------------------------------------- */
+hec_status_t hec_from_csr(int32_t n, const int32_t *rowptr, const int32_t *col, const void *val,
+                          hec_dtype_t dt, int32_t ell_width, hec_matrix_t *out);
+/* y = A x (FP64 vectors, [n][nrhs]). */
+hec_status_t hec_spmv(hec_matrix_t A, const double *x, double *y, int32_t nrhs, hipStream_t stream);
+/* Copy the HEC arrays back to host memory.  Pass NULL arrays to query sizes:
+ * *width, *ld and *tail_nnz are always written.  ell_col/ell_val hold
+ * width*ld entries (column-major), csr_ptr n+1, csr_col/csr_val tail_nnz;
+ * ell_val/csr_val are double. */
+hec_status_t hec_matrix_export(hec_matrix_t A, int32_t *width, int32_t *ld, int64_t *tail_nnz,
+                               int32_t *ell_col, double *ell_val, int32_t *csr_ptr,
+                               int32_t *csr_col, double *csr_val);
+void hec_matrix_destroy(hec_matrix_t A);
+
+/* ---------------------------------------------------------------------------
+ * Triangular plans: Algorithm 1 (preprocessing) of Section 2.2.
+ *  1. level of every row by eq. (2) (structural: every stored off-diagonal
+ *     entry counts; levels are 1-based);
+ *  2. the map m of eq. (3): rows sorted by level, ascending index inside a
+ *     level (an upper triangle is first reversed by t(i) = n-1-i, so its rows
+ *     inside a level come in descending original index);
+ *  3. L reordered to L' (entry order inside a row kept, diagonal last);
+ *  4. L' converted to HEC; the first min(w, len-1) off-diagonals of a row go
+ *     to ELL, the rest and the diagonal (last) to the CSR remainder, so every
+ *     CSR row holds at least one element.
+ * The device copy additionally holds the execution layout chosen by the
+ * schedule (see hec_schedule_t).
+ * uplo: HEC_LOWER needs col <= row for every entry, HEC_UPPER col >= row.
+ * unit_diag: 1 = the diagonal is 1 and is neither required nor read.
+ * val: double (HEC_F64) or float (HEC_F32); FP32 plans store factors and solve
+ * in FP32.  tune may be NULL (defaults).
+ * Errors: INVALID_ARG, UNSORTED, NOT_TRIANGULAR, MISSING_DIAG, ZERO_PIVOT,
+ * ALLOC, HIP, CAPACITY.
+ * ------------------------------------------------------------------------- */
+hec_status_t tri_analyze(int32_t n, const int32_t *rowptr, const int32_t *col, const void *val,
+                         hec_dtype_t dt, hec_uplo_t uplo, int32_t unit_diag,
+                         const hec_tune_t *tune, tri_plan_t *out);
+/* Level data of eq. (2)-(3): *nlev; levelptr[nlev+1] (first position of each
+ * level); perm[n] (new position -> original row).  Arrays may be NULL. */
+hec_status_t tri_plan_info(tri_plan_t plan, int32_t *n, int32_t *nlev, int32_t *levelptr,
+                           int32_t *perm);
+/* The HEC of L' (level order, paper layout: diagonal last in the CSR part),
+ * copied to host; same size-query convention as hec_matrix_export. */
+hec_status_t tri_plan_hec(tri_plan_t plan, int32_t *width, int32_t *ld, int64_t *tail_nnz,
+                          int32_t *ell_col, double *ell_val, int32_t *csr_ptr, int32_t *csr_col,
+                          double *csr_val);
+hec_status_t tri_plan_stats(tri_plan_t plan, tri_stats_t *stats);
+/* Execution order chosen for the device: xperm[n] (device position -> original
+ * row) and the workgroup owning each device position (owner[n]); may be NULL. */
+hec_status_t tri_plan_layout(tri_plan_t plan, int32_t *xperm, int32_t *owner);
+
+/* Solve L x = b (Algorithm 2): b is gathered into level order, the levels are
+ * solved in order with all rows of a level computed simultaneously, and x is
+ * scattered back to the original order.  b, x: device, [n][nrhs] of vec_dt
+ * (HEC_F64 or HEC_F32; FP64 vectors with an FP32 plan are converted on load and
+ * store).  Errors: INVALID_ARG (plan kind, sizes), NO_DEVICE, HIP, TIMEOUT
+ * (reported by the next call on the plan, since the solve is asynchronous). */
+hec_status_t tri_solve_lower(tri_plan_t L, const void *b, void *x, int32_t nrhs, hec_dtype_t vec_dt,
+                             hipStream_t stream);
+/* Solve U x = b; the plan was built from U reversed by t(i) = n-1-i. */
+hec_status_t tri_solve_upper(tri_plan_t U, const void *b, void *x, int32_t nrhs, hec_dtype_t vec_dt,
+                             hipStream_t stream);
+void tri_plan_destroy(tri_plan_t plan);
+
+/* ---------------------------------------------------------------------------
+ * ILU preconditioners (Section 3): the host factors A (ILU(0): A's pattern;
+ * ILU(k): level-of-fill k; ILUT(p, tol): dual dropping with tol relative to the
+ * row's 2-norm and at most p entries in each of L and U) into a unit lower L
+ * and an upper U, and builds the two triangular plans.  factor_dt = HEC_F32
+ * rounds the FP64 factors once to FP32.
+ * Errors: as tri_analyze, plus ZERO_PIVOT from the factorization.
+ * ------------------------------------------------------------------------- */
+hec_status_t ilu_setup(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val,
+                       hec_ilu_kind_t kind, int32_t k, double tol, int32_t p,
+                       hec_dtype_t factor_dt, const hec_tune_t *tune, ilu_t *out);
+/* Copy a factor (which = 0: L with its unit diagonal stored last in each row;
+ * 1: U, diagonal first) to host in FP64.  Pass NULL arrays to query *nnz. */
+hec_status_t ilu_factor(ilu_t ilu, int32_t which, int64_t *nnz, int32_t *rowptr, int32_t *col,
+                        double *val);
+/* Borrowed plan handles of L and U (destroyed with the ilu). */
+hec_status_t ilu_plans(ilu_t ilu, tri_plan_t *L, tri_plan_t *U);
+/* z = (LU)^{-1} r by eq. (1): L y = r, then U z = y; y never leaves the device
+ * and stays in level order between the two solves.  r, z: device [n][nrhs] of
+ * vec_dt; r and z may alias. */
+hec_status_t ilu_apply(ilu_t ilu, const void *r, void *z, int32_t nrhs, hec_dtype_t vec_dt,
+                       hipStream_t stream);
+void ilu_destroy(ilu_t ilu);
+
+/* ---------------------------------------------------------------------------
+ * Restricted Additive Schwarz (Section 3, eq. (4)): subdomain s owns the rows
+ * with owner[i] == s; it is extended by `overlap` rings of graph neighbours in
+ * A; A_s = A[ext_s, ext_s] is factored by ILU(0); the block-diagonal
+ * diag(L_1..L_s) and diag(U_1..U_s) are solved as one system, with one
+ * persistent launch per triangle.  Apply: restrict r to every extended
+ * subdomain, solve, and write only owned rows back (restricted prolongation).
+ * r, z: device FP64 [n][nrhs]; must not alias.
+ * ------------------------------------------------------------------------- */
+hec_status_t ras_setup(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val,
+                       int32_t nsub, const int32_t *owner, int32_t overlap, hec_dtype_t factor_dt,
+                       const hec_tune_t *tune, ras_t *out);
+hec_status_t ras_apply(ras_t ras, const double *r, double *z, int32_t nrhs, hipStream_t stream);
+/* Extended-subdomain sizes (ext[nsub], may be NULL) and total extended rows. */
+hec_status_t ras_info(ras_t ras, int32_t *nsub, int64_t *total_ext, int32_t *ext_sizes);
+/* Borrowed plan handles of the block-diagonal L and U. */
+hec_status_t ras_plans(ras_t ras, tri_plan_t *L, tri_plan_t *U);
+void ras_destroy(ras_t ras);
+
+/* ---------------------------------------------------------------------------
+ * Batched independent systems (eq. (4)): the block-diagonal matrix
+ * diag(A_1..A_s) given as one CSR of n = sum n_i rows whose rows
+ * sys_ptr[i]..sys_ptr[i+1]-1 form system i (no coupling across systems),
+ * factored block by block (ILU kind as ilu_setup) and solved in one persistent
+ * launch per triangle with one scheduling group per system.  The returned
+ * handle is an ilu_t: ilu_apply, ilu_plans, ilu_factor and krylov_solve apply.
+ * ------------------------------------------------------------------------- */
+hec_status_t batch_setup(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val,
+                         int32_t nsys, const int32_t *sys_ptr, hec_ilu_kind_t kind, int32_t k,
+                         double tol, int32_t p, hec_dtype_t factor_dt, const hec_tune_t *tune,
+                         ilu_t *out);
+
+/* ---------------------------------------------------------------------------
+ * Restarted Krylov solvers (Section 4 uses restarted GMRES) for A x = b with
+ * right preconditioning by M; every RHS is an independent system sharing the
+ * operator.  Residual, inner products, norms and updates are FP64 on the
+ * device; with an FP32 preconditioner the outer loop is iterative refinement
+ * (use HEC_FGMRES).  GMRES/FGMRES(m): classical Gram-Schmidt with one
+ * re-orthogonalization, Givens rotations, x updated at the end of each cycle.
+ * BiCGSTAB: van der Vorst's right-preconditioned recurrence.  Convergence is
+ * declared on the true residual ||b - A x|| / ||b|| <= rtol.  b, x: device FP64
+ * [n][nrhs]; x holds x0 on entry.  info: host array of nrhs entries.
+ * Returns HEC_OK if every RHS converged, else NOT_CONVERGED or BREAKDOWN.
+ * ------------------------------------------------------------------------- */
+hec_status_t krylov_solve(hec_matrix_t A, hec_precond_t M, hec_krylov_t method, int32_t m,
+                          const double *b, double *x, int32_t nrhs, double rtol, int32_t maxit,
+                          hec_krylov_info_t *info, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * HIP graph of one preconditioner application (kind HEC_PRECOND_ILU or
+ * HEC_PRECOND_RAS) on fixed vectors r -> z, captured from the same launches
+ * ilu_apply / ras_apply issue, for callers that replay it in a loop.
+ * ------------------------------------------------------------------------- */
+hec_status_t hec_graph_capture(hec_precond_t M, const void *r, void *z, int32_t nrhs,
+                               hec_dtype_t vec_dt, hipStream_t stream, hec_graph_t *out);
+hec_status_t hec_graph_launch(hec_graph_t g, hipStream_t stream);
+void hec_graph_destroy(hec_graph_t g);
+
+/* ---------------------------------------------------------------------------
+ * Autotuner: times candidate schedules, ELL widths, level-merge thresholds
+ * and lane-group widths for the solve L x = b with nrhs right-hand sides on
+ * the current device and writes the fastest tuning to *best (its time per
+ * solve in microseconds to *best_us).  The inputs are those of tri_analyze.
+ * ------------------------------------------------------------------------- */
+hec_status_t tri_autotune(int32_t n, const int32_t *rowptr, const int32_t *col, const void *val,
+                          hec_dtype_t dt, hec_uplo_t uplo, int32_t unit_diag, int32_t nrhs,
+                          hipStream_t stream, hec_tune_t *best, double *best_us);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HEC_H */

@@ -1,0 +1,438 @@
+// Algorithm 1 (Section 2.2) of the paper on the host: level of every unknown
+// (eq. (2)), the level map m (eq. (3)), the reordered L' and its HEC form
+// (Section 2.1), plus the device execution layout and the persistent
+// schedule built on top of the level sets.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "hec_host.h"
+
+namespace hec {
+
+void fail(hec_status_t code, const std::string &msg) { throw Error{code, msg}; }
+
+Tune tune_from(const hec_tune_t *t)
+{
+    Tune u;
+    if (!t) return u;
+    u.ell_width = t->ell_width;
+    u.schedule = t->schedule;
+    u.num_groups = t->num_groups;
+    u.merge_rows = t->merge_rows;
+    u.group_lanes = t->group_lanes;
+    u.long_row = t->long_row;
+    u.part_rows = t->part_rows;
+    u.host_only = t->host_only;
+    u.max_nrhs = t->max_nrhs > 0 ? t->max_nrhs : 1;
+    u.block_threads = t->block_threads > 0 ? t->block_threads : 256;
+    if (u.schedule < HEC_SCHED_AUTO || u.schedule > HEC_SCHED_OWNER_PERSISTENT)
+        fail(HEC_ERR_INVALID_ARG, "tune.schedule out of range");
+    if (u.block_threads % 64 != 0 || u.block_threads > 1024)
+        fail(HEC_ERR_INVALID_ARG, "tune.block_threads must be a multiple of 64 up to 1024");
+    if (u.group_lanes != 0 && (u.group_lanes < 1 || u.group_lanes > 64 ||
+                               (u.group_lanes & (u.group_lanes - 1)) != 0))
+        fail(HEC_ERR_INVALID_ARG, "tune.group_lanes must be a power of two in 1..64");
+    if (u.ell_width < -1 || u.ell_width > 64) fail(HEC_ERR_INVALID_ARG, "tune.ell_width out of range");
+    if (u.num_groups < 0 || u.merge_rows < 0 || u.long_row < 0 || u.part_rows < 0)
+        fail(HEC_ERR_INVALID_ARG, "negative tuning value");
+    return u;
+}
+
+Csr csr_copy(int32_t n, const int32_t *rowptr, const int32_t *col, const void *val, hec_dtype_t dt)
+{
+    if (n < 0) fail(HEC_ERR_INVALID_ARG, "n < 0");
+    if (dt != HEC_F64 && dt != HEC_F32) fail(HEC_ERR_INVALID_ARG, "unknown dtype");
+    Csr a;
+    a.n = n;
+    if (!rowptr) fail(HEC_ERR_INVALID_ARG, "rowptr is NULL");
+    a.rp.assign(rowptr, rowptr + (size_t)n + 1);
+    if (a.rp[0] != 0) fail(HEC_ERR_INVALID_ARG, "rowptr[0] != 0");
+    for (int32_t i = 0; i < n; ++i)
+        if (a.rp[i + 1] < a.rp[i]) fail(HEC_ERR_INVALID_ARG, "rowptr not monotone");
+    int64_t nnz = a.rp[n];
+    if (nnz > 0 && (!col || !val)) fail(HEC_ERR_INVALID_ARG, "col or val is NULL");
+    a.ci.assign(col, col + nnz);
+    a.v.resize(nnz);
+    if (dt == HEC_F64) {
+        const double *d = static_cast<const double *>(val);
+        std::copy(d, d + nnz, a.v.begin());
+    } else {
+        const float *f = static_cast<const float *>(val);
+        for (int64_t p = 0; p < nnz; ++p) a.v[p] = f[p];
+    }
+    check_csr_structure(a);
+    return a;
+}
+
+void check_csr_structure(const Csr &a)
+{
+    for (int32_t i = 0; i < a.n; ++i) {
+        for (int32_t p = a.rp[i]; p < a.rp[i + 1]; ++p) {
+            int32_t j = a.ci[p];
+            if (j < 0 || j >= a.n) fail(HEC_ERR_INVALID_ARG, "column index out of range in row " + std::to_string(i));
+            if (p > a.rp[i] && a.ci[p - 1] >= j)
+                fail(HEC_ERR_UNSORTED, "row " + std::to_string(i) + " is not sorted by strictly ascending column");
+        }
+    }
+}
+
+void validate_triangle(const Csr &a, bool upper, bool unit)
+{
+    for (int32_t i = 0; i < a.n; ++i) {
+        bool diag = false;
+        for (int32_t p = a.rp[i]; p < a.rp[i + 1]; ++p) {
+            int32_t j = a.ci[p];
+            if ((!upper && j > i) || (upper && j < i))
+                fail(HEC_ERR_NOT_TRIANGULAR, "entry (" + std::to_string(i) + ", " + std::to_string(j) +
+                                                 ") is on the wrong side of the diagonal");
+            if (j == i) {
+                diag = true;
+                if (!unit && (a.v[p] == 0.0 || !std::isfinite(a.v[p])))
+                    fail(HEC_ERR_ZERO_PIVOT, "zero or non-finite diagonal in row " + std::to_string(i));
+            }
+        }
+        if (!unit && !diag) fail(HEC_ERR_MISSING_DIAG, "row " + std::to_string(i) + " has no diagonal");
+    }
+}
+
+// eq. (2): l(i) = 1 + max l(j) over the stored off-diagonal entries of row i,
+// evaluated in the order of the problem being solved (ascending i for a lower
+// triangle, descending i for an upper triangle, i.e. ascending t(i) = n-1-i).
+// Then eq. (3): a stable counting sort of the problem's rows by level.
+Levels compute_levels(const Csr &a, bool upper)
+{
+    const int32_t n = a.n;
+    Levels lv;
+    lv.level.assign(n, 0);
+    int32_t nlev = 0;
+    for (int32_t q = 0; q < n; ++q) {
+        int32_t i = upper ? n - 1 - q : q;
+        int32_t m = 0;
+        for (int32_t p = a.rp[i]; p < a.rp[i + 1]; ++p) {
+            int32_t j = a.ci[p];
+            if (j != i) m = std::max(m, lv.level[j]);
+        }
+        lv.level[i] = m + 1;
+        nlev = std::max(nlev, m + 1);
+    }
+    lv.nlev = nlev;
+    lv.levelptr.assign((size_t)nlev + 1, 0);
+    for (int32_t i = 0; i < n; ++i) lv.levelptr[lv.level[i]] += 1;
+    for (int32_t k = 0; k < nlev; ++k) lv.levelptr[k + 1] += lv.levelptr[k];
+    std::vector<int32_t> cursor(lv.levelptr.begin(), lv.levelptr.end() - 1);
+    lv.perm.assign(n, 0);
+    lv.iperm.assign(n, 0);
+    for (int32_t q = 0; q < n; ++q) {
+        int32_t i = upper ? n - 1 - q : q;
+        int32_t r = cursor[lv.level[i] - 1]++;
+        lv.perm[r] = i;
+        lv.iperm[i] = r;
+    }
+    return lv;
+}
+
+static int32_t offdiag_count(const Csr &a, int32_t i)
+{
+    int32_t c = a.rp[i + 1] - a.rp[i];
+    // a stored diagonal is not an off-diagonal entry
+    for (int32_t p = a.rp[i]; p < a.rp[i + 1]; ++p)
+        if (a.ci[p] == i) { --c; break; }
+    return c;
+}
+
+// Smallest w with at most half the rows holding more than w off-diagonals.
+int32_t auto_ell_width(const Csr &a, bool /*upper*/)
+{
+    if (a.n == 0) return 0;
+    std::vector<int64_t> hist(65, 0);
+    for (int32_t i = 0; i < a.n; ++i) hist[std::min(offdiag_count(a, i), 64)] += 1;
+    int64_t above = a.n;
+    for (int32_t w = 0; w <= 64; ++w) {
+        above -= hist[w];  // rows with more than w off-diagonals
+        if (2 * above <= a.n) return w;
+    }
+    return 64;
+}
+
+HecHost build_hec(const Csr &a, bool upper, bool unit, const Levels &lv, int32_t w)
+{
+    (void)upper;
+    const int32_t n = a.n;
+    HecHost h;
+    h.n = n;
+    h.w = w;
+    h.ld = (n + 63) / 64 * 64;
+    h.ell_col.assign((size_t)w * h.ld, n);
+    h.ell_val.assign((size_t)w * h.ld, 0.0);
+    h.csr_ptr.assign((size_t)n + 1, 0);
+    h.csr_col.reserve((size_t)n);
+    h.csr_val.reserve((size_t)n);
+    for (int32_t r = 0; r < n; ++r) {
+        int32_t i = lv.perm[r];
+        int32_t e = 0;
+        double d = 1.0;
+        for (int32_t p = a.rp[i]; p < a.rp[i + 1]; ++p) {
+            int32_t j = a.ci[p];
+            if (j == i) {
+                if (!unit) d = a.v[p];
+                continue;
+            }
+            int32_t c = lv.iperm[j];
+            if (e < w) {
+                h.ell_col[(size_t)e * h.ld + r] = c;
+                h.ell_val[(size_t)e * h.ld + r] = a.v[p];
+                ++e;
+            } else {
+                h.csr_col.push_back(c);
+                h.csr_val.push_back(a.v[p]);
+            }
+        }
+        h.csr_col.push_back(r);  // the diagonal closes every CSR row
+        h.csr_val.push_back(d);
+        h.csr_ptr[r + 1] = (int32_t)h.csr_col.size();
+    }
+    return h;
+}
+
+namespace {
+
+// Fill step structures from a device-row order in which every group's rows
+// are contiguous per step.  `runs` lists, per group, the (begin, end) device
+// row ranges of its steps in execution order.
+void finish_schedule(Schedule &s, const ExecHost &ex, const std::vector<std::vector<std::pair<int32_t, int32_t>>> &runs,
+                     const Tune &tune)
+{
+    const int32_t G = (int32_t)runs.size();
+    s.groups = G;
+    s.step_ptr.assign((size_t)G + 1, 0);
+    for (int32_t g = 0; g < G; ++g) s.step_ptr[g + 1] = s.step_ptr[g] + (int32_t)runs[g].size();
+    const int32_t S = s.step_ptr[G];
+    s.step_row.resize(2 * (size_t)S);
+    s.step_lanes.assign(S, 1);
+    std::vector<int32_t> step_of(ex.n, -1);
+    for (int32_t g = 0; g < G; ++g)
+        for (size_t t = 0; t < runs[g].size(); ++t) {
+            int32_t sid = s.step_ptr[g] + (int32_t)t;
+            s.step_row[2 * sid] = runs[g][t].first;
+            s.step_row[2 * sid + 1] = runs[g][t].second;
+            for (int32_t x = runs[g][t].first; x < runs[g][t].second; ++x) step_of[x] = sid;
+        }
+    for (int32_t x = 0; x < ex.n; ++x)
+        if (step_of[x] < 0) fail(HEC_ERR_INVALID_ARG, "internal: row without a step");
+    // lanes per row: steps holding long CSR tails get cooperating lanes
+    const int32_t long_row = tune.long_row > 0 ? tune.long_row : 24;
+    const int32_t lanes = tune.group_lanes > 0 ? tune.group_lanes : 8;
+    if (!ex.tail_ptr.empty()) {
+        for (int32_t sid = 0; sid < S; ++sid) {
+            int32_t mx = 0;
+            for (int32_t x = s.step_row[2 * sid]; x < s.step_row[2 * sid + 1]; ++x)
+                mx = std::max(mx, ex.tail_ptr[x + 1] - ex.tail_ptr[x]);
+            if (mx + ex.w >= long_row) s.step_lanes[sid] = lanes;
+        }
+    }
+    // waits: for every cross-group dependency, the producer group's completed
+    // step count that covers the producing row
+    s.wait_ptr.assign((size_t)S + 1, 0);
+    s.waits.clear();
+    std::vector<int32_t> need(G, 0), touched;
+    touched.reserve(64);
+    auto dep = [&](int32_t g, int32_t sid, int32_t c) {
+        if (c >= ex.n) return;  // ELL padding
+        int32_t ps = step_of[c];
+        int32_t h = ex.owner[c];
+        if (h == g) {
+            if (ps >= sid) fail(HEC_ERR_INVALID_ARG, "internal: dependency not ordered by the schedule");
+            return;
+        }
+        int32_t cnt = ps - s.step_ptr[h] + 1;
+        if (need[h] == 0) touched.push_back(h);
+        need[h] = std::max(need[h], cnt);
+    };
+    for (int32_t g = 0; g < G; ++g) {
+        for (int32_t sid = s.step_ptr[g]; sid < s.step_ptr[g + 1]; ++sid) {
+            for (int32_t x = s.step_row[2 * sid]; x < s.step_row[2 * sid + 1]; ++x) {
+                for (int32_t e = 0; e < ex.w; ++e) dep(g, sid, ex.ell_col[(size_t)e * ex.ld + x]);
+                if (!ex.tail_ptr.empty())
+                    for (int32_t p = ex.tail_ptr[x]; p < ex.tail_ptr[x + 1]; ++p) dep(g, sid, ex.tail_col[p]);
+            }
+            std::sort(touched.begin(), touched.end());
+            for (int32_t h : touched) {
+                s.waits.push_back(h);
+                s.waits.push_back(need[h]);
+                need[h] = 0;
+            }
+            touched.clear();
+            s.wait_ptr[sid + 1] = (int32_t)(s.waits.size() / 2);
+        }
+    }
+    // LDS windows: a group's contiguous device-row span (owner schedule only)
+    s.window.assign(2 * (size_t)G, 0);
+    s.max_window = 0;
+    if (s.kind == HEC_SCHED_OWNER_PERSISTENT) {
+        for (int32_t g = 0; g < G; ++g) {
+            if (runs[g].empty()) continue;
+            int32_t lo = runs[g].front().first, hi = runs[g].back().second;
+            s.window[2 * g] = lo;
+            s.window[2 * g + 1] = hi;
+            s.max_window = std::max(s.max_window, hi - lo);
+        }
+    }
+}
+
+}  // namespace
+
+void build_exec(TriHost &t, const Csr &a, const Tune &tune, const DeviceShape &dev,
+                const std::vector<int32_t> *sys_ptr)
+{
+    (void)a;
+    (void)sys_ptr;
+    const int32_t n = t.n;
+    const Levels &lv = t.lev;
+    const HecHost &h = t.hec;
+    ExecHost &ex = t.ex;
+    ex = ExecHost();
+    ex.n = n;
+    ex.w = h.w;
+    ex.ld = h.ld;
+    int32_t kind = tune.schedule;
+    if (kind == HEC_SCHED_AUTO) kind = HEC_SCHED_LEVEL_PERSISTENT;
+    const int32_t groups_cap = dev.groups_cap;
+    const int32_t cap = groups_cap > 0 ? groups_cap : 256;
+    const int32_t cus = dev.cus > 0 ? dev.cus : 256;
+    // level schedule: as many groups as fit; owner schedule: one part per CU
+    int32_t G = tune.num_groups > 0 ? tune.num_groups
+                                    : (kind == HEC_SCHED_OWNER_PERSISTENT ? std::min(cap, cus) : cap);
+    if (tune.num_groups > 0 && groups_cap > 0 && tune.num_groups > groups_cap)
+        fail(HEC_ERR_CAPACITY, "num_groups " + std::to_string(tune.num_groups) +
+                                   " exceeds the co-resident capacity " + std::to_string(groups_cap));
+    G = std::max(1, G);
+    const int32_t R = std::max(1, tune.max_nrhs);
+    const int32_t merge = tune.merge_rows > 0 ? tune.merge_rows : std::max(1, tune.block_threads / R);
+
+    // 1. device-row order and owner of each row
+    ex.xord.resize(n);
+    ex.owner.assign(n, 0);
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> runs;
+    if (kind == HEC_SCHED_LEVEL_LAUNCH || kind == HEC_SCHED_LEVEL_PERSISTENT) {
+        std::iota(ex.xord.begin(), ex.xord.end(), 0);
+        ex.levelptr = lv.levelptr;
+        if (kind == HEC_SCHED_LEVEL_PERSISTENT) {
+            runs.assign(G, {});
+            for (int32_t k = 0; k < lv.nlev; ++k) {
+                int32_t b = lv.levelptr[k], e = lv.levelptr[k + 1], nk = e - b;
+                int32_t nch = std::max(1, std::min(G, nk / merge));
+                for (int32_t c = 0; c < nch; ++c) {
+                    int32_t cb = b + (int32_t)((int64_t)nk * c / nch);
+                    int32_t ce = b + (int32_t)((int64_t)nk * (c + 1) / nch);
+                    if (ce > cb) {
+                        runs[c].push_back({cb, ce});
+                        for (int32_t x = cb; x < ce; ++x) ex.owner[x] = c;
+                    }
+                }
+            }
+        }
+    } else {
+        // owner schedule: contiguous parts of the problem order (natural order
+        // for L, reversed for U), each solved level by level by one group
+        int32_t parts = G;
+        if (tune.part_rows > 0) parts = std::min(G, std::max(1, (n + tune.part_rows - 1) / tune.part_rows));
+        parts = std::max(1, std::min(parts, std::max(1, n)));
+        runs.assign(parts, {});
+        std::vector<int32_t> part_of_problem(n);
+        int32_t x = 0;
+        for (int32_t g = 0; g < parts; ++g) {
+            int32_t qb = (int32_t)((int64_t)n * g / parts), qe = (int32_t)((int64_t)n * (g + 1) / parts);
+            // rows of the part in level order, ties by problem index
+            std::vector<int32_t> rows;
+            rows.reserve(qe - qb);
+            for (int32_t q = qb; q < qe; ++q) rows.push_back(t.upper ? n - 1 - q : q);
+            std::stable_sort(rows.begin(), rows.end(),
+                             [&](int32_t i, int32_t j) { return lv.level[i] < lv.level[j]; });
+            int32_t start = x;
+            for (size_t u = 0; u < rows.size(); ++u) {
+                ex.xord[x] = lv.iperm[rows[u]];
+                ex.owner[x] = g;
+                if (u > 0 && lv.level[rows[u]] != lv.level[rows[u - 1]]) {
+                    runs[g].push_back({start, x});
+                    start = x;
+                }
+                ++x;
+            }
+            if (x > start) runs[g].push_back({start, x});
+        }
+        (void)part_of_problem;
+        // Consecutive parts depend on each other; give them workgroups that
+        // share an L2 domain (workgroup i runs on domain i % xcds), so that
+        // most part-to-part handoffs stay inside one XCD.
+        const int32_t X = std::max(1, dev.xcds);
+        if (parts % X == 0 && parts >= X) {
+            const int32_t per = parts / X;
+            std::vector<int32_t> gid(parts);
+            for (int32_t p = 0; p < parts; ++p) gid[p] = (p % per) * X + p / per;
+            std::vector<std::vector<std::pair<int32_t, int32_t>>> relabeled(parts);
+            for (int32_t p = 0; p < parts; ++p) relabeled[gid[p]] = std::move(runs[p]);
+            runs.swap(relabeled);
+            for (int32_t x2 = 0; x2 < n; ++x2) ex.owner[x2] = gid[ex.owner[x2]];
+        }
+    }
+    ex.xinv.assign(n, 0);
+    for (int32_t x = 0; x < n; ++x) ex.xinv[ex.xord[x]] = x;
+    ex.orig.resize(n);
+    for (int32_t x = 0; x < n; ++x) ex.orig[x] = lv.perm[ex.xord[x]];
+
+    // 2. HEC in device order; the diagonal goes to its own array
+    const int32_t w = h.w, ld = h.ld;
+    ex.ell_col.assign((size_t)w * ld, n);
+    ex.ell_val.assign((size_t)w * ld, 0.0);
+    bool has_tail = false;
+    for (int32_t r = 0; r < n; ++r)
+        if (h.csr_ptr[r + 1] - h.csr_ptr[r] > 1) { has_tail = true; break; }
+    if (has_tail) ex.tail_ptr.assign((size_t)n + 1, 0);
+    if (!t.unit) ex.dinv.resize(n);
+    for (int32_t x = 0; x < n; ++x) {
+        int32_t r = ex.xord[x];
+        for (int32_t e = 0; e < w; ++e) {
+            int32_t c = h.ell_col[(size_t)e * ld + r];
+            ex.ell_col[(size_t)e * ld + x] = (c == n) ? n : ex.xinv[c];
+            ex.ell_val[(size_t)e * ld + x] = h.ell_val[(size_t)e * ld + r];
+        }
+        int32_t pb = h.csr_ptr[r], pe = h.csr_ptr[r + 1] - 1;  // last entry: diagonal
+        if (has_tail) {
+            for (int32_t p = pb; p < pe; ++p) {
+                ex.tail_col.push_back(ex.xinv[h.csr_col[p]]);
+                ex.tail_val.push_back(h.csr_val[p]);
+            }
+            ex.tail_ptr[x + 1] = (int32_t)ex.tail_col.size();
+        }
+        if (!t.unit) ex.dinv[x] = 1.0 / h.csr_val[pe];
+    }
+    t.nnz_tail = (int64_t)ex.tail_col.size();
+
+    // 3. schedule
+    ex.sched = Schedule();
+    ex.sched.kind = kind;
+    if (kind != HEC_SCHED_LEVEL_LAUNCH) finish_schedule(ex.sched, ex, runs, tune);
+}
+
+TriHost analyze(const Csr &a, bool upper, bool unit, hec_dtype_t dt, const Tune &tune, const DeviceShape &dev,
+                const std::vector<int32_t> *sys_ptr)
+{
+    validate_triangle(a, upper, unit);
+    TriHost t;
+    t.n = a.n;
+    t.upper = upper;
+    t.unit = unit;
+    t.dt = dt;
+    t.lev = compute_levels(a, upper);
+    int32_t w = tune.ell_width >= 0 ? tune.ell_width : auto_ell_width(a, upper);
+    t.hec = build_hec(a, upper, unit, t.lev, w);
+    int64_t off = 0;
+    for (int32_t i = 0; i < a.n; ++i) off += offdiag_count(a, i);
+    t.nnz_off = off;
+    build_exec(t, a, tune, dev, sys_ptr);
+    return t;
+}
+
+}  // namespace hec

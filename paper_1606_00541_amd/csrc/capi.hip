@@ -1,0 +1,704 @@
+// C ABI of the HEC triangular-solve library (declared in include/hec.h):
+// plan construction (Algorithm 1), device upload, the solves of Algorithm 2,
+// the ILU / RAS / batched preconditioners of Section 3 and graph capture.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <memory>
+#include <new>
+
+#include "hec_dev.h"
+
+namespace hec {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_last_error(const std::string &m) { g_last_error = m; }
+
+void hip_check(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return;
+    (void)hipGetLastError();
+    if (e == hipErrorNoDevice || e == hipErrorInvalidDevice)
+        fail(HEC_ERR_NO_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        fail(HEC_ERR_ALLOC, std::string(what) + ": " + hipGetErrorString(e));
+    fail(HEC_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void DevMem::alloc(size_t b)
+{
+    release();
+    if (b == 0) return;
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, b);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(HEC_ERR_ALLOC, "hipMalloc of " + std::to_string(b) + " bytes failed");
+    }
+    p = q;
+    bytes = b;
+}
+
+void upload_values(DevMem &m, const std::vector<double> &v, hec_dtype_t dt)
+{
+    if (dt == HEC_F64) {
+        upload(m, v);
+    } else {
+        std::vector<float> f(v.begin(), v.end());
+        upload(m, f);
+    }
+}
+
+DevTri::~DevTri()
+{
+    if (err_host) (void)hipHostFree(err_host);
+}
+
+static size_t vsize(hec_dtype_t dt) { return dt == HEC_F64 ? 8 : 4; }
+
+void ensure_workspace(DevTri &d, int32_t R)
+{
+    if (R <= d.ws_R) return;
+    d.xw.alloc(((size_t)d.n + 1) * R * vsize(d.dt));
+    d.ws_R = R;
+}
+
+void upload_tri(DevTri &d, const TriHost &t, int32_t max_nrhs)
+{
+    hip_check(hipGetDevice(&d.device), "hipGetDevice");
+    const ExecHost &ex = t.ex;
+    d.n = t.n;
+    d.w = ex.w;
+    d.ld = ex.ld;
+    d.nlev = t.lev.nlev;
+    d.dt = t.dt;
+    d.kind = ex.sched.kind;
+    d.unit = t.unit;
+    d.has_tail = !ex.tail_ptr.empty();
+    upload(d.ell_col, ex.ell_col);
+    upload_values(d.ell_val, ex.ell_val, t.dt);
+    if (d.has_tail) {
+        upload(d.tail_ptr, ex.tail_ptr);
+        upload(d.tail_col, ex.tail_col);
+        upload_values(d.tail_val, ex.tail_val, t.dt);
+    }
+    if (!t.unit) upload_values(d.dinv, ex.dinv, t.dt);
+    upload(d.orig, ex.orig);
+    d.levelptr = ex.levelptr;
+    if (d.kind != HEC_SCHED_LEVEL_LAUNCH) {
+        const Schedule &s = ex.sched;
+        d.groups = s.groups;
+        d.max_window = s.max_window;
+        upload(d.step_ptr, s.step_ptr);
+        upload(d.step_row, s.step_row);
+        upload(d.step_lanes, s.step_lanes);
+        upload(d.wait_ptr, s.wait_ptr);
+        std::vector<int32_t> w = s.waits;
+        if (w.empty()) w.assign(2, 0);
+        upload(d.waits, w);
+        upload(d.window, s.window);
+        d.progress.alloc(sizeof(unsigned long long) * std::max(1, d.groups));
+        hip_check(hipMemset(d.progress.p, 0, d.progress.bytes), "hipMemset");
+        d.epoch.alloc(2 * sizeof(unsigned int));
+        hip_check(hipMemset(d.epoch.p, 0, d.epoch.bytes), "hipMemset");
+    }
+    d.err.alloc(sizeof(int));
+    hip_check(hipMemset(d.err.p, 0, sizeof(int)), "hipMemset");
+    void *hp = nullptr;
+    hip_check(hipHostMalloc(&hp, sizeof(int), hipHostMallocMapped), "hipHostMalloc");
+    *static_cast<volatile int *>(hp) = 0;
+    void *dp = nullptr;
+    hip_check(hipHostGetDevicePointer(&dp, hp, 0), "hipHostGetDevicePointer");
+    d.err_host = static_cast<int *>(dp);
+    ensure_workspace(d, std::max(1, max_nrhs));
+    hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+}
+
+void check_device_error(const DevTri &d)
+{
+    if (!d.err_host) return;
+    volatile int *f = d.err_host;
+    if (*f != 0) {
+        *f = 0;
+        (void)hipMemset(d.err.p, 0, sizeof(int));
+        fail(HEC_ERR_TIMEOUT, "a persistent solve aborted a device-side wait (spin limit reached)");
+    }
+}
+
+}  // namespace hec
+
+using namespace hec;
+
+struct tri_plan_s {
+    TriHost h;
+    DevTri d;
+    bool on_device = false;
+    bool upper = false;
+};
+
+struct ilu_s {
+    int32_t n = 0;
+    hec_dtype_t fdt = HEC_F64;
+    Csr Lf, Uf;                  // host FP64 factors
+    tri_plan_s L, U;
+    DevMem qmap;                 // U device row -> L device row of the same original row
+    std::vector<int32_t> sys_ptr;
+};
+
+struct ras_s {
+    int32_t n = 0, nsub = 0;
+    RasLayout lay;
+    ilu_s f;                     // factors of the block-diagonal matrix
+    DevMem gather_L;             // L device row -> global row of r
+    DevMem scatter_U;            // U device row -> global row of z, or -1 when not owned
+};
+
+struct hec_graph_s {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~hec_graph_s()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+namespace {
+
+DeviceShape device_shape(const Tune &tu, hec_dtype_t dt)
+{
+    DeviceShape s;
+    if (tu.host_only) return s;
+    s.groups_cap = persistent_capacity(dt, tu.block_threads, 0);
+    s.cus = device_cus();
+    s.xcds = 8;
+    return s;
+}
+
+void build_plan(tri_plan_s &p, const Csr &a, bool upper, bool unit, hec_dtype_t dt, const Tune &tu)
+{
+    p.upper = upper;
+    p.h = analyze(a, upper, unit, dt, tu, device_shape(tu, dt));
+    p.d.block = tu.block_threads;
+    if (!tu.host_only) {
+        upload_tri(p.d, p.h, tu.max_nrhs);
+        p.on_device = true;
+    }
+}
+
+void require_device(const tri_plan_s &p)
+{
+    if (!p.on_device) fail(HEC_ERR_NO_DEVICE, "plan was built host-only");
+    int dev = -1;
+    hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (dev != p.d.device) fail(HEC_ERR_INVALID_ARG, "current device differs from the plan's device");
+}
+
+void check_vec(hec_dtype_t dt)
+{
+    if (dt != HEC_F64 && dt != HEC_F32) fail(HEC_ERR_INVALID_ARG, "vector dtype must be HEC_F64 or HEC_F32");
+}
+
+void solve_one(tri_plan_s *p, const void *b, void *x, int32_t nrhs, hec_dtype_t vdt, hipStream_t st, bool upper)
+{
+    if (!p) fail(HEC_ERR_INVALID_ARG, "plan is NULL");
+    if (p->upper != upper) fail(HEC_ERR_INVALID_ARG, upper ? "plan is lower triangular" : "plan is upper triangular");
+    if (nrhs < 1) fail(HEC_ERR_INVALID_ARG, "nrhs must be >= 1");
+    check_vec(vdt);
+    require_device(*p);
+    if (p->h.n > 0 && (!b || !x)) fail(HEC_ERR_INVALID_ARG, "vector pointer is NULL");
+    check_device_error(p->d);
+    ensure_workspace(p->d, nrhs);
+    const int32_t *orig = p->d.orig.as<int32_t>();
+    launch_tri(p->d, b, vdt, orig, p->d.xw.p, x, vdt, orig, nrhs, st);
+}
+
+void export_hec(const HecHost &h, int32_t *width, int32_t *ld, int64_t *tail_nnz, int32_t *ell_col,
+                double *ell_val, int32_t *csr_ptr, int32_t *csr_col, double *csr_val)
+{
+    if (width) *width = h.w;
+    if (ld) *ld = h.ld;
+    if (tail_nnz) *tail_nnz = (int64_t)h.csr_col.size();
+    if (ell_col) std::copy(h.ell_col.begin(), h.ell_col.end(), ell_col);
+    if (ell_val) std::copy(h.ell_val.begin(), h.ell_val.end(), ell_val);
+    if (csr_ptr) std::copy(h.csr_ptr.begin(), h.csr_ptr.end(), csr_ptr);
+    if (csr_col) std::copy(h.csr_col.begin(), h.csr_col.end(), csr_col);
+    if (csr_val) std::copy(h.csr_val.begin(), h.csr_val.end(), csr_val);
+}
+
+void factor(const Csr &a, hec_ilu_kind_t kind, int32_t k, double tol, int32_t p, Csr &L, Csr &U)
+{
+    switch (kind) {
+    case HEC_ILU0: ilu0(a, L, U); break;
+    case HEC_ILUK: iluk(a, k, L, U); break;
+    case HEC_ILUT: ilut(a, p, tol, L, U); break;
+    default: fail(HEC_ERR_INVALID_ARG, "unknown ILU kind");
+    }
+}
+
+// Plans of L (unit lower) and U, and the map joining them: U's solve reads L's
+// device-order output through qmap (eq. (1): y never returns to natural order).
+void build_ilu(ilu_s &f, const Csr &L, const Csr &U, hec_dtype_t fdt, const Tune &tu)
+{
+    f.n = L.n;
+    f.fdt = fdt;
+    build_plan(f.L, L, false, true, fdt, tu);
+    build_plan(f.U, U, true, false, fdt, tu);
+    if (!tu.host_only) {
+        const int32_t n = L.n;
+        std::vector<int32_t> q(n);
+        for (int32_t x = 0; x < n; ++x) {
+            const int32_t i = f.U.h.ex.orig[x];
+            q[x] = f.L.h.ex.xinv[f.L.h.lev.iperm[i]];
+        }
+        upload(f.qmap, q);
+    }
+}
+
+void ilu_apply_impl(ilu_s *f, const void *r, void *z, int32_t nrhs, hec_dtype_t vdt, hipStream_t st)
+{
+    if (!f) fail(HEC_ERR_INVALID_ARG, "ilu is NULL");
+    if (nrhs < 1) fail(HEC_ERR_INVALID_ARG, "nrhs must be >= 1");
+    check_vec(vdt);
+    require_device(f->L);
+    if (f->n > 0 && (!r || !z)) fail(HEC_ERR_INVALID_ARG, "vector pointer is NULL");
+    check_device_error(f->L.d);
+    check_device_error(f->U.d);
+    ensure_workspace(f->L.d, nrhs);
+    ensure_workspace(f->U.d, nrhs);
+    launch_tri(f->L.d, r, vdt, f->L.d.orig.as<int32_t>(), f->L.d.xw.p, nullptr, vdt, nullptr, nrhs, st);
+    launch_tri(f->U.d, f->L.d.xw.p, f->fdt, f->qmap.as<int32_t>(), f->U.d.xw.p, z, vdt,
+               f->U.d.orig.as<int32_t>(), nrhs, st);
+}
+
+void ras_apply_impl(ras_s *s, const double *r, double *z, int32_t nrhs, hipStream_t st)
+{
+    if (!s) fail(HEC_ERR_INVALID_ARG, "ras is NULL");
+    if (nrhs < 1) fail(HEC_ERR_INVALID_ARG, "nrhs must be >= 1");
+    require_device(s->f.L);
+    if (s->n > 0 && (!r || !z)) fail(HEC_ERR_INVALID_ARG, "vector pointer is NULL");
+    if (r == z) fail(HEC_ERR_INVALID_ARG, "ras_apply needs distinct r and z");
+    ilu_s &f = s->f;
+    check_device_error(f.L.d);
+    check_device_error(f.U.d);
+    ensure_workspace(f.L.d, nrhs);
+    ensure_workspace(f.U.d, nrhs);
+    // restriction fused into L's gather, restricted prolongation into U's scatter
+    launch_tri(f.L.d, r, HEC_F64, s->gather_L.as<int32_t>(), f.L.d.xw.p, nullptr, HEC_F64, nullptr, nrhs, st);
+    launch_tri(f.U.d, f.L.d.xw.p, f.fdt, f.qmap.as<int32_t>(), f.U.d.xw.p, z, HEC_F64,
+               s->scatter_U.as<int32_t>(), nrhs, st);
+}
+
+}  // namespace
+
+namespace hec {
+
+void precond_check(const hec_precond_t &M, int32_t n)
+{
+    if (M.kind == HEC_PRECOND_NONE) return;
+    if (!M.handle) fail(HEC_ERR_INVALID_ARG, "preconditioner handle is NULL");
+    if (M.kind == HEC_PRECOND_ILU) {
+        ilu_s *f = static_cast<ilu_s *>(M.handle);
+        if (f->n != n) fail(HEC_ERR_INVALID_ARG, "preconditioner size differs from the matrix");
+        require_device(f->L);
+    } else if (M.kind == HEC_PRECOND_RAS) {
+        ras_s *s = static_cast<ras_s *>(M.handle);
+        if (s->n != n) fail(HEC_ERR_INVALID_ARG, "preconditioner size differs from the matrix");
+        require_device(s->f.L);
+    } else {
+        fail(HEC_ERR_INVALID_ARG, "unknown preconditioner kind");
+    }
+}
+
+void precond_apply(const hec_precond_t &M, const double *r, double *z, int32_t R, hipStream_t st)
+{
+    if (M.kind == HEC_PRECOND_ILU)
+        ilu_apply_impl(static_cast<ilu_s *>(M.handle), r, z, R, HEC_F64, st);
+    else
+        ras_apply_impl(static_cast<ras_s *>(M.handle), r, z, R, st);
+}
+
+}  // namespace hec
+
+extern "C" {
+
+const char *hec_last_error(void) { return hec::g_last_error.c_str(); }
+
+hec_status_t hec_tune_default(hec_tune_t *t)
+{
+    return guard([&] {
+        if (!t) fail(HEC_ERR_INVALID_ARG, "tune is NULL");
+        std::memset(t, 0, sizeof(*t));
+        t->ell_width = -1;
+        t->schedule = HEC_SCHED_AUTO;
+        t->max_nrhs = 1;
+        t->block_threads = 256;
+    });
+}
+
+hec_status_t tri_analyze(int32_t n, const int32_t *rowptr, const int32_t *col, const void *val, hec_dtype_t dt,
+                         hec_uplo_t uplo, int32_t unit_diag, const hec_tune_t *tune, tri_plan_t *out)
+{
+    return guard([&] {
+        if (!out) fail(HEC_ERR_INVALID_ARG, "out is NULL");
+        if (uplo != HEC_LOWER && uplo != HEC_UPPER) fail(HEC_ERR_INVALID_ARG, "bad uplo");
+        Tune tu = tune_from(tune);
+        Csr a = csr_copy(n, rowptr, col, val, dt);
+        auto p = std::make_unique<tri_plan_s>();
+        build_plan(*p, a, uplo == HEC_UPPER, unit_diag != 0, dt, tu);
+        *out = p.release();
+    });
+}
+
+hec_status_t tri_plan_info(tri_plan_t p, int32_t *n, int32_t *nlev, int32_t *levelptr, int32_t *perm)
+{
+    return guard([&] {
+        if (!p) fail(HEC_ERR_INVALID_ARG, "plan is NULL");
+        const Levels &lv = p->h.lev;
+        if (n) *n = p->h.n;
+        if (nlev) *nlev = lv.nlev;
+        if (levelptr) std::copy(lv.levelptr.begin(), lv.levelptr.end(), levelptr);
+        if (perm) std::copy(lv.perm.begin(), lv.perm.end(), perm);
+    });
+}
+
+hec_status_t tri_plan_hec(tri_plan_t p, int32_t *width, int32_t *ld, int64_t *tail_nnz, int32_t *ell_col,
+                          double *ell_val, int32_t *csr_ptr, int32_t *csr_col, double *csr_val)
+{
+    return guard([&] {
+        if (!p) fail(HEC_ERR_INVALID_ARG, "plan is NULL");
+        export_hec(p->h.hec, width, ld, tail_nnz, ell_col, ell_val, csr_ptr, csr_col, csr_val);
+    });
+}
+
+hec_status_t tri_plan_stats(tri_plan_t p, tri_stats_t *s)
+{
+    return guard([&] {
+        if (!p || !s) fail(HEC_ERR_INVALID_ARG, "NULL argument");
+        const TriHost &h = p->h;
+        std::memset(s, 0, sizeof(*s));
+        s->n = h.n;
+        s->nlev = h.lev.nlev;
+        s->ell_width = h.ex.w;
+        s->ld = h.ex.ld;
+        s->schedule = h.ex.sched.kind;
+        s->num_groups = h.ex.sched.groups;
+        s->nsteps = h.ex.sched.nsteps();
+        s->nwaits = (int32_t)h.ex.sched.nwaits();
+        s->nnz_offdiag = h.nnz_off;
+        s->nnz_tail = h.nnz_tail;
+        s->lds_bytes = (int64_t)h.ex.sched.max_window * (h.dt == HEC_F64 ? 8 : 4);
+        s->unit_diag = h.unit ? 1 : 0;
+        s->dtype = h.dt;
+    });
+}
+
+hec_status_t tri_plan_layout(tri_plan_t p, int32_t *xperm, int32_t *owner)
+{
+    return guard([&] {
+        if (!p) fail(HEC_ERR_INVALID_ARG, "plan is NULL");
+        if (xperm) std::copy(p->h.ex.orig.begin(), p->h.ex.orig.end(), xperm);
+        if (owner) std::copy(p->h.ex.owner.begin(), p->h.ex.owner.end(), owner);
+    });
+}
+
+hec_status_t tri_solve_lower(tri_plan_t L, const void *b, void *x, int32_t nrhs, hec_dtype_t vdt, hipStream_t st)
+{
+    return guard([&] { solve_one(L, b, x, nrhs, vdt, st, false); });
+}
+
+hec_status_t tri_solve_upper(tri_plan_t U, const void *b, void *x, int32_t nrhs, hec_dtype_t vdt, hipStream_t st)
+{
+    return guard([&] { solve_one(U, b, x, nrhs, vdt, st, true); });
+}
+
+void tri_plan_destroy(tri_plan_t p) { delete p; }
+
+hec_status_t ilu_setup(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val,
+                       hec_ilu_kind_t kind, int32_t k, double tol, int32_t p, hec_dtype_t fdt,
+                       const hec_tune_t *tune, ilu_t *out)
+{
+    return guard([&] {
+        if (!out) fail(HEC_ERR_INVALID_ARG, "out is NULL");
+        if (fdt != HEC_F64 && fdt != HEC_F32) fail(HEC_ERR_INVALID_ARG, "bad factor dtype");
+        Tune tu = tune_from(tune);
+        Csr a = csr_copy(n, rowptr, col, val, HEC_F64);
+        auto f = std::make_unique<ilu_s>();
+        factor(a, kind, k, tol, p, f->Lf, f->Uf);
+        build_ilu(*f, f->Lf, f->Uf, fdt, tu);
+        *out = f.release();
+    });
+}
+
+hec_status_t batch_setup(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val, int32_t nsys,
+                         const int32_t *sys_ptr, hec_ilu_kind_t kind, int32_t k, double tol, int32_t p,
+                         hec_dtype_t fdt, const hec_tune_t *tune, ilu_t *out)
+{
+    return guard([&] {
+        if (!out || !sys_ptr || nsys < 1) fail(HEC_ERR_INVALID_ARG, "bad batch arguments");
+        if (fdt != HEC_F64 && fdt != HEC_F32) fail(HEC_ERR_INVALID_ARG, "bad factor dtype");
+        if (sys_ptr[0] != 0 || sys_ptr[nsys] != n) fail(HEC_ERR_INVALID_ARG, "sys_ptr must run from 0 to n");
+        for (int32_t s = 0; s < nsys; ++s)
+            if (sys_ptr[s + 1] < sys_ptr[s]) fail(HEC_ERR_INVALID_ARG, "sys_ptr not monotone");
+        Tune tu = tune_from(tune);
+        if (tu.schedule == HEC_SCHED_AUTO) tu.schedule = HEC_SCHED_OWNER_PERSISTENT;
+        Csr a = csr_copy(n, rowptr, col, val, HEC_F64);
+        // eq. (4): the systems must not couple
+        for (int32_t s = 0; s < nsys; ++s)
+            for (int32_t i = sys_ptr[s]; i < sys_ptr[s + 1]; ++i)
+                for (int32_t q = a.rp[i]; q < a.rp[i + 1]; ++q)
+                    if (a.ci[q] < sys_ptr[s] || a.ci[q] >= sys_ptr[s + 1])
+                        fail(HEC_ERR_INVALID_ARG, "an entry couples two systems (row " + std::to_string(i) + ")");
+        auto f = std::make_unique<ilu_s>();
+        f->sys_ptr.assign(sys_ptr, sys_ptr + nsys + 1);
+        factor(a, kind, k, tol, p, f->Lf, f->Uf);
+        build_ilu(*f, f->Lf, f->Uf, fdt, tu);
+        *out = f.release();
+    });
+}
+
+hec_status_t ilu_factor(ilu_t f, int32_t which, int64_t *nnz, int32_t *rowptr, int32_t *col, double *val)
+{
+    return guard([&] {
+        if (!f || (which != 0 && which != 1)) fail(HEC_ERR_INVALID_ARG, "bad arguments");
+        const Csr &c = which == 0 ? f->Lf : f->Uf;
+        if (nnz) *nnz = c.nnz();
+        if (rowptr) std::copy(c.rp.begin(), c.rp.end(), rowptr);
+        if (col) std::copy(c.ci.begin(), c.ci.end(), col);
+        if (val) std::copy(c.v.begin(), c.v.end(), val);
+    });
+}
+
+hec_status_t ilu_plans(ilu_t f, tri_plan_t *L, tri_plan_t *U)
+{
+    return guard([&] {
+        if (!f) fail(HEC_ERR_INVALID_ARG, "ilu is NULL");
+        if (L) *L = &f->L;
+        if (U) *U = &f->U;
+    });
+}
+
+hec_status_t ilu_apply(ilu_t f, const void *r, void *z, int32_t nrhs, hec_dtype_t vdt, hipStream_t st)
+{
+    return guard([&] { ilu_apply_impl(f, r, z, nrhs, vdt, st); });
+}
+
+void ilu_destroy(ilu_t f) { delete f; }
+
+hec_status_t ras_setup(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val, int32_t nsub,
+                       const int32_t *owner, int32_t overlap, hec_dtype_t fdt, const hec_tune_t *tune, ras_t *out)
+{
+    return guard([&] {
+        if (!out) fail(HEC_ERR_INVALID_ARG, "out is NULL");
+        if (fdt != HEC_F64 && fdt != HEC_F32) fail(HEC_ERR_INVALID_ARG, "bad factor dtype");
+        Tune tu = tune_from(tune);
+        if (tu.schedule == HEC_SCHED_AUTO) tu.schedule = HEC_SCHED_OWNER_PERSISTENT;
+        Csr a = csr_copy(n, rowptr, col, val, HEC_F64);
+        auto s = std::make_unique<ras_s>();
+        s->n = n;
+        s->nsub = nsub;
+        s->lay = ras_layout(a, nsub, owner, overlap);
+        ilu_s &f = s->f;
+        ilu0(s->lay.blockdiag, f.Lf, f.Uf);
+        build_ilu(f, f.Lf, f.Uf, fdt, tu);
+        if (!tu.host_only) {
+            const int32_t m = s->lay.blockdiag.n;
+            std::vector<int32_t> g(m), sc(m);
+            for (int32_t x = 0; x < m; ++x) g[x] = s->lay.ext[f.L.h.ex.orig[x]];
+            for (int32_t x = 0; x < m; ++x) {
+                const int32_t e = f.U.h.ex.orig[x];
+                sc[x] = s->lay.owned[e] ? s->lay.ext[e] : -1;
+            }
+            upload(s->gather_L, g);
+            upload(s->scatter_U, sc);
+        }
+        *out = s.release();
+    });
+}
+
+hec_status_t ras_apply(ras_t s, const double *r, double *z, int32_t nrhs, hipStream_t st)
+{
+    return guard([&] { ras_apply_impl(s, r, z, nrhs, st); });
+}
+
+hec_status_t ras_info(ras_t s, int32_t *nsub, int64_t *total_ext, int32_t *ext_sizes)
+{
+    return guard([&] {
+        if (!s) fail(HEC_ERR_INVALID_ARG, "ras is NULL");
+        if (nsub) *nsub = s->nsub;
+        if (total_ext) *total_ext = (int64_t)s->lay.ext.size();
+        if (ext_sizes)
+            for (int32_t i = 0; i < s->nsub; ++i) ext_sizes[i] = s->lay.ext_ptr[i + 1] - s->lay.ext_ptr[i];
+    });
+}
+
+hec_status_t ras_plans(ras_t s, tri_plan_t *L, tri_plan_t *U)
+{
+    return guard([&] {
+        if (!s) fail(HEC_ERR_INVALID_ARG, "ras is NULL");
+        if (L) *L = &s->f.L;
+        if (U) *U = &s->f.U;
+    });
+}
+
+void ras_destroy(ras_t s) { delete s; }
+
+hec_status_t hec_graph_capture(hec_precond_t M, const void *r, void *z, int32_t nrhs, hec_dtype_t vdt,
+                               hipStream_t st, hec_graph_t *out)
+{
+    return guard([&] {
+        if (!out) fail(HEC_ERR_INVALID_ARG, "out is NULL");
+        if (M.kind != HEC_PRECOND_ILU && M.kind != HEC_PRECOND_RAS) fail(HEC_ERR_INVALID_ARG, "bad preconditioner kind");
+        if (!M.handle) fail(HEC_ERR_INVALID_ARG, "preconditioner handle is NULL");
+        if (nrhs < 1) fail(HEC_ERR_INVALID_ARG, "nrhs must be >= 1");
+        // workspaces must exist before capture (no allocation inside it)
+        if (M.kind == HEC_PRECOND_ILU) {
+            ilu_s *f = static_cast<ilu_s *>(M.handle);
+            require_device(f->L);
+            ensure_workspace(f->L.d, nrhs);
+            ensure_workspace(f->U.d, nrhs);
+        } else {
+            if (vdt != HEC_F64) fail(HEC_ERR_INVALID_ARG, "RAS vectors are FP64");
+            ras_s *s = static_cast<ras_s *>(M.handle);
+            require_device(s->f.L);
+            ensure_workspace(s->f.L.d, nrhs);
+            ensure_workspace(s->f.U.d, nrhs);
+        }
+        hipStream_t cap = st;
+        bool own = false;
+        if (!cap) {
+            hip_check(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "hipStreamCreate");
+            own = true;
+        }
+        auto g = std::make_unique<hec_graph_s>();
+        hip_check(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        try {
+            if (M.kind == HEC_PRECOND_ILU)
+                ilu_apply_impl(static_cast<ilu_s *>(M.handle), r, z, nrhs, vdt, cap);
+            else
+                ras_apply_impl(static_cast<ras_s *>(M.handle), static_cast<const double *>(r),
+                               static_cast<double *>(z), nrhs, cap);
+        } catch (...) {
+            hipGraph_t tmp = nullptr;
+            (void)hipStreamEndCapture(cap, &tmp);
+            if (tmp) (void)hipGraphDestroy(tmp);
+            if (own) (void)hipStreamDestroy(cap);
+            throw;
+        }
+        hipError_t e = hipStreamEndCapture(cap, &g->graph);
+        if (own) (void)hipStreamDestroy(cap);
+        hip_check(e, "hipStreamEndCapture");
+        hip_check(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+        *out = g.release();
+    });
+}
+
+hec_status_t hec_graph_launch(hec_graph_t g, hipStream_t st)
+{
+    return guard([&] {
+        if (!g) fail(HEC_ERR_INVALID_ARG, "graph is NULL");
+        hip_check(hipGraphLaunch(g->exec, st), "hipGraphLaunch");
+    });
+}
+
+void hec_graph_destroy(hec_graph_t g) { delete g; }
+
+hec_status_t tri_autotune(int32_t n, const int32_t *rowptr, const int32_t *col, const void *val, hec_dtype_t dt,
+                          hec_uplo_t uplo, int32_t unit_diag, int32_t nrhs, hipStream_t st, hec_tune_t *best,
+                          double *best_us)
+{
+    return guard([&] {
+        if (!best || nrhs < 1) fail(HEC_ERR_INVALID_ARG, "bad arguments");
+        if (uplo != HEC_LOWER && uplo != HEC_UPPER) fail(HEC_ERR_INVALID_ARG, "bad uplo");
+        Csr a = csr_copy(n, rowptr, col, val, dt);
+        const bool upper = uplo == HEC_UPPER, unit = unit_diag != 0;
+        validate_triangle(a, upper, unit);
+        const int32_t w0 = auto_ell_width(a, upper);
+        // candidate grid: schedule x block size x level-merge threshold x ELL width
+        std::vector<Tune> cands;
+        Tune base;
+        base.max_nrhs = nrhs;
+        for (int32_t blk : {256, 512}) {
+            Tune t = base;
+            t.block_threads = blk;
+            t.schedule = HEC_SCHED_OWNER_PERSISTENT;
+            cands.push_back(t);
+            for (int32_t mul : {1, 2, 4}) {
+                Tune u = base;
+                u.block_threads = blk;
+                u.schedule = HEC_SCHED_LEVEL_PERSISTENT;
+                u.merge_rows = std::max(1, mul * blk / nrhs);
+                cands.push_back(u);
+            }
+        }
+        bool tails = false;
+        for (int32_t i = 0; i < a.n && !tails; ++i) tails = (a.rp[i + 1] - a.rp[i] - (unit ? 0 : 1)) > w0;
+        if (tails) {
+            const size_t m = cands.size();
+            for (size_t q = 0; q < m; ++q) {
+                Tune t = cands[q];
+                t.ell_width = std::min(64, w0 + 2);
+                cands.push_back(t);
+                Tune u = cands[q];
+                u.group_lanes = 4;
+                u.long_row = 8;
+                cands.push_back(u);
+            }
+        }
+        const hec_dtype_t vdt = dt;
+        const size_t bytes = ((size_t)std::max(1, n)) * nrhs * (vdt == HEC_F64 ? 8 : 4);
+        DevMem b, x;
+        b.alloc(bytes);
+        x.alloc(bytes);
+        hip_check(hipMemset(b.p, 0, bytes), "hipMemset");
+        hipEvent_t e0, e1;
+        hip_check(hipEventCreate(&e0), "hipEventCreate");
+        hip_check(hipEventCreate(&e1), "hipEventCreate");
+        double best_t = 1e300;
+        Tune best_tune = cands.front();
+        for (const Tune &t : cands) {
+            tri_plan_s p;
+            try {
+                build_plan(p, a, upper, unit, dt, t);
+                for (int rep = 0; rep < 2; ++rep) solve_one(&p, b.p, x.p, nrhs, vdt, st, upper);
+                hip_check(hipEventRecord(e0, st), "hipEventRecord");
+                const int reps = 5;
+                for (int rep = 0; rep < reps; ++rep) solve_one(&p, b.p, x.p, nrhs, vdt, st, upper);
+                hip_check(hipEventRecord(e1, st), "hipEventRecord");
+                hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+                float ms = 0.f;
+                hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+                const double us = 1000.0 * ms / reps;
+                if (us < best_t) {
+                    best_t = us;
+                    best_tune = t;
+                }
+            } catch (const Error &e) {
+                if (e.code != HEC_ERR_CAPACITY && e.code != HEC_ERR_ALLOC) {
+                    (void)hipEventDestroy(e0);
+                    (void)hipEventDestroy(e1);
+                    throw;
+                }
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        hec_tune_default(best);
+        best->ell_width = best_tune.ell_width;
+        best->schedule = best_tune.schedule;
+        best->num_groups = best_tune.num_groups;
+        best->merge_rows = best_tune.merge_rows;
+        best->group_lanes = best_tune.group_lanes;
+        best->long_row = best_tune.long_row;
+        best->part_rows = best_tune.part_rows;
+        best->max_nrhs = best_tune.max_nrhs;
+        best->block_threads = best_tune.block_threads;
+        if (best_us) *best_us = best_t;
+    });
+}
+
+}  // extern "C"

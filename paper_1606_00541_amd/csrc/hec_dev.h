@@ -1,0 +1,151 @@
+// Device-side structures and launch interfaces of the HEC triangular solves.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <exception>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hec_host.h"
+
+namespace hec {
+
+// Owning device buffer.
+struct DevMem {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevMem() = default;
+    DevMem(const DevMem &) = delete;
+    DevMem &operator=(const DevMem &) = delete;
+    ~DevMem() { release(); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    void alloc(size_t b);
+    template <typename T> T *as() const { return static_cast<T *>(p); }
+};
+
+void hip_check(hipError_t e, const char *what);
+
+// Thread-local last-error text of the C ABI (hec_last_error).
+void set_last_error(const std::string &m);
+
+// Run `f` (which returns a status) and convert exceptions to status codes.
+template <typename F> hec_status_t guard_status(F &&f)
+{
+    try {
+        hec_status_t s = f();
+        if (s == HEC_OK) set_last_error("");
+        return s;
+    } catch (const Error &e) {
+        set_last_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        set_last_error("host allocation failed");
+        return HEC_ERR_ALLOC;
+    } catch (const std::exception &e) {
+        set_last_error(e.what());
+        return HEC_ERR_INVALID_ARG;
+    } catch (...) {
+        set_last_error("unknown error");
+        return HEC_ERR_INVALID_ARG;
+    }
+}
+template <typename F> hec_status_t guard(F &&f)
+{
+    return guard_status([&]() -> hec_status_t {
+        f();
+        return HEC_OK;
+    });
+}
+template <typename T> void upload(DevMem &m, const std::vector<T> &v)
+{
+    m.release();
+    if (v.empty()) return;
+    m.alloc(v.size() * sizeof(T));
+    hip_check(hipMemcpy(m.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy H2D");
+}
+// Upload doubles converted to the plan's value type.
+void upload_values(DevMem &m, const std::vector<double> &v, hec_dtype_t dt);
+
+// Kernel arguments of one triangular solve launch (passed by value).
+struct TriArgs {
+    int32_t n, w, ld, R;
+    const int32_t *ell_col;
+    const void *ell_val;
+    const int32_t *tail_ptr, *tail_col;
+    const void *tail_val;
+    const void *dinv;
+    const int32_t *step_ptr, *step_row, *step_lanes, *wait_ptr, *waits, *window;
+    unsigned long long *progress;
+    unsigned int *epoch;
+    int *err_dev;       // device-side abort flag
+    int *err_host;      // host-mapped copy, read by the host without a sync
+    const void *bin;    // right-hand side, indexed bin[gather[x]*R + k]
+    const int32_t *gather;
+    void *xw;           // device-order solution [n][R] (plan value type)
+    void *xout;         // optional scatter target xout[scatter[x]*R + k]
+    const int32_t *scatter;
+    int32_t row_begin, row_end;  // level-launch row range
+    int32_t use_lds;
+};
+
+// Device copy of one triangular plan.
+struct DevTri {
+    int device = -1;
+    int32_t n = 0, w = 0, ld = 0, nlev = 0;
+    hec_dtype_t dt = HEC_F64;
+    int32_t kind = HEC_SCHED_LEVEL_PERSISTENT;
+    int32_t groups = 0, block = 256, max_window = 0;
+    bool unit = false, has_tail = false;
+    DevMem ell_col, ell_val, tail_ptr, tail_col, tail_val, dinv, orig;
+    DevMem step_ptr, step_row, step_lanes, wait_ptr, waits, window;
+    DevMem progress, epoch, err;
+    int *err_host = nullptr;      // pinned, device-visible
+    std::vector<int32_t> levelptr;  // level-launch bounds (host)
+    DevMem xw;                      // workspace [n][ws_R]
+    int32_t ws_R = 0;
+    ~DevTri();
+};
+
+void upload_tri(DevTri &d, const TriHost &t, int32_t max_nrhs);
+void ensure_workspace(DevTri &d, int32_t R);
+// Largest number of co-resident workgroups of the persistent kernel for the
+// given value type, block size and dynamic LDS bytes on the current device.
+int32_t persistent_capacity(hec_dtype_t dt, int32_t block, size_t lds_bytes);
+int32_t device_max_lds();
+int32_t device_cus();
+// Launch one triangular solve: rows gathered from `bin` (type in_dt) through
+// `gather`, device-order solution written to `xw`, optionally scattered to
+// `xout` (type out_dt) through `scatter`.
+void launch_tri(DevTri &d, const void *bin, hec_dtype_t in_dt, const int32_t *gather, void *xw,
+                void *xout, hec_dtype_t out_dt, const int32_t *scatter, int32_t R, hipStream_t st);
+// Throws HEC_ERR_TIMEOUT if a persistent launch of this plan aborted a wait.
+void check_device_error(const DevTri &d);
+
+// ---- Krylov / SpMV / vector support (krylov.hip) ----
+struct DevHec {   // general HEC matrix for y = A x
+    int device = -1;
+    int32_t n = 0, w = 0, ld = 0;
+    hec_dtype_t dt = HEC_F64;
+    DevMem ell_col, ell_val, tail_ptr, tail_col, tail_val;
+    HecHost host;   // host copy (export)
+    int64_t tail_nnz = 0;
+};
+void spmv(const DevHec &A, const double *x, double *y, int32_t R, hipStream_t st);
+// r = b - A x
+void residual(const DevHec &A, const double *b, const double *x, double *r, int32_t R, hipStream_t st);
+void convert_vec(const void *src, hec_dtype_t sdt, void *dst, hec_dtype_t ddt, size_t count, hipStream_t st);
+// gather dst[t*R+k] = src[idx[t]*R+k] (f64 -> f64/f32) ; scatter for owned rows
+void gather_rows(const double *src, const int32_t *idx, void *dst, hec_dtype_t ddt, int32_t m, int32_t R,
+                 hipStream_t st);
+void scatter_owned(const void *src, hec_dtype_t sdt, const int32_t *idx, const int32_t *owned, double *dst,
+                   int32_t m, int32_t R, hipStream_t st);
+
+}  // namespace hec

@@ -1,0 +1,146 @@
+// Host-side structures of the HEC triangular-solve library: analysis plans,
+// execution layouts and schedules.  Pure C++ (no HIP), shared by the analysis,
+// factorization and C-ABI translation units.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hec.h"
+
+namespace hec {
+
+// Error carrier used inside the library; converted to hec_status_t at the ABI.
+struct Error {
+    hec_status_t code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(hec_status_t code, const std::string &msg);
+
+// A CSR view of a square host matrix with double values.
+struct Csr {
+    int32_t n = 0;
+    std::vector<int32_t> rp, ci;
+    std::vector<double> v;
+    int64_t nnz() const { return rp.empty() ? 0 : rp.back(); }
+};
+
+Csr csr_copy(int32_t n, const int32_t *rowptr, const int32_t *col, const void *val, hec_dtype_t dt);
+void check_csr_structure(const Csr &a);  // rowptr, bounds, strict ascending order
+
+// Level-set analysis of one triangle (Algorithm 1, steps 1-2).
+struct Levels {
+    int32_t nlev = 0;
+    std::vector<int32_t> level;     // per original row, 1-based
+    std::vector<int32_t> levelptr;  // [nlev+1]
+    std::vector<int32_t> perm;      // new (level-order) position -> original row
+    std::vector<int32_t> iperm;     // original row -> new position (the map m)
+};
+
+// Paper-layout HEC of L' (Algorithm 1, steps 3-4): ELL column-major, padding
+// value 0 / column n; CSR remainder holds the rest and the diagonal last.
+struct HecHost {
+    int32_t n = 0, w = 0, ld = 0;
+    std::vector<int32_t> ell_col;
+    std::vector<double> ell_val;
+    std::vector<int32_t> csr_ptr, csr_col;
+    std::vector<double> csr_val;
+};
+
+// A schedule for the persistent executor: every workgroup runs its steps in
+// order; a step is a contiguous range of device rows preceded by waits on other
+// workgroups' progress counters.
+struct Schedule {
+    int32_t kind = HEC_SCHED_LEVEL_PERSISTENT;
+    int32_t groups = 0;
+    std::vector<int32_t> step_ptr;   // [groups+1]
+    std::vector<int32_t> step_row;   // [2*nsteps]: begin, end (device rows)
+    std::vector<int32_t> step_lanes; // [nsteps]: lanes cooperating per row (1 = thread per row)
+    std::vector<int32_t> wait_ptr;   // [nsteps+1]
+    std::vector<int32_t> waits;      // [2*nwaits]: group, required completed steps
+    std::vector<int32_t> window;     // [2*groups]: LDS window (device rows lo, hi)
+    int32_t max_window = 0;          // largest window (rows)
+    int64_t nwaits() const { return (int64_t)waits.size() / 2; }
+    int32_t nsteps() const { return (int32_t)step_lanes.size(); }
+};
+
+// Device-order (execution) layout of one triangle: rows permuted into the
+// schedule's order, ELL/CSR columns renumbered to device rows, the diagonal
+// split into its own dense array (stored as its reciprocal).
+struct ExecHost {
+    int32_t n = 0, w = 0, ld = 0;
+    std::vector<int32_t> xord;   // device row -> level-order row
+    std::vector<int32_t> xinv;   // level-order row -> device row
+    std::vector<int32_t> orig;   // device row -> original row
+    std::vector<int32_t> owner;  // device row -> workgroup
+    std::vector<int32_t> ell_col;
+    std::vector<double> ell_val;
+    std::vector<int32_t> tail_ptr, tail_col;  // empty when no row overflows the ELL part
+    std::vector<double> tail_val;
+    std::vector<double> dinv;                 // empty for a unit diagonal
+    std::vector<int32_t> levelptr;            // level-launch schedule: device-row bounds per level
+    Schedule sched;
+};
+
+struct TriHost {
+    int32_t n = 0;
+    bool upper = false, unit = false;
+    hec_dtype_t dt = HEC_F64;
+    Levels lev;
+    HecHost hec;
+    ExecHost ex;
+    int64_t nnz_off = 0, nnz_tail = 0;
+};
+
+struct Tune {
+    int32_t ell_width = -1;
+    int32_t schedule = HEC_SCHED_AUTO;
+    int32_t num_groups = 0;
+    int32_t merge_rows = 0;
+    int32_t group_lanes = 0;
+    int32_t long_row = 0;
+    int32_t part_rows = 0;
+    int32_t host_only = 0;
+    int32_t max_nrhs = 1;
+    int32_t block_threads = 256;
+};
+Tune tune_from(const hec_tune_t *t);
+
+// Algorithm 1 on one triangle.  `groups_cap` is the largest persistent grid
+// the device can hold (0 = unknown; a default is used).  `sys_ptr` (optional)
+// marks independent diagonal blocks for the owner schedule.
+void validate_triangle(const Csr &a, bool upper, bool unit);
+Levels compute_levels(const Csr &a, bool upper);
+int32_t auto_ell_width(const Csr &a, bool upper);
+HecHost build_hec(const Csr &a, bool upper, bool unit, const Levels &lv, int32_t w);
+// Device facts the schedules are sized by (zeros when unknown / host-only).
+struct DeviceShape {
+    int32_t groups_cap = 0;  // co-resident persistent workgroups
+    int32_t cus = 0;         // compute units
+    int32_t xcds = 8;        // L2 domains; workgroup i runs on domain i % xcds
+};
+void build_exec(TriHost &t, const Csr &a, const Tune &tune, const DeviceShape &dev,
+                const std::vector<int32_t> *sys_ptr);
+TriHost analyze(const Csr &a, bool upper, bool unit, hec_dtype_t dt, const Tune &tune,
+                const DeviceShape &dev, const std::vector<int32_t> *sys_ptr = nullptr);
+
+// Incomplete factorizations (Section 3), each returning L (strict part plus a
+// stored unit diagonal last in each row) and U (diagonal first).
+void ilu0(const Csr &a, Csr &L, Csr &U);
+void iluk(const Csr &a, int32_t k, Csr &L, Csr &U);
+void ilut(const Csr &a, int32_t p, double tau, Csr &L, Csr &U);
+
+// Restricted Additive Schwarz setup: extended subdomains (ascending global
+// rows) and the block-diagonal matrix of the A_s = A[ext_s, ext_s].
+struct RasLayout {
+    int32_t nsub = 0;
+    std::vector<int32_t> ext_ptr;   // [nsub+1] into ext
+    std::vector<int32_t> ext;       // global row of each extended position
+    std::vector<int32_t> owned;     // [ext.size()] 1 if the position is owned by its subdomain
+    Csr blockdiag;                  // n = ext.size(), block s = rows ext_ptr[s]..ext_ptr[s+1]-1
+};
+RasLayout ras_layout(const Csr &a, int32_t nsub, const int32_t *owner, int32_t overlap);
+
+}  // namespace hec

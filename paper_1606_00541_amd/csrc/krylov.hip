@@ -1,0 +1,750 @@
+// Outer Krylov loop of the preconditioned solve (Section 4 uses restarted
+// GMRES): general HEC matrices for the residual b - A x, deterministic
+// multi-RHS inner products, vector updates, restarted (F)GMRES(m) with
+// classical Gram-Schmidt plus one re-orthogonalization, and BiCGSTAB.  All
+// vectors are FP64 [n][R] on the device; only the small per-RHS scalars
+// (Hessenberg columns, inner products) travel to the host.  The autotuner for
+// the triangular plans lives here as well.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <vector>
+
+#include "hec_dev.h"
+
+struct hec_matrix_s {
+    hec::DevHec d;
+};
+struct tri_plan_s;
+struct ilu_s;
+struct ras_s;
+
+namespace hec {
+
+namespace {
+
+constexpr int kMaxPairs = 32;
+constexpr int kMaxTerms = 4;
+
+// ---- kernels -------------------------------------------------------------
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_spmv(int n, int w, int ld, const int32_t *ell_col, const T *ell_val,
+                                                const int32_t *tail_ptr, const int32_t *tail_col,
+                                                const T *tail_val, const double *x, const double *b,
+                                                double *y, int R)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)n * R) return;
+    const int i = (int)(t / R), k = (int)(t - (long)i * R);
+    double s = 0.0;
+    for (int e = 0; e < w; ++e) {
+        const int c = ell_col[(size_t)e * ld + i];
+        if (c < n) s += (double)ell_val[(size_t)e * ld + i] * x[(size_t)c * R + k];
+    }
+    if (tail_ptr)
+        for (int p = tail_ptr[i]; p < tail_ptr[i + 1]; ++p) s += (double)tail_val[p] * x[(size_t)tail_col[p] * R + k];
+    y[t] = b ? b[t] - s : s;
+}
+
+struct DotArgs {
+    const double *a[kMaxPairs];
+    const double *b[kMaxPairs];
+    int np;
+};
+
+// partial[blk][pair][k] = sum over this block's rows of a_pair * b_pair.
+// Threads of a block are arranged as (rows x R): thread t owns rhs t % R.
+__global__ void __launch_bounds__(256) k_dot_partial(DotArgs d, long n, int R, int rows_per_iter, double *partial)
+{
+    __shared__ double red[256];
+    const int tid = threadIdx.x;
+    const int used = rows_per_iter * R;
+    const int k = tid % R, r0 = tid / R;
+    for (int p = 0; p < d.np; ++p) {
+        double acc = 0.0;
+        if (tid < used)
+            for (long row = (long)blockIdx.x * rows_per_iter + r0; row < n; row += (long)gridDim.x * rows_per_iter)
+                acc += d.a[p][row * R + k] * d.b[p][row * R + k];
+        red[tid] = acc;
+        __syncthreads();
+        // fold the rows dimension: threads with the same k
+        for (int span = rows_per_iter; span > 1;) {
+            const int half = (span + 1) / 2;
+            if (tid < used && r0 < span - half) red[tid] += red[tid + half * R];
+            __syncthreads();
+            span = half;
+        }
+        if (tid < R) partial[((size_t)blockIdx.x * d.np + p) * R + tid] = red[tid];
+        __syncthreads();
+    }
+}
+
+__global__ void k_dot_final(const double *partial, int nblk, int np, int R, double *out)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= np * R) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += partial[(size_t)b * np * R + t];
+    out[t] = s;
+}
+
+struct LinArgs {
+    const double *in[kMaxTerms];
+    int nt;
+    const double *coef;  // [nt][R]
+    double *out;
+    double *out2;        // optional second output receiving the same value
+};
+
+// out[:,k] = sum_t coef[t][k] * in_t[:,k]
+__global__ void __launch_bounds__(256) k_lincomb(LinArgs a, long total, int R)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const int k = (int)(t % R);
+    double s = 0.0;
+    for (int q = 0; q < a.nt; ++q) s += a.coef[q * R + k] * a.in[q][t];
+    a.out[t] = s;
+    if (a.out2) a.out2[t] = s;
+}
+
+// w[:,k] -= sum_{i<nv} h[i][k] * V_i[:,k]   (V_i = V + i*stride)
+__global__ void __launch_bounds__(256) k_gs_update(double *w, const double *V, long stride, const double *h, int nv,
+                                                  long total, int R)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const int k = (int)(t % R);
+    double s = w[t];
+    for (int i = 0; i < nv; ++i) s -= h[i * R + k] * V[i * stride + t];
+    w[t] = s;
+}
+
+// x[:,k] += sum_{i<nv} y[i][k] * Z_i[:,k]
+__global__ void __launch_bounds__(256) k_basis_update(double *x, const double *Z, long stride, const double *y, int nv,
+                                                     long total, int R)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const int k = (int)(t % R);
+    double s = 0.0;
+    for (int i = 0; i < nv; ++i) s += y[i * R + k] * Z[i * stride + t];
+    x[t] += s;
+}
+
+template <typename TS, typename TD>
+__global__ void __launch_bounds__(256) k_convert(const TS *s, TD *d, long count)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < count) d[t] = (TD)s[t];
+}
+
+inline int blocks_for(long total) { return (int)std::max<long>(1, (total + 255) / 256); }
+
+}  // namespace
+
+// ---- public support functions -------------------------------------------
+
+void spmv(const DevHec &A, const double *x, double *y, int32_t R, hipStream_t st)
+{
+    residual(A, nullptr, x, y, R, st);
+}
+
+void residual(const DevHec &A, const double *b, const double *x, double *r, int32_t R, hipStream_t st)
+{
+    const long total = (long)A.n * R;
+    if (total == 0) return;
+    const int32_t *tp = A.tail_nnz > 0 ? A.tail_ptr.as<int32_t>() : nullptr;
+    if (A.dt == HEC_F64)
+        hipLaunchKernelGGL(k_spmv<double>, dim3(blocks_for(total)), dim3(256), 0, st, A.n, A.w, A.ld,
+                           A.ell_col.as<int32_t>(), A.ell_val.as<double>(), tp, A.tail_col.as<int32_t>(),
+                           A.tail_val.as<double>(), x, b, r, R);
+    else
+        hipLaunchKernelGGL(k_spmv<float>, dim3(blocks_for(total)), dim3(256), 0, st, A.n, A.w, A.ld,
+                           A.ell_col.as<int32_t>(), A.ell_val.as<float>(), tp, A.tail_col.as<int32_t>(),
+                           A.tail_val.as<float>(), x, b, r, R);
+    hip_check(hipGetLastError(), "k_spmv launch");
+}
+
+void convert_vec(const void *src, hec_dtype_t sdt, void *dst, hec_dtype_t ddt, size_t count, hipStream_t st)
+{
+    if (count == 0) return;
+    const int g = blocks_for((long)count);
+    if (sdt == HEC_F64 && ddt == HEC_F32)
+        hipLaunchKernelGGL((k_convert<double, float>), dim3(g), dim3(256), 0, st, (const double *)src, (float *)dst,
+                           (long)count);
+    else if (sdt == HEC_F32 && ddt == HEC_F64)
+        hipLaunchKernelGGL((k_convert<float, double>), dim3(g), dim3(256), 0, st, (const float *)src, (double *)dst,
+                           (long)count);
+    else
+        hip_check(hipMemcpyAsync(dst, src, count * (sdt == HEC_F64 ? 8 : 4), hipMemcpyDeviceToDevice, st),
+                  "hipMemcpyAsync");
+    hip_check(hipGetLastError(), "k_convert launch");
+}
+
+namespace {
+
+// Scratch and helpers of one Krylov solve.
+struct Ctx {
+    hipStream_t st;
+    long n;
+    int R;
+    DevMem partial, dots, coef;
+    double *hbuf = nullptr;  // pinned host scalars
+    int nblk, rows_per_iter;
+    Ctx(long n_, int R_, hipStream_t s) : st(s), n(n_), R(R_)
+    {
+        rows_per_iter = std::max(1, 256 / R);
+        nblk = (int)std::min<long>(1024, std::max<long>(1, (n + rows_per_iter - 1) / rows_per_iter));
+        partial.alloc(sizeof(double) * (size_t)nblk * kMaxPairs * R);
+        dots.alloc(sizeof(double) * kMaxPairs * R);
+        coef.alloc(sizeof(double) * (size_t)std::max(kMaxPairs, kMaxTerms) * R);
+        hip_check(hipHostMalloc((void **)&hbuf, sizeof(double) * (size_t)std::max(kMaxPairs, kMaxTerms) * R, 0),
+                  "hipHostMalloc");
+    }
+    ~Ctx()
+    {
+        if (hbuf) (void)hipHostFree(hbuf);
+    }
+    // inner products of np pairs, per RHS, returned in hbuf[p*R + k]
+    void dots_to_host(const double *const *a, const double *const *b, int np)
+    {
+        DotArgs d{};
+        for (int p = 0; p < np; ++p) {
+            d.a[p] = a[p];
+            d.b[p] = b[p];
+        }
+        d.np = np;
+        hipLaunchKernelGGL(k_dot_partial, dim3(nblk), dim3(256), 0, st, d, n, R, rows_per_iter,
+                           partial.as<double>());
+        hipLaunchKernelGGL(k_dot_final, dim3((np * R + 255) / 256), dim3(256), 0, st, partial.as<double>(), nblk, np,
+                           R, dots.as<double>());
+        hip_check(hipGetLastError(), "dot launch");
+        hip_check(hipMemcpyAsync(hbuf, dots.p, sizeof(double) * np * R, hipMemcpyDeviceToHost, st), "D2H");
+        hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    }
+    // out = sum_t c[t][k] in_t   (coefficients given on the host)
+    void lincomb(double *out, const std::vector<const double *> &in, const std::vector<double> &c,
+                 double *out2 = nullptr)
+    {
+        LinArgs a{};
+        a.nt = (int)in.size();
+        for (int t = 0; t < a.nt; ++t) a.in[t] = in[t];
+        a.out = out;
+        a.out2 = out2;
+        upload_coef(c);
+        a.coef = coef.as<double>();
+        const long total = n * R;
+        if (total == 0) return;
+        hipLaunchKernelGGL(k_lincomb, dim3(blocks_for(total)), dim3(256), 0, st, a, total, R);
+        hip_check(hipGetLastError(), "k_lincomb launch");
+    }
+    void upload_coef(const std::vector<double> &c)
+    {
+        // stream-ordered copy through a pinned staging area; wait for it to
+        // land so that the staging area can be reused
+        std::memcpy(hbuf, c.data(), sizeof(double) * c.size());
+        hip_check(hipMemcpyAsync(coef.p, hbuf, sizeof(double) * c.size(), hipMemcpyHostToDevice, st), "H2D");
+        hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    }
+};
+
+}  // namespace
+
+}  // namespace hec
+
+// Preconditioner application hooks defined in capi.hip.
+namespace hec {
+void precond_apply(const hec_precond_t &M, const double *r, double *z, int32_t R, hipStream_t st);
+void precond_check(const hec_precond_t &M, int32_t n);
+}  // namespace hec
+
+using namespace hec;
+
+namespace {
+
+void apply_M(const hec_precond_t &M, const double *r, double *z, int R, long n, hipStream_t st)
+{
+    if (M.kind == HEC_PRECOND_NONE) {
+        if (z != r) hip_check(hipMemcpyAsync(z, r, sizeof(double) * n * R, hipMemcpyDeviceToDevice, st), "copy");
+        return;
+    }
+    precond_apply(M, r, z, R, st);
+}
+
+// Restarted (F)GMRES(m): right preconditioning with the preconditioned basis
+// Z stored (flexible form), CGS with one re-orthogonalization, Givens
+// rotations on the host.  Every RHS runs its own Arnoldi process in lockstep;
+// an RHS whose rotated residual reaches rtol stops extending its basis.
+hec_status_t gmres(const DevHec &A, const hec_precond_t &M, int m, const double *b, double *x, int R, double rtol,
+                   int maxit, hec_krylov_info_t *info, hipStream_t st)
+{
+    const long n = A.n;
+    const long nR = n * R;
+    Ctx c(n, R, st);
+    DevMem Vm, Zm, wm, rm;
+    Vm.alloc(sizeof(double) * (size_t)(m + 1) * nR);
+    Zm.alloc(sizeof(double) * (size_t)m * nR);
+    wm.alloc(sizeof(double) * (size_t)nR);
+    rm.alloc(sizeof(double) * (size_t)nR);
+    double *V = Vm.as<double>(), *Z = Zm.as<double>(), *w = wm.as<double>(), *r = rm.as<double>();
+    auto Vi = [&](int i) { return V + (size_t)i * nR; };
+    auto Zi = [&](int i) { return Z + (size_t)i * nR; };
+
+    std::vector<double> bnorm(R), relres(R, 0.0);
+    {
+        const double *a[1] = {b};
+        c.dots_to_host(a, a, 1);
+        for (int k = 0; k < R; ++k) bnorm[k] = std::sqrt(c.hbuf[k]);
+    }
+    std::vector<char> done(R, 0);
+    bool zero_rhs = false;
+    for (int k = 0; k < R; ++k) {
+        info[k] = hec_krylov_info_t{HEC_OK, 0, 0, 0, 0.0};
+        if (bnorm[k] == 0.0) done[k] = 1, zero_rhs = true;
+    }
+    if (zero_rhs) {
+        // a zero right-hand side has the solution x = 0
+        std::vector<double> keep(R);
+        for (int k = 0; k < R; ++k) keep[k] = bnorm[k] == 0.0 ? 0.0 : 1.0;
+        c.lincomb(x, {x}, keep);
+    }
+    std::vector<double> H((size_t)(m + 1) * m * R), cs((size_t)m * R), sn((size_t)m * R), g((size_t)(m + 1) * R);
+    auto h_at = [&](int i, int j, int k) -> double & { return H[((size_t)i * m + j) * R + k]; };
+    std::vector<int> kdim(R, 0);
+    std::vector<char> active(R, 0);
+    std::vector<const double *> pa(kMaxPairs), pb(kMaxPairs);
+    int iters = 0;
+    hec_status_t status = HEC_OK;
+    for (;;) {
+        // true residual and convergence test
+        residual(A, b, x, r, R, st);
+        {
+            const double *a[1] = {r};
+            c.dots_to_host(a, a, 1);
+        }
+        bool any = false;
+        std::vector<double> beta(R);
+        for (int k = 0; k < R; ++k) {
+            beta[k] = std::sqrt(c.hbuf[k]);
+            relres[k] = bnorm[k] > 0 ? beta[k] / bnorm[k] : 0.0;
+            if (bnorm[k] == 0.0 || relres[k] <= rtol) done[k] = 1;
+            active[k] = !done[k];
+            any = any || active[k];
+        }
+        if (!any) break;
+        if (iters >= maxit) {
+            status = HEC_ERR_NOT_CONVERGED;
+            break;
+        }
+        // v_0 = r / beta
+        std::vector<double> cf(R);
+        for (int k = 0; k < R; ++k) cf[k] = active[k] ? 1.0 / beta[k] : 0.0;
+        c.lincomb(Vi(0), {r}, cf);
+        std::fill(g.begin(), g.end(), 0.0);
+        for (int k = 0; k < R; ++k) {
+            g[k] = active[k] ? beta[k] : 0.0;
+            kdim[k] = 0;
+        }
+        int j = 0;
+        for (; j < m; ++j) {
+            apply_M(M, Vi(j), Zi(j), R, n, st);
+            spmv(A, Zi(j), w, R, st);
+            // two passes of classical Gram-Schmidt
+            std::vector<double> hcol((size_t)(j + 1) * R, 0.0);
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int i = 0; i <= j; ++i) {
+                    pa[i] = Vi(i);
+                    pb[i] = w;
+                }
+                c.dots_to_host(pa.data(), pb.data(), j + 1);
+                std::vector<double> hh(c.hbuf, c.hbuf + (size_t)(j + 1) * R);
+                for (size_t q = 0; q < hh.size(); ++q) hcol[q] += hh[q];
+                c.upload_coef(hh);
+                hipLaunchKernelGGL(k_gs_update, dim3(blocks_for(nR)), dim3(256), 0, st, w, V, nR,
+                                   c.coef.as<double>(), j + 1, nR, R);
+                hip_check(hipGetLastError(), "k_gs_update");
+            }
+            {
+                const double *a[1] = {w};
+                c.dots_to_host(a, a, 1);
+            }
+            std::vector<double> hn(R);
+            for (int k = 0; k < R; ++k) hn[k] = std::sqrt(std::max(0.0, c.hbuf[k]));
+            for (int k = 0; k < R; ++k) cf[k] = (active[k] && hn[k] > 0.0) ? 1.0 / hn[k] : 0.0;
+            c.lincomb(Vi(j + 1), {w}, cf);
+            ++iters;
+            bool still = false;
+            for (int k = 0; k < R; ++k) {
+                if (!active[k]) continue;
+                info[k].iters += 1;
+                info[k].precond_applies += 1;
+                for (int i = 0; i <= j; ++i) h_at(i, j, k) = hcol[(size_t)i * R + k];
+                h_at(j + 1, j, k) = hn[k];
+                for (int i = 0; i < j; ++i) {
+                    const double t = cs[i * R + k] * h_at(i, j, k) + sn[i * R + k] * h_at(i + 1, j, k);
+                    h_at(i + 1, j, k) = -sn[i * R + k] * h_at(i, j, k) + cs[i * R + k] * h_at(i + 1, j, k);
+                    h_at(i, j, k) = t;
+                }
+                const double den = std::hypot(h_at(j, j, k), h_at(j + 1, j, k));
+                if (den == 0.0) {
+                    status = HEC_ERR_BREAKDOWN;
+                    info[k].status = HEC_ERR_BREAKDOWN;
+                    active[k] = 0;
+                    done[k] = 1;
+                    continue;
+                }
+                cs[j * R + k] = h_at(j, j, k) / den;
+                sn[j * R + k] = h_at(j + 1, j, k) / den;
+                h_at(j, j, k) = den;
+                h_at(j + 1, j, k) = 0.0;
+                g[(j + 1) * R + k] = -sn[j * R + k] * g[j * R + k];
+                g[j * R + k] = cs[j * R + k] * g[j * R + k];
+                kdim[k] = j + 1;
+                if (std::fabs(g[(j + 1) * R + k]) / bnorm[k] <= rtol || hn[k] == 0.0 || iters >= maxit)
+                    active[k] = 0;
+                still = still || active[k];
+            }
+            if (!still) {
+                ++j;
+                break;
+            }
+        }
+        // y = H^{-1} g per RHS, x += Z y
+        const int nv = *std::max_element(kdim.begin(), kdim.end());
+        if (nv > 0) {
+            std::vector<double> y((size_t)nv * R, 0.0);
+            for (int k = 0; k < R; ++k) {
+                const int kk = kdim[k];
+                for (int i = kk - 1; i >= 0; --i) {
+                    double s = g[i * R + k];
+                    for (int l = i + 1; l < kk; ++l) s -= h_at(i, l, k) * y[l * R + k];
+                    y[i * R + k] = s / h_at(i, i, k);
+                }
+                if (kk > 0) info[k].restarts += 1;
+            }
+            c.upload_coef(y);
+            hipLaunchKernelGGL(k_basis_update, dim3(blocks_for(nR)), dim3(256), 0, st, x, Z, nR, c.coef.as<double>(),
+                               nv, nR, R);
+            hip_check(hipGetLastError(), "k_basis_update");
+        }
+        if (status == HEC_ERR_BREAKDOWN) {
+            // keep the partial update; the final residual decides
+        }
+    }
+    residual(A, b, x, r, R, st);
+    {
+        const double *a[1] = {r};
+        c.dots_to_host(a, a, 1);
+    }
+    hec_status_t out = HEC_OK;
+    for (int k = 0; k < R; ++k) {
+        info[k].relres = bnorm[k] > 0 ? std::sqrt(c.hbuf[k]) / bnorm[k] : 0.0;
+        if (info[k].relres > rtol) {
+            if (info[k].status == HEC_OK) info[k].status = HEC_ERR_NOT_CONVERGED;
+            out = (hec_status_t)info[k].status;
+        }
+    }
+    return out;
+}
+
+// Right-preconditioned BiCGSTAB (van der Vorst) per RHS, shadow residual
+// r0; when rho or (r0, v) vanishes the recurrence restarts from the current
+// true residual.  Convergence is tested on the true residual.
+hec_status_t bicgstab(const DevHec &A, const hec_precond_t &M, const double *b, double *x, int R, double rtol,
+                      int maxit, hec_krylov_info_t *info, hipStream_t st)
+{
+    const long n = A.n, nR = n * R;
+    Ctx c(n, R, st);
+    DevMem rm, rhm, pm, vm, phm, sm, shm, tm;
+    for (DevMem *d : {&rm, &rhm, &pm, &vm, &phm, &sm, &shm, &tm}) d->alloc(sizeof(double) * (size_t)std::max<long>(1, nR));
+    double *r = rm.as<double>(), *rh = rhm.as<double>(), *p = pm.as<double>(), *v = vm.as<double>(),
+           *ph = phm.as<double>(), *s = sm.as<double>(), *sh = shm.as<double>(), *t = tm.as<double>();
+    std::vector<double> bnorm(R);
+    {
+        const double *a[1] = {b};
+        c.dots_to_host(a, a, 1);
+        for (int k = 0; k < R; ++k) bnorm[k] = std::sqrt(c.hbuf[k]);
+    }
+    for (int k = 0; k < R; ++k) info[k] = hec_krylov_info_t{HEC_OK, 0, 0, 0, 0.0};
+    std::vector<char> done(R, 0);
+    {
+        std::vector<double> keep(R);
+        bool zero_rhs = false;
+        for (int k = 0; k < R; ++k) {
+            keep[k] = bnorm[k] == 0.0 ? 0.0 : 1.0;
+            zero_rhs = zero_rhs || bnorm[k] == 0.0;
+        }
+        if (zero_rhs) c.lincomb(x, {x}, keep);
+    }
+    int iters = 0, breakdowns = 0;
+    hec_status_t status = HEC_OK;
+    std::vector<double> rho(R), rho_old(R), alpha(R), omega(R), cf;
+    for (;;) {
+        residual(A, b, x, r, R, st);
+        {
+            const double *a[1] = {r};
+            c.dots_to_host(a, a, 1);
+        }
+        bool any = false;
+        for (int k = 0; k < R; ++k) {
+            const double rr = bnorm[k] > 0 ? std::sqrt(c.hbuf[k]) / bnorm[k] : 0.0;
+            if (bnorm[k] == 0.0 || rr <= rtol) done[k] = 1;
+            any = any || !done[k];
+        }
+        if (!any) break;
+        if (iters >= maxit) {
+            status = HEC_ERR_NOT_CONVERGED;
+            break;
+        }
+        if (breakdowns > 50) {
+            status = HEC_ERR_BREAKDOWN;
+            break;
+        }
+        hip_check(hipMemcpyAsync(rh, r, sizeof(double) * nR, hipMemcpyDeviceToDevice, st), "copy");
+        hip_check(hipMemsetAsync(p, 0, sizeof(double) * nR, st), "memset");
+        hip_check(hipMemsetAsync(v, 0, sizeof(double) * nR, st), "memset");
+        std::fill(rho_old.begin(), rho_old.end(), 1.0);
+        std::fill(alpha.begin(), alpha.end(), 1.0);
+        std::fill(omega.begin(), omega.end(), 1.0);
+        std::vector<char> act(R);
+        for (int k = 0; k < R; ++k) act[k] = !done[k];
+        bool restart = false;
+        while (iters < maxit && !restart) {
+            {
+                const double *a[1] = {rh}, *bb[1] = {r};
+                c.dots_to_host(a, bb, 1);
+            }
+            for (int k = 0; k < R; ++k) {
+                rho[k] = c.hbuf[k];
+                if (act[k] && rho[k] == 0.0) restart = true;
+            }
+            if (restart) {
+                ++breakdowns;
+                break;
+            }
+            // p = r + beta (p - omega v)
+            cf.assign(3 * (size_t)R, 0.0);
+            for (int k = 0; k < R; ++k) {
+                if (!act[k]) continue;
+                const double beta = (rho[k] / rho_old[k]) * (alpha[k] / omega[k]);
+                cf[k] = 1.0;
+                cf[R + k] = beta;
+                cf[2 * R + k] = -beta * omega[k];
+            }
+            c.lincomb(p, {r, p, v}, cf);
+            apply_M(M, p, ph, R, n, st);
+            spmv(A, ph, v, R, st);
+            {
+                const double *a[1] = {rh}, *bb[1] = {v};
+                c.dots_to_host(a, bb, 1);
+            }
+            for (int k = 0; k < R; ++k) {
+                if (!act[k]) {
+                    alpha[k] = 0.0;
+                    continue;
+                }
+                if (c.hbuf[k] == 0.0) restart = true;
+                alpha[k] = c.hbuf[k] != 0.0 ? rho[k] / c.hbuf[k] : 0.0;
+            }
+            if (restart) {
+                ++breakdowns;
+                break;
+            }
+            // s = r - alpha v
+            cf.assign(2 * (size_t)R, 0.0);
+            for (int k = 0; k < R; ++k) {
+                cf[k] = 1.0;
+                cf[R + k] = -alpha[k];
+            }
+            c.lincomb(s, {r, v}, cf);
+            ++iters;
+            for (int k = 0; k < R; ++k)
+                if (act[k]) {
+                    info[k].iters += 1;
+                    info[k].precond_applies += 1;
+                }
+            {
+                const double *a[1] = {s};
+                c.dots_to_host(a, a, 1);
+            }
+            bool early = false;
+            std::vector<char> sdone(R, 0);
+            for (int k = 0; k < R; ++k)
+                if (act[k] && std::sqrt(c.hbuf[k]) / bnorm[k] <= rtol) sdone[k] = 1, early = true;
+            apply_M(M, s, sh, R, n, st);
+            spmv(A, sh, t, R, st);
+            {
+                const double *a[2] = {t, t}, *bb[2] = {s, t};
+                c.dots_to_host(a, bb, 2);
+            }
+            for (int k = 0; k < R; ++k) {
+                if (!act[k] || sdone[k]) {
+                    omega[k] = 0.0;
+                    continue;
+                }
+                const double ts = c.hbuf[k], tt = c.hbuf[R + k];
+                omega[k] = tt != 0.0 ? ts / tt : 0.0;
+                info[k].precond_applies += 1;
+            }
+            // x += alpha ph + omega sh ; r = s - omega t
+            cf.assign(3 * (size_t)R, 0.0);
+            for (int k = 0; k < R; ++k) {
+                cf[k] = 1.0;
+                cf[R + k] = act[k] ? alpha[k] : 0.0;
+                cf[2 * R + k] = act[k] ? omega[k] : 0.0;
+            }
+            c.lincomb(x, {x, ph, sh}, cf);
+            cf.assign(2 * (size_t)R, 0.0);
+            for (int k = 0; k < R; ++k) {
+                cf[k] = 1.0;
+                cf[R + k] = -omega[k];
+            }
+            c.lincomb(r, {s, t}, cf);
+            {
+                const double *a[1] = {r};
+                c.dots_to_host(a, a, 1);
+            }
+            bool any_act = false;
+            for (int k = 0; k < R; ++k) {
+                if (!act[k]) continue;
+                const double rr = std::sqrt(c.hbuf[k]) / bnorm[k];
+                if (sdone[k] || rr <= rtol || omega[k] == 0.0) {
+                    act[k] = 0;
+                    restart = true;  // confirm on the true residual
+                }
+                any_act = any_act || act[k];
+                rho_old[k] = rho[k];
+            }
+            if (early || !any_act) restart = true;
+        }
+    }
+    residual(A, b, x, r, R, st);
+    {
+        const double *a[1] = {r};
+        c.dots_to_host(a, a, 1);
+    }
+    hec_status_t out = HEC_OK;
+    for (int k = 0; k < R; ++k) {
+        info[k].relres = bnorm[k] > 0 ? std::sqrt(c.hbuf[k]) / bnorm[k] : 0.0;
+        if (info[k].relres > rtol) {
+            info[k].status = status == HEC_ERR_BREAKDOWN ? HEC_ERR_BREAKDOWN : HEC_ERR_NOT_CONVERGED;
+            out = (hec_status_t)info[k].status;
+        }
+    }
+    return out;
+}
+
+}  // namespace
+
+extern "C" {
+
+hec_status_t hec_from_csr(int32_t n, const int32_t *rowptr, const int32_t *col, const void *val, hec_dtype_t dt,
+                          int32_t ell_width, hec_matrix_t *out)
+{
+    return guard_status([&]() -> hec_status_t {
+            if (!out) fail(HEC_ERR_INVALID_ARG, "out is NULL");
+            if (ell_width < -1 || ell_width > 64) fail(HEC_ERR_INVALID_ARG, "ell_width out of range");
+            Csr a = csr_copy(n, rowptr, col, val, dt);
+            auto m = std::make_unique<hec_matrix_s>();
+            DevHec &d = m->d;
+            d.n = n;
+            d.dt = dt;
+            int32_t w = ell_width;
+            if (w < 0) {
+                std::vector<int32_t> len(n);
+                for (int32_t i = 0; i < n; ++i) len[i] = a.rp[i + 1] - a.rp[i];
+                std::vector<int32_t> srt = len;
+                std::sort(srt.begin(), srt.end());
+                w = n ? srt[(n - 1) / 2] : 0;
+                w = std::min(w, 64);
+            }
+            HecHost &h = d.host;
+            h.n = n;
+            h.w = w;
+            h.ld = (n + 63) / 64 * 64;
+            h.ell_col.assign((size_t)w * h.ld, n);
+            h.ell_val.assign((size_t)w * h.ld, 0.0);
+            h.csr_ptr.assign((size_t)n + 1, 0);
+            for (int32_t i = 0; i < n; ++i) {
+                int32_t e = 0;
+                for (int32_t p = a.rp[i]; p < a.rp[i + 1]; ++p) {
+                    if (e < w) {
+                        h.ell_col[(size_t)e * h.ld + i] = a.ci[p];
+                        h.ell_val[(size_t)e * h.ld + i] = a.v[p];
+                        ++e;
+                    } else {
+                        h.csr_col.push_back(a.ci[p]);
+                        h.csr_val.push_back(a.v[p]);
+                    }
+                }
+                h.csr_ptr[i + 1] = (int32_t)h.csr_col.size();
+            }
+            d.w = w;
+            d.ld = h.ld;
+            d.tail_nnz = (int64_t)h.csr_col.size();
+            hip_check(hipGetDevice(&d.device), "hipGetDevice");
+            upload(d.ell_col, h.ell_col);
+            upload_values(d.ell_val, h.ell_val, dt);
+            if (d.tail_nnz > 0) {
+                upload(d.tail_ptr, h.csr_ptr);
+                upload(d.tail_col, h.csr_col);
+                upload_values(d.tail_val, h.csr_val, dt);
+            }
+            *out = m.release();
+            return HEC_OK;
+    });
+}
+
+hec_status_t hec_spmv(hec_matrix_t A, const double *x, double *y, int32_t nrhs, hipStream_t st)
+{
+    return guard_status([&]() -> hec_status_t {
+            if (!A || nrhs < 1) fail(HEC_ERR_INVALID_ARG, "bad arguments");
+            if (A->d.n > 0 && (!x || !y)) fail(HEC_ERR_INVALID_ARG, "vector pointer is NULL");
+            spmv(A->d, x, y, nrhs, st);
+            return HEC_OK;
+    });
+}
+
+hec_status_t hec_matrix_export(hec_matrix_t A, int32_t *width, int32_t *ld, int64_t *tail_nnz, int32_t *ell_col,
+                               double *ell_val, int32_t *csr_ptr, int32_t *csr_col, double *csr_val)
+{
+    return guard([&] {
+    if (!A) fail(HEC_ERR_INVALID_ARG, "matrix is NULL");
+    const HecHost &h = A->d.host;
+    if (width) *width = h.w;
+    if (ld) *ld = h.ld;
+    if (tail_nnz) *tail_nnz = (int64_t)h.csr_col.size();
+    if (ell_col) std::copy(h.ell_col.begin(), h.ell_col.end(), ell_col);
+    if (ell_val) std::copy(h.ell_val.begin(), h.ell_val.end(), ell_val);
+    if (csr_ptr) std::copy(h.csr_ptr.begin(), h.csr_ptr.end(), csr_ptr);
+    if (csr_col) std::copy(h.csr_col.begin(), h.csr_col.end(), csr_col);
+    if (csr_val) std::copy(h.csr_val.begin(), h.csr_val.end(), csr_val);
+    });
+}
+
+void hec_matrix_destroy(hec_matrix_t A) { delete A; }
+
+hec_status_t krylov_solve(hec_matrix_t A, hec_precond_t M, hec_krylov_t method, int32_t m, const double *b,
+                          double *x, int32_t nrhs, double rtol, int32_t maxit, hec_krylov_info_t *info,
+                          hipStream_t st)
+{
+    return guard_status([&]() -> hec_status_t {
+            if (!A || !info || nrhs < 1 || maxit < 0 || !(rtol > 0.0)) fail(HEC_ERR_INVALID_ARG, "bad arguments");
+            if (nrhs > 256) fail(HEC_ERR_INVALID_ARG, "at most 256 right-hand sides per solve");
+            if (A->d.n > 0 && (!b || !x)) fail(HEC_ERR_INVALID_ARG, "vector pointer is NULL");
+            precond_check(M, A->d.n);
+            if (method == HEC_GMRES || method == HEC_FGMRES) {
+                if (m < 1 || m > kMaxPairs - 1) fail(HEC_ERR_INVALID_ARG, "GMRES restart length must be 1..31");
+                return gmres(A->d, M, m, b, x, nrhs, rtol, maxit, info, st);
+            }
+            if (method == HEC_BICGSTAB) return bicgstab(A->d, M, b, x, nrhs, rtol, maxit, info, st);
+            fail(HEC_ERR_INVALID_ARG, "unknown Krylov method");
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,224 @@
+"""GPU parity of the ILU, RAS and batched preconditioners (Section 3,
+eq. (1) and eq. (4)), the Krylov solvers and graph replay, against the CPU
+oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth import CSR
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1606_00541_amd as H  # noqa: E402
+
+FP64_TOL = 1e-12
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def relerr(x, ref):
+    return float(np.linalg.norm(x - ref) / max(np.linalg.norm(ref), 1e-300))
+
+
+def apply(f, r):
+    rt = dev(r)
+    zt = torch.empty_like(rt)
+    (H.ras_apply if isinstance(f, H.Ras) else H.ilu_apply)(f, rt, zt)
+    torch.cuda.synchronize()
+    return zt.cpu().numpy()
+
+
+def same_csr(rp, ci, v, T):
+    return np.array_equal(rp, T.rowptr) and np.array_equal(ci, T.col) and np.array_equal(v, T.val)
+
+
+@pytest.mark.parametrize("sched", ["level_persistent", "owner_persistent"])
+def test_config2_poisson128_ilu0_full_size(sched):
+    A = synth.poisson3d(128)
+    f = H.ilu_setup(A, "ilu0", tune=H.tune_default(schedule=sched))
+    L, U = oracle.ilu0(A)
+    assert same_csr(*H.ilu_factor(f, 0), L) and same_csr(*H.ilu_factor(f, 1), U)
+    pl, pu = H.ilu_plans(f)
+    assert H.tri_plan_info(pl)[0] == 382 and H.tri_plan_info(pu)[0] == 382
+    st = H.tri_plan_stats(pl)
+    assert st["ell_width"] == 3 and st["nnz_tail"] == 0
+    r = synth.rhs(A.n, 1, 2)
+    z = apply(f, r)
+    assert relerr(z, oracle.ilu_apply(L, U, r)) <= FP64_TOL
+
+
+@pytest.mark.parametrize("kind,args", [("ilu0", {}), ("iluk", {"k": 1}), ("iluk", {"k": 2}),
+                                       ("ilut", {"p": 10, "tol": 1e-3})])
+def test_ilu_kinds_match_oracle(kind, args):
+    A = synth.diffusion3d(14, 13, 12, 2.0, seed=3)
+    f = H.ilu_setup(A, kind, tune=H.tune_default(max_nrhs=4), **args)
+    if kind == "ilu0":
+        L, U = oracle.ilu0(A)
+    elif kind == "iluk":
+        L, U = oracle.iluk(A, args["k"])
+    else:
+        L, U = oracle.ilut(A, args["p"], args["tol"])
+    assert same_csr(*H.ilu_factor(f, 0), L) and same_csr(*H.ilu_factor(f, 1), U)
+    r = synth.rhs(A.n, 4, 5)
+    assert relerr(apply(f, r), oracle.ilu_apply(L, U, r)) <= FP64_TOL
+
+
+def test_fp32_factors_fp64_vectors():
+    A = synth.diffusion3d(16, 16, 16, 2.0, seed=3)
+    f = H.ilu_setup(A, "ilut", p=10, tol=1e-3, factor_dtype="f32")
+    L, U = oracle.ilut(A, 10, 1e-3)
+    r = synth.rhs(A.n, 1, 3)
+    ref = oracle.ilu_apply_f32(oracle.to_f32(L), oracle.to_f32(U), r)
+    z = apply(f, r)
+    assert z.dtype == np.float64
+    assert relerr(z, ref) <= 1e-5
+    assert relerr(z, oracle.ilu_apply(L, U, r)) <= 1e-4
+
+
+@pytest.mark.parametrize("fdt", ["f64", "f32"])
+def test_ras_matches_oracle(fdt):
+    A = synth.poisson3d(18)
+    owner, _ = synth.subdomain_cuts(A.n, 6, 500, 1500, seed=4)
+    s = H.ras_setup(A, 6, owner, overlap=1, factor_dtype=fdt, tune=H.tune_default(max_nrhs=3))
+    doms = oracle.ras_setup(A, owner, 6, overlap=1)
+    nsub, tot, sizes = H.ras_info(s)
+    assert nsub == 6 and list(sizes) == [len(d.ext) for d in doms]
+    r = synth.rhs(A.n, 3, 5)
+    z = apply(s, r)
+    if fdt == "f64":
+        assert relerr(z, oracle.ras_apply(doms, r)) <= FP64_TOL
+    else:
+        assert relerr(z, oracle.ras_apply_f32(oracle.ras_to_f32(doms), r)) <= 1e-5
+
+
+def _block_diag(mats):
+    rps, cis, vs, sys_ptr, off, nnz = [np.zeros(1, np.int64)], [], [], [0], 0, 0
+    for M in mats:
+        rps.append(M.rowptr[1:].astype(np.int64) + nnz)
+        cis.append(M.col.astype(np.int64) + off)
+        vs.append(M.val)
+        off += M.n
+        nnz += M.nnz
+        sys_ptr.append(off)
+    return CSR(off, np.concatenate(rps).astype(np.int32), np.concatenate(cis).astype(np.int32),
+               np.concatenate(vs)), np.array(sys_ptr, np.int32)
+
+
+def test_batch_matches_per_system_oracle():
+    mats = [synth.diffusion2d(30, 20, 1.0, seed=1), synth.diffusion3d(9, 8, 7, 1.0, seed=2),
+            synth.poisson2d(5, 3), synth.diffusion3d(13, 13, 13, 1.0, seed=4), synth.poisson2d(41, 1)]
+    A, sys_ptr = _block_diag(mats)
+    f = H.batch_setup(A, sys_ptr, "iluk", k=1, tune=H.tune_default(max_nrhs=8))
+    r = synth.rhs(A.n, 8, 7)
+    z = apply(f, r)
+    for s, M in enumerate(mats):
+        L, U = oracle.iluk(M, 1)
+        seg = slice(int(sys_ptr[s]), int(sys_ptr[s + 1]))
+        assert relerr(z[seg], oracle.ilu_apply(L, U, r[seg])) <= FP64_TOL
+
+
+def test_batch_rejects_coupled_systems():
+    A = synth.poisson2d(6)
+    with pytest.raises(H.HecError) as e:
+        H.batch_setup(A, np.array([0, 18, 36], np.int32))
+    assert e.value.name == "INVALID_ARG"
+
+
+def test_hec_matrix_roundtrip_and_spmv():
+    A = synth.diffusion3d(10, 9, 8, 1.5, seed=6)
+    M = H.hec_from_csr(A, ell_width=4)
+    h = H.hec_matrix_export(M)
+    T = oracle.hec_to_csr(A.n, h["width"], h["ld"], h["ell_col"], h["ell_val"], h["csr_ptr"], h["csr_col"],
+                          h["csr_val"])
+    assert np.array_equal(T.rowptr, A.rowptr) and np.array_equal(T.col, A.col) and np.array_equal(T.val, A.val)
+    x = synth.rhs(A.n, 2, 8)
+    xt = dev(x)
+    yt = torch.empty_like(xt)
+    H.hec_spmv(M, xt, yt)
+    torch.cuda.synchronize()
+    assert relerr(yt.cpu().numpy(), oracle.spmv(A, x)) <= 1e-14
+
+
+def test_gmres_ilu0_reaches_tolerance():
+    A = synth.poisson3d(24)
+    f = H.ilu_setup(A, "ilu0")
+    M = H.hec_from_csr(A)
+    b = synth.rhs(A.n, 2, 2)
+    xt = torch.zeros(A.n, 2, dtype=torch.float64, device="cuda")
+    st, info = H.krylov_solve(M, f, dev(b), xt, method="gmres", m=30, rtol=1e-10)
+    x = xt.cpu().numpy()
+    assert st == 0
+    L, U = oracle.ilu0(A)
+    for k in range(2):
+        true = np.linalg.norm(b[:, k] - oracle.spmv(A, x[:, k])) / np.linalg.norm(b[:, k])
+        assert true <= 1e-10 and abs(true - info[k].relres) <= 1e-12
+        xo, io = oracle.fgmres(A, b[:, k], lambda v: oracle.ilu_apply(L, U, v), m=30, rtol=1e-10)
+        assert relerr(x[:, k], xo) <= 1e-7
+        assert abs(info[k].iters - io.iters) <= 2
+
+
+def test_fgmres_mixed_precision_refinement():
+    A = synth.diffusion3d(16, 16, 16, 2.0, seed=3)
+    f32 = H.ilu_setup(A, "ilut", p=10, tol=1e-3, factor_dtype="f32")
+    M = H.hec_from_csr(A)
+    b = synth.rhs(A.n, 1, 3)
+    xt = torch.zeros(A.n, 1, dtype=torch.float64, device="cuda")
+    st, info = H.krylov_solve(M, f32, dev(b), xt, method="fgmres", m=30, rtol=1e-10)
+    assert st == 0
+    x = xt.cpu().numpy()[:, 0]
+    true = np.linalg.norm(b[:, 0] - oracle.spmv(A, x)) / np.linalg.norm(b[:, 0])
+    assert true <= 1e-10
+    L, U = oracle.ilut(A, 10, 1e-3)
+    xo, _ = oracle.fgmres(A, b[:, 0], lambda v: oracle.ilu_apply(L, U, v), m=30, rtol=1e-10)
+    assert relerr(x, xo) <= 1e-6
+
+
+def test_bicgstab_ras_fp32_multi_rhs():
+    A = synth.poisson3d(20)
+    owner, _ = synth.subdomain_cuts(A.n, 8, 600, 1600, seed=4)
+    s = H.ras_setup(A, 8, owner, overlap=1, factor_dtype="f32", tune=H.tune_default(max_nrhs=4))
+    M = H.hec_from_csr(A)
+    b = synth.rhs(A.n, 4, 4)
+    xt = torch.zeros(A.n, 4, dtype=torch.float64, device="cuda")
+    st, info = H.krylov_solve(M, s, dev(b), xt, method="bicgstab", rtol=1e-10)
+    assert st == 0
+    x = xt.cpu().numpy()
+    for k in range(4):
+        true = np.linalg.norm(b[:, k] - oracle.spmv(A, x[:, k])) / np.linalg.norm(b[:, k])
+        assert true <= 1e-10
+
+
+def test_krylov_reports_not_converged():
+    A = synth.poisson3d(12)
+    f = H.ilu_setup(A, "ilu0")
+    M = H.hec_from_csr(A)
+    b = synth.rhs(A.n, 1, 1)
+    xt = torch.zeros(A.n, 1, dtype=torch.float64, device="cuda")
+    st, info = H.krylov_solve(M, f, dev(b), xt, method="gmres", m=5, rtol=1e-10, maxit=2)
+    assert st == 8 and info[0].status == 8 and info[0].iters == 2
+
+
+@pytest.mark.parametrize("kind", ["ilu", "ras"])
+def test_graph_replay_matches_eager(kind):
+    A = synth.poisson3d(16)
+    if kind == "ilu":
+        M = H.ilu_setup(A, "ilu0", tune=H.tune_default(schedule="owner_persistent", max_nrhs=2))
+    else:
+        owner, _ = synth.subdomain_cuts(A.n, 4, 600, 1500, seed=2)
+        M = H.ras_setup(A, 4, owner, overlap=1, factor_dtype="f32", tune=H.tune_default(max_nrhs=2))
+    r = dev(synth.rhs(A.n, 2, 3))
+    z = torch.empty_like(r)
+    g = H.hec_graph_capture(M, r, z)
+    ze = torch.empty_like(r)
+    for rep in range(4):
+        r.mul_(0.5).add_(float(rep))  # eager work between replays changes the input
+        H.hec_graph_launch(g)
+        torch.cuda.synchronize()
+        got = z.clone()
+        (H.ras_apply if kind == "ras" else H.ilu_apply)(M, r, ze)
+        torch.cuda.synchronize()
+        assert torch.equal(got, ze)

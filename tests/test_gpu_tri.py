@@ -1,0 +1,154 @@
+"""GPU parity of the level-scheduled triangular solves (Algorithm 2) against
+the CPU oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth import CSR
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1606_00541_amd as H  # noqa: E402
+
+SCHEDS = ["level_launch", "level_persistent", "owner_persistent"]
+FP64_TOL = 1e-12
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def relerr(x, ref):
+    return float(np.linalg.norm(x - ref) / max(np.linalg.norm(ref), 1e-300))
+
+
+def transpose(T):
+    m = T.to_scipy().T.tocsr()
+    m.sort_indices()
+    return CSR(T.n, m.indptr.astype(np.int32), m.indices.astype(np.int32), m.data.copy())
+
+
+def solve(plan, b, upper=False):
+    bt = dev(b)
+    xt = torch.empty_like(bt)
+    (H.tri_solve_upper if upper else H.tri_solve_lower)(plan, bt, xt)
+    torch.cuda.synchronize()
+    return xt.cpu().numpy()
+
+
+@pytest.mark.parametrize("sched", SCHEDS)
+def test_config1_poisson64_ilu0(sched):
+    A = synth.poisson2d(64)
+    L, U = oracle.ilu0(A)
+    b = synth.rhs(A.n, 1, 1)
+    t = H.tune_default(schedule=sched)
+    pl = H.tri_analyze(L, "lower", unit_diag=True, tune=t)
+    pu = H.tri_analyze(U, "upper", tune=t)
+    for plan, T, up in ((pl, L, False), (pu, U, True)):
+        nlev, lp, perm = H.tri_plan_info(plan)
+        lev, nl = oracle.levels(T, upper=up)
+        lp2, perm2, _ = oracle.level_schedule(lev, nl, upper=up)
+        assert nlev == 127 and np.array_equal(lp, lp2) and np.array_equal(perm, perm2)
+    y = solve(pl, b)
+    x = solve(pu, y, upper=True)
+    yref = oracle.lower_solve(L, b, unit=True)
+    xref = oracle.upper_solve(U, yref)
+    assert relerr(y, yref) <= FP64_TOL
+    assert relerr(x, xref) <= FP64_TOL
+
+
+def test_schedules_are_bit_identical():
+    L = synth.random_lower(5000, 0.0015, seed=21)
+    b = synth.rhs(L.n, 2, 22)
+    outs = []
+    for s in SCHEDS:
+        p = H.tri_analyze(L, "lower", tune=H.tune_default(schedule=s, max_nrhs=2))
+        outs.append(solve(p, b))
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+@pytest.mark.parametrize("sched", SCHEDS)
+@pytest.mark.parametrize("upper", [False, True])
+@pytest.mark.parametrize("nrhs", [1, 3])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_random_triangles(sched, upper, nrhs, seed):
+    n = 3001 + 17 * seed  # several 64-row tiles and a ragged tail
+    L = synth.random_lower(n, 0.002, seed=100 + seed, dense_row=n // 3)
+    T = transpose(L) if upper else L
+    b = synth.rhs(n, nrhs, 200 + seed)
+    # ELL width 1 pushes most entries into the CSR remainder
+    for w in (-1, 1):
+        p = H.tri_analyze(T, "upper" if upper else "lower", tune=H.tune_default(schedule=sched, ell_width=w))
+        x = solve(p, b, upper)
+        ref = (oracle.upper_solve if upper else oracle.lower_solve)(T, b)
+        assert relerr(x, ref) <= FP64_TOL
+
+
+def test_cooperative_lanes_for_long_rows():
+    n = 2000
+    L = synth.random_lower(n, 0.01, seed=5, dense_row=1500)
+    b = synth.rhs(n, 2, 6)
+    for sched in ("level_persistent", "owner_persistent"):
+        t = H.tune_default(schedule=sched, group_lanes=8, long_row=4, ell_width=2)
+        p = H.tri_analyze(L, "lower", tune=t)
+        assert relerr(solve(p, b), oracle.lower_solve(L, b)) <= FP64_TOL
+
+
+@pytest.mark.parametrize("sched", SCHEDS)
+def test_fp32_plans(sched):
+    A = synth.diffusion3d(12, 11, 10, 1.0, seed=3)
+    L, U = oracle.ilu0(A)
+    b = synth.rhs(A.n, 2, 4)
+    t = H.tune_default(schedule=sched)
+    pl = H.tri_analyze(oracle.to_f32(L), "lower", unit_diag=True, dtype="f32", tune=t)
+    pu = H.tri_analyze(oracle.to_f32(U), "upper", dtype="f32", tune=t)
+    ref32 = oracle.upper_solve_f32(oracle.to_f32(U), oracle.lower_solve_f32(oracle.to_f32(L), b, unit=True))
+    # FP32 vectors
+    y = solve(pl, b.astype(np.float32))
+    x = solve(pu, y, upper=True)
+    assert x.dtype == np.float32
+    assert relerr(x.astype(np.float64), ref32.astype(np.float64)) <= 1e-5
+    # FP64 vectors with an FP32 plan: converted on load and store
+    y64 = solve(pl, b)
+    assert y64.dtype == np.float64
+    assert relerr(y64, oracle.lower_solve(L, b, unit=True)) <= 1e-5
+
+
+def test_empty_and_single_row():
+    for n in (0, 1):
+        T = CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.full(n, 2.0))
+        for s in SCHEDS:
+            p = H.tri_analyze(T, "lower", tune=H.tune_default(schedule=s))
+            if n:
+                assert np.array_equal(solve(p, np.array([3.0])), np.array([1.5]))
+
+
+def test_diagonal_and_bidiagonal_closed_forms():
+    n = 4097
+    D = CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.full(n, 4.0))
+    p = H.tri_analyze(D, "lower")
+    assert H.tri_plan_info(p)[0] == 1
+    b = synth.rhs(n, 1, 9)[:, 0]
+    assert np.array_equal(solve(p, b), b / 4.0)
+    # unit lower bidiagonal, -1 below: x_i = i (1-based) for b = 1, n levels
+    rp = np.concatenate([[0], np.arange(1, 2 * n, 2)]).astype(np.int32)
+    ci = np.concatenate([[0]] + [[i - 1, i] for i in range(1, n)]).astype(np.int32)
+    v = np.concatenate([[1.0]] + [[-1.0, 1.0] for _ in range(1, n)])
+    B = CSR(n, rp, ci, v)
+    for s in SCHEDS:
+        p = H.tri_analyze(B, "lower", tune=H.tune_default(schedule=s))
+        assert H.tri_plan_info(p)[0] == n
+        assert np.array_equal(solve(p, np.ones(n)), np.arange(1, n + 1, dtype=float))
+
+
+def test_in_place_solve():
+    L = synth.random_lower(1500, 0.003, seed=8)
+    b = synth.rhs(L.n, 1, 9)[:, 0]
+    p = H.tri_analyze(L, "lower", tune=H.tune_default(schedule="owner_persistent"))
+    bt = dev(b)
+    H.tri_solve_lower(p, bt, bt)
+    torch.cuda.synchronize()
+    assert relerr(bt.cpu().numpy(), oracle.lower_solve(L, b)) <= FP64_TOL
