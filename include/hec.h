@@ -88,6 +88,8 @@ typedef struct hec_tune {
     int32_t host_only;      /* 1 = build the host plan only (no device upload) */
     int32_t max_nrhs;       /* workspace is allocated for up to this many RHS (grows on demand) */
     int32_t block_threads;  /* threads per workgroup (64..1024, multiple of 64) */
+    int32_t chunk_rows;     /* owner schedule: rows of matrix data staged in LDS per chunk
+                               (a multiple of block_threads, at most 4x; 0 = 2x) */
 } hec_tune_t;
 
 /* Per-RHS outcome of krylov_solve. */
@@ -101,10 +103,11 @@ typedef struct hec_krylov_info {
 
 /* Statistics of a triangular plan. */
 typedef struct tri_stats {
-    int32_t n, nlev, ell_width, ld, num_groups, nsteps, nwaits, schedule;
+    int32_t n, nlev, ell_width, ld, num_groups, nsteps, nexport, schedule;
     int64_t nnz_offdiag;     /* stored off-diagonal entries */
     int64_t nnz_tail;        /* off-diagonals in the CSR remainder */
-    int64_t lds_bytes;       /* LDS per workgroup used by the persistent kernel */
+    int64_t lds_rows;        /* largest per-workgroup LDS window, in rows */
+    int64_t nremote;         /* dependency entries read across workgroups */
     int32_t unit_diag, dtype;
 } tri_stats_t;
 

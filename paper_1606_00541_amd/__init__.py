@@ -45,7 +45,7 @@ class HecError(RuntimeError):
 class Tune(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int32) for f in (
         "ell_width", "schedule", "num_groups", "merge_rows", "group_lanes", "long_row", "part_rows",
-        "host_only", "max_nrhs", "block_threads")]
+        "host_only", "max_nrhs", "block_threads", "chunk_rows")]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -58,9 +58,9 @@ class KrylovInfo(ctypes.Structure):
 
 class TriStats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int32) for f in (
-        "n", "nlev", "ell_width", "ld", "num_groups", "nsteps", "nwaits", "schedule")] + [
-        ("nnz_offdiag", ctypes.c_int64), ("nnz_tail", ctypes.c_int64), ("lds_bytes", ctypes.c_int64),
-        ("unit_diag", ctypes.c_int32), ("dtype", ctypes.c_int32)]
+        "n", "nlev", "ell_width", "ld", "num_groups", "nsteps", "nexport", "schedule")] + [
+        ("nnz_offdiag", ctypes.c_int64), ("nnz_tail", ctypes.c_int64), ("lds_rows", ctypes.c_int64),
+        ("nremote", ctypes.c_int64), ("unit_diag", ctypes.c_int32), ("dtype", ctypes.c_int32)]
 
 
 class Precond(ctypes.Structure):

@@ -27,6 +27,7 @@ Tune tune_from(const hec_tune_t *t)
     u.host_only = t->host_only;
     u.max_nrhs = t->max_nrhs > 0 ? t->max_nrhs : 1;
     u.block_threads = t->block_threads > 0 ? t->block_threads : 256;
+    u.chunk_rows = t->chunk_rows > 0 ? t->chunk_rows : 2 * u.block_threads;
     if (u.schedule < HEC_SCHED_AUTO || u.schedule > HEC_SCHED_OWNER_PERSISTENT)
         fail(HEC_ERR_INVALID_ARG, "tune.schedule out of range");
     if (u.block_threads % 64 != 0 || u.block_threads > 1024)
@@ -37,6 +38,8 @@ Tune tune_from(const hec_tune_t *t)
     if (u.ell_width < -1 || u.ell_width > 64) fail(HEC_ERR_INVALID_ARG, "tune.ell_width out of range");
     if (u.num_groups < 0 || u.merge_rows < 0 || u.long_row < 0 || u.part_rows < 0)
         fail(HEC_ERR_INVALID_ARG, "negative tuning value");
+    if (u.chunk_rows % u.block_threads != 0 || u.chunk_rows > 4 * u.block_threads)
+        fail(HEC_ERR_INVALID_ARG, "tune.chunk_rows must be 1, 2 or 4 times block_threads");
     return u;
 }
 
@@ -201,7 +204,7 @@ namespace {
 // Fill step structures from a device-row order in which every group's rows
 // are contiguous per step.  `runs` lists, per group, the (begin, end) device
 // row ranges of its steps in execution order.
-void finish_schedule(Schedule &s, const ExecHost &ex, const std::vector<std::vector<std::pair<int32_t, int32_t>>> &runs,
+void finish_schedule(Schedule &s, ExecHost &ex, const std::vector<std::vector<std::pair<int32_t, int32_t>>> &runs,
                      const Tune &tune)
 {
     const int32_t G = (int32_t)runs.size();
@@ -232,39 +235,62 @@ void finish_schedule(Schedule &s, const ExecHost &ex, const std::vector<std::vec
             if (mx + ex.w >= long_row) s.step_lanes[sid] = lanes;
         }
     }
-    // waits: for every cross-group dependency, the producer group's completed
-    // step count that covers the producing row
-    s.wait_ptr.assign((size_t)S + 1, 0);
-    s.waits.clear();
-    std::vector<int32_t> need(G, 0), touched;
-    touched.reserve(64);
-    auto dep = [&](int32_t g, int32_t sid, int32_t c) {
+    // exported rows: produced by one group, read by another.  Check that
+    // every same-group dependency comes from an earlier step, count the
+    // cross-group reads, then give exported rows mailbox slots group by group
+    // and re-encode cross-group columns as n + 1 + slot.
+    std::vector<char> exported(ex.n, 0);
+    s.remote_reads = 0;
+    auto scan = [&](int32_t g, int32_t sid, int32_t c) {
         if (c >= ex.n) return;  // ELL padding
-        int32_t ps = step_of[c];
-        int32_t h = ex.owner[c];
-        if (h == g) {
-            if (ps >= sid) fail(HEC_ERR_INVALID_ARG, "internal: dependency not ordered by the schedule");
+        if (ex.owner[c] == g) {
+            if (step_of[c] >= sid) fail(HEC_ERR_INVALID_ARG, "internal: dependency not ordered by the schedule");
             return;
         }
-        int32_t cnt = ps - s.step_ptr[h] + 1;
-        if (need[h] == 0) touched.push_back(h);
-        need[h] = std::max(need[h], cnt);
+        exported[c] = 1;
+        s.remote_reads += 1;
     };
-    for (int32_t g = 0; g < G; ++g) {
-        for (int32_t sid = s.step_ptr[g]; sid < s.step_ptr[g + 1]; ++sid) {
+    for (int32_t g = 0; g < G; ++g)
+        for (int32_t sid = s.step_ptr[g]; sid < s.step_ptr[g + 1]; ++sid)
             for (int32_t x = s.step_row[2 * sid]; x < s.step_row[2 * sid + 1]; ++x) {
-                for (int32_t e = 0; e < ex.w; ++e) dep(g, sid, ex.ell_col[(size_t)e * ex.ld + x]);
+                for (int32_t e = 0; e < ex.w; ++e) scan(g, sid, ex.ell_col[(size_t)e * ex.ld + x]);
                 if (!ex.tail_ptr.empty())
-                    for (int32_t p = ex.tail_ptr[x]; p < ex.tail_ptr[x + 1]; ++p) dep(g, sid, ex.tail_col[p]);
+                    for (int32_t p = ex.tail_ptr[x]; p < ex.tail_ptr[x + 1]; ++p) scan(g, sid, ex.tail_col[p]);
             }
-            std::sort(touched.begin(), touched.end());
-            for (int32_t h : touched) {
-                s.waits.push_back(h);
-                s.waits.push_back(need[h]);
-                need[h] = 0;
+    s.exp_slot.assign(ex.n, -1);
+    s.exp_ptr.assign((size_t)G + 1, 0);
+    int32_t slot = 0;
+    for (int32_t g = 0; g < G; ++g) {
+        for (int32_t sid = s.step_ptr[g]; sid < s.step_ptr[g + 1]; ++sid)
+            for (int32_t x = s.step_row[2 * sid]; x < s.step_row[2 * sid + 1]; ++x)
+                if (exported[x]) s.exp_slot[x] = slot++;
+        s.exp_ptr[g + 1] = slot;
+    }
+    s.nexp = slot;
+    auto encode = [&](int32_t x, int32_t &c) {
+        if (c < ex.n && ex.owner[c] != ex.owner[x]) c = ex.n + 1 + s.exp_slot[c];
+    };
+    for (int32_t x = 0; x < ex.n; ++x) {
+        for (int32_t e = 0; e < ex.w; ++e) encode(x, ex.ell_col[(size_t)e * ex.ld + x]);
+        if (!ex.tail_ptr.empty())
+            for (int32_t p = ex.tail_ptr[x]; p < ex.tail_ptr[x + 1]; ++p) encode(x, ex.tail_col[p]);
+    }
+    // chunks (owner schedule): consecutive steps of a group holding at most
+    // chunk_rows rows together (steps were cut to fit beforehand)
+    s.chunk_ptr.assign((size_t)G + 1, 0);
+    s.chunk_step.clear();
+    if (s.kind == HEC_SCHED_OWNER_PERSISTENT) {
+        s.chunk_rows = tune.chunk_rows;
+        for (int32_t g = 0; g < G; ++g) {
+            int32_t sid = s.step_ptr[g];
+            while (sid < s.step_ptr[g + 1]) {
+                const int32_t first = sid, r0 = s.step_row[2 * sid];
+                while (sid < s.step_ptr[g + 1] && s.step_row[2 * sid + 1] - r0 <= s.chunk_rows) ++sid;
+                if (sid == first) fail(HEC_ERR_INVALID_ARG, "internal: step larger than a chunk");
+                s.chunk_step.push_back(first);
+                s.chunk_step.push_back(sid);
             }
-            touched.clear();
-            s.wait_ptr[sid + 1] = (int32_t)(s.waits.size() / 2);
+            s.chunk_ptr[g + 1] = (int32_t)(s.chunk_step.size() / 2);
         }
     }
     // LDS windows: a group's contiguous device-row span (owner schedule only)
@@ -413,6 +439,17 @@ void build_exec(TriHost &t, const Csr &a, const Tune &tune, const DeviceShape &d
     // 3. schedule
     ex.sched = Schedule();
     ex.sched.kind = kind;
+    if (kind == HEC_SCHED_OWNER_PERSISTENT) {
+        // a step never exceeds one chunk: cut longer levels into pieces (rows
+        // of one level are independent, so the extra barrier is harmless)
+        for (auto &gr : runs) {
+            std::vector<std::pair<int32_t, int32_t>> cut;
+            for (auto &r : gr)
+                for (int32_t b = r.first; b < r.second; b += tune.chunk_rows)
+                    cut.push_back({b, std::min(r.second, b + tune.chunk_rows)});
+            gr.swap(cut);
+        }
+    }
     if (kind != HEC_SCHED_LEVEL_LAUNCH) finish_schedule(ex.sched, ex, runs, tune);
 }
 

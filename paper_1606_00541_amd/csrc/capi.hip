@@ -64,6 +64,13 @@ void ensure_workspace(DevTri &d, int32_t R)
 {
     if (R <= d.ws_R) return;
     d.xw.alloc(((size_t)d.n + 1) * R * vsize(d.dt));
+    if (d.nexp > 0) {
+        // both halves start empty; the stride stays the allocated width so
+        // that every launch resets exactly what any later launch may read
+        const size_t cnt = 2 * (size_t)d.nexp * R;
+        d.mbox.alloc(cnt * vsize(d.dt));
+        fill_sentinel(d.mbox.p, cnt, d.dt);
+    }
     d.ws_R = R;
 }
 
@@ -96,13 +103,14 @@ void upload_tri(DevTri &d, const TriHost &t, int32_t max_nrhs)
         upload(d.step_ptr, s.step_ptr);
         upload(d.step_row, s.step_row);
         upload(d.step_lanes, s.step_lanes);
-        upload(d.wait_ptr, s.wait_ptr);
-        std::vector<int32_t> w = s.waits;
-        if (w.empty()) w.assign(2, 0);
-        upload(d.waits, w);
         upload(d.window, s.window);
-        d.progress.alloc(sizeof(unsigned long long) * std::max(1, d.groups));
-        hip_check(hipMemset(d.progress.p, 0, d.progress.bytes), "hipMemset");
+        d.nexp = s.nexp;
+        upload(d.exp_slot, s.exp_slot);
+        upload(d.exp_ptr, s.exp_ptr);
+        upload(d.chunk_ptr, s.chunk_ptr);
+        upload(d.chunk_step, s.chunk_step);
+        d.chunk_rows = s.chunk_rows;
+        d.max_lanes_one = std::all_of(s.step_lanes.begin(), s.step_lanes.end(), [](int32_t v) { return v == 1; });
         d.epoch.alloc(2 * sizeof(unsigned int));
         hip_check(hipMemset(d.epoch.p, 0, d.epoch.bytes), "hipMemset");
     }
@@ -388,10 +396,11 @@ hec_status_t tri_plan_stats(tri_plan_t p, tri_stats_t *s)
         s->schedule = h.ex.sched.kind;
         s->num_groups = h.ex.sched.groups;
         s->nsteps = h.ex.sched.nsteps();
-        s->nwaits = (int32_t)h.ex.sched.nwaits();
+        s->nexport = h.ex.sched.nexp;
+        s->nremote = h.ex.sched.remote_reads;
         s->nnz_offdiag = h.nnz_off;
         s->nnz_tail = h.nnz_tail;
-        s->lds_bytes = (int64_t)h.ex.sched.max_window * (h.dt == HEC_F64 ? 8 : 4);
+        s->lds_rows = h.ex.sched.max_window;
         s->unit_diag = h.unit ? 1 : 0;
         s->dtype = h.dt;
     });

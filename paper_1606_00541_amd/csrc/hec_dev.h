@@ -74,6 +74,12 @@ template <typename T> void upload(DevMem &m, const std::vector<T> &v)
 // Upload doubles converted to the plan's value type.
 void upload_values(DevMem &m, const std::vector<double> &v, hec_dtype_t dt);
 
+// Mailbox sentinels: NaN bit patterns arithmetic never produces (computed
+// NaNs are the canonical quiet NaN).  A slot holding the sentinel has not
+// received its value yet.
+constexpr unsigned long long kSentinel64 = 0x7FF4DEADBEEF0001ull;
+constexpr unsigned int kSentinel32 = 0x7FA0BEEFu;
+
 // Kernel arguments of one triangular solve launch (passed by value).
 struct TriArgs {
     int32_t n, w, ld, R;
@@ -82,18 +88,23 @@ struct TriArgs {
     const int32_t *tail_ptr, *tail_col;
     const void *tail_val;
     const void *dinv;
-    const int32_t *step_ptr, *step_row, *step_lanes, *wait_ptr, *waits, *window;
-    unsigned long long *progress;
+    const int32_t *step_ptr, *step_row, *step_lanes, *window;
+    const int32_t *exp_slot, *exp_ptr;
+    const int32_t *chunk_ptr, *chunk_step;  // owner schedule: LDS-staged chunks
+    int32_t chunk_rows;
+    int32_t in_f64, out_f64;                // vector types of bin / xout
+    void *mbox;          // [2][nexp][mbox_stride] values crossing workgroups
+    int32_t nexp, mbox_stride;
     unsigned int *epoch;
-    int *err_dev;       // device-side abort flag
-    int *err_host;      // host-mapped copy, read by the host without a sync
-    const void *bin;    // right-hand side, indexed bin[gather[x]*R + k]
+    int *err_dev;        // device-side abort flag
+    int *err_host;       // host-mapped copy, read by the host without a sync
+    const void *bin;     // right-hand side, indexed bin[gather[x]*R + k]
     const int32_t *gather;
-    void *xw;           // device-order solution [n][R] (plan value type)
-    void *xout;         // optional scatter target xout[scatter[x]*R + k]
+    void *xw;            // device-order solution [n][R] (plan value type)
+    void *xout;          // optional scatter target xout[scatter[x]*R + k]
     const int32_t *scatter;
     int32_t row_begin, row_end;  // level-launch row range
-    int32_t use_lds;
+    int32_t write_xw;            // persistent: also store every row to xw
 };
 
 // Device copy of one triangular plan.
@@ -102,11 +113,13 @@ struct DevTri {
     int32_t n = 0, w = 0, ld = 0, nlev = 0;
     hec_dtype_t dt = HEC_F64;
     int32_t kind = HEC_SCHED_LEVEL_PERSISTENT;
-    int32_t groups = 0, block = 256, max_window = 0;
+    int32_t groups = 0, block = 256, max_window = 0, nexp = 0;
     bool unit = false, has_tail = false;
     DevMem ell_col, ell_val, tail_ptr, tail_col, tail_val, dinv, orig;
-    DevMem step_ptr, step_row, step_lanes, wait_ptr, waits, window;
-    DevMem progress, epoch, err;
+    DevMem step_ptr, step_row, step_lanes, window, exp_slot, exp_ptr, chunk_ptr, chunk_step;
+    int32_t chunk_rows = 0;
+    bool max_lanes_one = true;     // every step runs one thread per (row, rhs)
+    DevMem epoch, err, mbox;
     int *err_host = nullptr;      // pinned, device-visible
     std::vector<int32_t> levelptr;  // level-launch bounds (host)
     DevMem xw;                      // workspace [n][ws_R]
@@ -114,6 +127,8 @@ struct DevTri {
     ~DevTri();
 };
 
+// Fill `count` values of type dt with the mailbox sentinel (synchronous).
+void fill_sentinel(void *p, size_t count, hec_dtype_t dt);
 void upload_tri(DevTri &d, const TriHost &t, int32_t max_nrhs);
 void ensure_workspace(DevTri &d, int32_t R);
 // Largest number of co-resident workgroups of the persistent kernel for the

@@ -50,25 +50,35 @@ struct HecHost {
 };
 
 // A schedule for the persistent executor: every workgroup runs its steps in
-// order; a step is a contiguous range of device rows preceded by waits on other
-// workgroups' progress counters.
+// order; a step is a contiguous range of device rows (rows of one level, or a
+// chunk of one).  Rows read by a workgroup other than their owner are
+// "exported": their values also travel through a double-buffered mailbox
+// whose slots consumers poll until the value has arrived.
 struct Schedule {
     int32_t kind = HEC_SCHED_LEVEL_PERSISTENT;
     int32_t groups = 0;
     std::vector<int32_t> step_ptr;   // [groups+1]
     std::vector<int32_t> step_row;   // [2*nsteps]: begin, end (device rows)
     std::vector<int32_t> step_lanes; // [nsteps]: lanes cooperating per row (1 = thread per row)
-    std::vector<int32_t> wait_ptr;   // [nsteps+1]
-    std::vector<int32_t> waits;      // [2*nwaits]: group, required completed steps
     std::vector<int32_t> window;     // [2*groups]: LDS window (device rows lo, hi)
     int32_t max_window = 0;          // largest window (rows)
-    int64_t nwaits() const { return (int64_t)waits.size() / 2; }
+    int32_t nexp = 0;                // exported rows
+    std::vector<int32_t> exp_slot;   // [n]: device row -> mailbox slot, or -1
+    std::vector<int32_t> exp_ptr;    // [groups+1]: mailbox slots of each group (contiguous)
+    int64_t remote_reads = 0;        // dependency entries that cross workgroups
+    // owner schedule: each group's steps are cut into chunks of at most
+    // chunk_rows rows whose matrix data is staged in LDS one chunk ahead
+    int32_t chunk_rows = 0;
+    std::vector<int32_t> chunk_ptr;  // [groups+1] into chunk_step
+    std::vector<int32_t> chunk_step; // [2*nchunks]: first step, end step
     int32_t nsteps() const { return (int32_t)step_lanes.size(); }
 };
 
 // Device-order (execution) layout of one triangle: rows permuted into the
 // schedule's order, ELL/CSR columns renumbered to device rows, the diagonal
-// split into its own dense array (stored as its reciprocal).
+// split into its own dense array (stored as its reciprocal).  Under a
+// persistent schedule a column c > n names mailbox slot c - n - 1 (a value
+// produced by another workgroup); c == n is ELL padding.
 struct ExecHost {
     int32_t n = 0, w = 0, ld = 0;
     std::vector<int32_t> xord;   // device row -> level-order row
@@ -105,6 +115,7 @@ struct Tune {
     int32_t host_only = 0;
     int32_t max_nrhs = 1;
     int32_t block_threads = 256;
+    int32_t chunk_rows = 0;
 };
 Tune tune_from(const hec_tune_t *t);
 

@@ -10,10 +10,12 @@
 // Two executions of the same row routine:
 //   k_level       one launch per level (the paper's shape);
 //   k_persistent  one launch for the whole solve: every workgroup runs its
-//                 list of steps (a contiguous range of device rows), waiting
-//                 before a step on the progress counters of the workgroups
-//                 that produce its inputs.  Under the owner schedule the
-//                 workgroup's own solution values also live in LDS.
+//                 list of steps (a contiguous range of device rows of one
+//                 level).  A dependency produced by the same workgroup is
+//                 read from LDS (owner schedule) or from the workspace after
+//                 the step barrier; a dependency produced by another
+//                 workgroup is read from a mailbox slot, polled until the
+//                 producer's value replaces the sentinel.
 // The row routine subtracts the ELL terms in slot order, then the CSR-tail
 // terms, then multiplies by the stored reciprocal diagonal, so both
 // executions produce bit-identical results for rows run one thread per
@@ -33,61 +35,104 @@ constexpr unsigned kSpinLimit = 1u << 22;  // polls before a wait is declared hu
 
 int32_t capacity_of(const void *kern, int32_t block, size_t lds);
 
-// Solution values that other workgroups of a persistent launch may read are
-// written and read as agent-scope relaxed atomics: the stores go through to
-// the point of coherence shared by all XCDs and the loads do not hit stale
-// cache lines, so no cache-wide writeback or invalidate is needed.  A
-// producer waits for its stores to complete before it bumps its progress
-// counter; a consumer reads the values only after it saw the counter.  The
-// per-level launch (COH = false) relies on kernel boundaries instead.
-template <typename T, bool COH>
-__device__ __forceinline__ T gload(const T *p)
+template <typename T> __device__ __forceinline__ T sentinel();
+template <> __device__ __forceinline__ double sentinel<double>() { return __longlong_as_double((long long)kSentinel64); }
+template <> __device__ __forceinline__ float sentinel<float>() { return __uint_as_float(kSentinel32); }
+__device__ __forceinline__ bool is_sentinel(double v) { return __double_as_longlong(v) == (long long)kSentinel64; }
+__device__ __forceinline__ bool is_sentinel(float v) { return __float_as_uint(v) == kSentinel32; }
+
+// Per-launch state of the persistent kernel shared by the row routine.
+template <typename T> struct Ctx {
+    T *xl;          // LDS window (device rows lo..hi-1), holds b then x
+    int lo, hi;
+    T *mbox_rd;     // this launch's mailbox half
+    int *abort;     // LDS flag: a poll gave up
+};
+
+// Mailbox slots are written with agent-scope relaxed atomic stores, which go
+// through to the point of coherence shared by all XCDs, and polled with
+// agent-scope relaxed atomic loads, which do not hit stale cache lines.  The
+// value itself is the signal, so no flag, fence or cache-wide writeback is
+// needed.  The poll is bounded; on expiry it raises the abort flags.
+template <typename T>
+__device__ __forceinline__ T poll_slot(const T *p, int *err_dev, int *err_host, int *abort)
 {
-    if (COH) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    T v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!is_sentinel(v)) return v;
+    unsigned spins = 0;
+    for (;;) {
+        __builtin_amdgcn_s_sleep(1);
+        v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!is_sentinel(v)) return v;
+        ++spins;
+        if ((spins & 255u) == 0 &&
+            (spins > kSpinLimit || __hip_atomic_load(err_dev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+            __hip_atomic_store(err_dev, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(err_host, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            *abort = 1;
+            return T(0);
+        }
+    }
+}
+
+// Value of dependency column c for right-hand side k.
+template <typename T, bool PERS, bool LDS>
+__device__ __forceinline__ T dep_value(const TriArgs &a, const Ctx<T> &cx, int c, int k)
+{
+    if (PERS && c > a.n)
+        return poll_slot<T>(cx.mbox_rd + (size_t)(c - a.n - 1) * a.mbox_stride + k, a.err_dev, a.err_host,
+                            cx.abort);
+    if (LDS && c >= cx.lo && c < cx.hi) return cx.xl[(c - cx.lo) * a.R + k];
+    const T *p = static_cast<const T *>(a.xw) + (size_t)c * a.R + k;
+    // a value of this workgroup from an earlier step (persistent) or of an
+    // earlier launch (per-level): workgroup-scope coherence suffices
+    if (PERS) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     return *p;
 }
 
-template <typename T, bool COH>
-__device__ __forceinline__ void gstore(T *p, T v)
+template <typename T, typename TIn, bool LDS>
+__device__ __forceinline__ T rhs_value(const TriArgs &a, const Ctx<T> &cx, int x, int k)
 {
-    if (COH) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    else *p = v;
-}
-
-template <typename T, bool LDS, bool COH>
-__device__ __forceinline__ T load_x(const TriArgs &a, const T *xw, const T *xl, int lo, int hi, int c, int k)
-{
-    if (LDS && c >= lo && c < hi) return xl[(c - lo) * a.R + k];
-    return gload<T, COH>(xw + (size_t)c * a.R + k);
+    if (LDS) return cx.xl[(x - cx.lo) * a.R + k];  // gathered at kernel start
+    return static_cast<T>(static_cast<const TIn *>(a.bin)[(size_t)a.gather[x] * a.R + k]);
 }
 
 // Partial sum of one row's off-diagonal terms (lane `lane` of `lanes`).
-template <typename T, bool LDS, bool COH>
-__device__ __forceinline__ T row_terms(const TriArgs &a, int x, int k, int lane, int lanes, const T *xl, int lo,
-                                       int hi)
+template <typename T, bool PERS, bool LDS>
+__device__ __forceinline__ T row_terms(const TriArgs &a, const Ctx<T> &cx, int x, int k, int lane, int lanes)
 {
     const T *ev = static_cast<const T *>(a.ell_val);
-    const T *xw = static_cast<const T *>(a.xw);
     T part = T(0);
     for (int e = lane; e < a.w; e += lanes) {
         const int c = a.ell_col[(size_t)e * a.ld + x];
         const T v = ev[(size_t)e * a.ld + x];
-        if (c < a.n) part += v * load_x<T, LDS, COH>(a, xw, xl, lo, hi, c, k);
+        if (c != a.n) part += v * dep_value<T, PERS, LDS>(a, cx, c, k);
     }
     if (a.tail_ptr) {
         const T *tv = static_cast<const T *>(a.tail_val);
         for (int p = a.tail_ptr[x] + lane; p < a.tail_ptr[x + 1]; p += lanes)
-            part += tv[p] * load_x<T, LDS, COH>(a, xw, xl, lo, hi, a.tail_col[p], k);
+            part += tv[p] * dep_value<T, PERS, LDS>(a, cx, a.tail_col[p], k);
     }
     return part;
 }
 
-template <typename T, typename TOut, bool LDS, bool COH>
-__device__ __forceinline__ void finish_row(const TriArgs &a, int x, int k, T s, T *xl, int lo, int hi)
+template <typename T, typename TOut, bool PERS, bool LDS>
+__device__ __forceinline__ void finish_row(const TriArgs &a, const Ctx<T> &cx, int x, int k, T s)
 {
     if (a.dinv) s *= static_cast<const T *>(a.dinv)[x];
-    gstore<T, COH>(static_cast<T *>(a.xw) + (size_t)x * a.R + k, s);
-    if (LDS && x >= lo && x < hi) xl[(x - lo) * a.R + k] = s;
+    if (LDS) cx.xl[(x - cx.lo) * a.R + k] = s;
+    if (!PERS) {
+        static_cast<T *>(a.xw)[(size_t)x * a.R + k] = s;
+    } else if (!LDS || a.write_xw) {
+        __hip_atomic_store(static_cast<T *>(a.xw) + (size_t)x * a.R + k, s, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    if (PERS) {
+        const int slot = a.exp_slot[x];
+        if (slot >= 0)
+            __hip_atomic_store(cx.mbox_rd + (size_t)slot * a.mbox_stride + k, s, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
     if (a.xout) {
         const int dst = a.scatter[x];
         if (dst >= 0) static_cast<TOut *>(a.xout)[(size_t)dst * a.R + k] = static_cast<TOut>(s);
@@ -95,37 +140,36 @@ __device__ __forceinline__ void finish_row(const TriArgs &a, int x, int k, T s, 
 }
 
 // Thread-per-(row, rhs) solve of one row: s = b - sum, in slot order.
-template <typename T, typename TIn, typename TOut, bool LDS, bool COH>
-__device__ __forceinline__ void solve_item(const TriArgs &a, int x, int k, T *xl, int lo, int hi)
+template <typename T, typename TIn, typename TOut, bool PERS, bool LDS>
+__device__ __forceinline__ void solve_item(const TriArgs &a, const Ctx<T> &cx, int x, int k)
 {
     const T *ev = static_cast<const T *>(a.ell_val);
-    const T *xw = static_cast<const T *>(a.xw);
-    T s = static_cast<T>(static_cast<const TIn *>(a.bin)[(size_t)a.gather[x] * a.R + k]);
+    T s = rhs_value<T, TIn, LDS>(a, cx, x, k);
     for (int e = 0; e < a.w; ++e) {
         const int c = a.ell_col[(size_t)e * a.ld + x];
         const T v = ev[(size_t)e * a.ld + x];
-        if (c < a.n) s -= v * load_x<T, LDS, COH>(a, xw, xl, lo, hi, c, k);
+        if (c != a.n) s -= v * dep_value<T, PERS, LDS>(a, cx, c, k);
     }
     if (a.tail_ptr) {
         const T *tv = static_cast<const T *>(a.tail_val);
         for (int p = a.tail_ptr[x]; p < a.tail_ptr[x + 1]; ++p)
-            s -= tv[p] * load_x<T, LDS, COH>(a, xw, xl, lo, hi, a.tail_col[p], k);
+            s -= tv[p] * dep_value<T, PERS, LDS>(a, cx, a.tail_col[p], k);
     }
-    finish_row<T, TOut, LDS, COH>(a, x, k, s, xl, lo, hi);
+    finish_row<T, TOut, PERS, LDS>(a, cx, x, k, s);
 }
 
 // Rows [rb, re) x R right-hand sides, `lanes` lanes per (row, rhs).  With
 // lanes > 1 the lanes of a group split the row's terms and combine them with
 // a butterfly of cross-lane shuffles inside the wavefront.
-template <typename T, typename TIn, typename TOut, bool LDS, bool COH>
-__device__ __forceinline__ void solve_range(const TriArgs &a, int rb, int re, int lanes, T *xl, int lo, int hi)
+template <typename T, typename TIn, typename TOut, bool LDS>
+__device__ __forceinline__ void solve_range(const TriArgs &a, const Ctx<T> &cx, int rb, int re, int lanes)
 {
     const int R = a.R;
     if (lanes == 1) {
         const int items = (re - rb) * R;
         for (int t = threadIdx.x; t < items; t += blockDim.x) {
             const int q = t / R;
-            solve_item<T, TIn, TOut, LDS, COH>(a, rb + q, t - q * R, xl, lo, hi);
+            solve_item<T, TIn, TOut, true, LDS>(a, cx, rb + q, t - q * R);
         }
         return;
     }
@@ -136,12 +180,9 @@ __device__ __forceinline__ void solve_range(const TriArgs &a, int rb, int re, in
         const int lane = t & (lanes - 1);
         const int q = t / lanes;
         const int x = rb + q / R, k = q - (q / R) * R;
-        T part = act ? row_terms<T, LDS, COH>(a, x, k, lane, lanes, xl, lo, hi) : T(0);
+        T part = act ? row_terms<T, true, LDS>(a, cx, x, k, lane, lanes) : T(0);
         for (int off = lanes >> 1; off > 0; off >>= 1) part += __shfl_xor(part, off, lanes);
-        if (act && lane == 0) {
-            T s = static_cast<T>(static_cast<const TIn *>(a.bin)[(size_t)a.gather[x] * R + k]) - part;
-            finish_row<T, TOut, LDS, COH>(a, x, k, s, xl, lo, hi);
-        }
+        if (act && lane == 0) finish_row<T, TOut, true, LDS>(a, cx, x, k, rhs_value<T, TIn, LDS>(a, cx, x, k) - part);
     }
 }
 
@@ -153,18 +194,19 @@ __global__ void __launch_bounds__(256) k_level(TriArgs a)
     const int items = (a.row_end - a.row_begin) * a.R;
     if (t >= items) return;
     const int q = t / a.R;
-    solve_item<T, TIn, TOut, false, false>(a, a.row_begin + q, t - q * a.R, nullptr, 0, 0);
+    Ctx<T> cx{nullptr, 0, 0, nullptr, nullptr};
+    solve_item<T, TIn, TOut, false, false>(a, cx, a.row_begin + q, t - q * a.R);
 }
 
-// One launch for the whole solve (see the file comment).  The progress
-// counter of workgroup g holds (epoch << 32) | completed steps; the epoch is
-// read at kernel start and advanced by the last workgroup to finish, so the
-// counters never need clearing between launches (also under graph replay).
+// One launch for the whole solve.  The mailbox half used by a launch is the
+// parity of the plan's epoch word; the epoch is read at kernel start and
+// advanced by the last workgroup to finish, so consecutive launches (also
+// graph replays) alternate halves.  Each workgroup first resets its own slots
+// of the other half to the sentinel, ready for the next launch.
 template <typename T, typename TIn, typename TOut, bool LDS>
 __global__ void __launch_bounds__(1024) k_persistent(TriArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    T *xl = reinterpret_cast<T *>(smem);
     __shared__ unsigned s_epoch;
     __shared__ int s_abort;
     const int g = blockIdx.x;
@@ -173,44 +215,50 @@ __global__ void __launch_bounds__(1024) k_persistent(TriArgs a)
         s_abort = 0;
     }
     __syncthreads();
-    const unsigned long long base = (unsigned long long)s_epoch << 32;
-    int lo = 0, hi = 0;
+    const unsigned par = s_epoch & 1u;
+    T *mbox = static_cast<T *>(a.mbox);
+    const size_t half = (size_t)a.nexp * a.mbox_stride;
+    Ctx<T> cx;
+    cx.xl = reinterpret_cast<T *>(smem);
+    cx.lo = LDS ? a.window[2 * g] : 0;
+    cx.hi = LDS ? a.window[2 * g + 1] : 0;
+    cx.mbox_rd = mbox + (par ? half : 0);
+    cx.abort = &s_abort;
+    if (a.nexp > 0) {
+        T *other = mbox + (par ? 0 : half);
+        const size_t e0 = (size_t)a.exp_ptr[g] * a.mbox_stride, e1 = (size_t)a.exp_ptr[g + 1] * a.mbox_stride;
+        for (size_t i = e0 + threadIdx.x; i < e1; i += blockDim.x) other[i] = sentinel<T>();
+    }
     if (LDS) {
-        lo = a.window[2 * g];
-        hi = a.window[2 * g + 1];
+        const TIn *bin = static_cast<const TIn *>(a.bin);
+        const int items = (cx.hi - cx.lo) * a.R;
+        for (int t = threadIdx.x; t < items; t += blockDim.x) {
+            const int q = t / a.R, k = t - q * a.R;
+            cx.xl[t] = static_cast<T>(bin[(size_t)a.gather[cx.lo + q] * a.R + k]);
+        }
+        __syncthreads();
     }
     const int s0 = a.step_ptr[g], s1 = a.step_ptr[g + 1];
+    int rb = 0, re = 0, ln = 1;
+    if (s0 < s1) {
+        rb = a.step_row[2 * s0];
+        re = a.step_row[2 * s0 + 1];
+        ln = a.step_lanes[s0];
+    }
     for (int s = s0; s < s1; ++s) {
-        const int wb = a.wait_ptr[s], we = a.wait_ptr[s + 1];
-        if (we > wb) {
-            for (int q = wb + (int)threadIdx.x; q < we; q += blockDim.x) {
-                const int h = a.waits[2 * q];
-                const unsigned long long need = base | (unsigned)a.waits[2 * q + 1];
-                unsigned spins = 0;
-                while (__hip_atomic_load(&a.progress[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-                    ++spins;
-                    if ((spins & 255u) == 0 &&
-                        (spins > kSpinLimit ||
-                         __hip_atomic_load(a.err_dev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
-                        __hip_atomic_store(a.err_dev, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        __hip_atomic_store(a.err_host, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-                        s_abort = 1;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                }
-            }
-            __syncthreads();
-            if (s_abort) break;
+        // next step's bounds are loaded while this step runs
+        int nrb = 0, nre = 0, nln = 1;
+        if (s + 1 < s1) {
+            nrb = a.step_row[2 * s + 2];
+            nre = a.step_row[2 * s + 3];
+            nln = a.step_lanes[s + 1];
         }
-        solve_range<T, TIn, TOut, LDS, true>(a, a.step_row[2 * s], a.step_row[2 * s + 1], a.step_lanes[s], xl, lo,
-                                             hi);
-        // every store of this step has completed before the counter moves
-        __builtin_amdgcn_s_waitcnt(0);
+        solve_range<T, TIn, TOut, LDS>(a, cx, rb, re, ln);
         __syncthreads();
-        if (threadIdx.x == 0)
-            __hip_atomic_store(&a.progress[g], base | (unsigned)(s - s0 + 1), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+        if (s_abort) break;
+        rb = nrb;
+        re = nre;
+        ln = nln;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -220,6 +268,233 @@ __global__ void __launch_bounds__(1024) k_persistent(TriArgs a)
             __hip_atomic_store(&a.epoch[0], s_epoch + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
+}
+
+// Owner-schedule kernel with LDS-staged matrix data.  Workgroup g owns the
+// device rows [lo, hi): their right-hand side is gathered into an LDS window
+// at kernel start and every solved value replaces its row's b there.  The
+// group's steps are cut into chunks of at most RPT * blockDim rows; the ELL
+// columns and values, reciprocal diagonal, mailbox slot and scatter target
+// of chunk q+1 are loaded into registers while chunk q is solved, then stored
+// to the other half of a double buffer in LDS, so a step reads everything but
+// cross-group values from LDS.  W is the ELL width; plans with a CSR tail,
+// W > 8 or cooperative lanes use k_persistent.
+template <typename T, int W, int RPT, bool UNIT>
+__global__ void __launch_bounds__(1024) k_owner(TriArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ unsigned s_epoch;
+    __shared__ int s_abort;
+    const int g = blockIdx.x;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int R = a.R, n = a.n;
+    if (tid == 0) {
+        s_epoch = __hip_atomic_load(a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_abort = 0;
+    }
+    __syncthreads();
+    const unsigned par = s_epoch & 1u;
+    T *mbox = static_cast<T *>(a.mbox);
+    const size_t half = (size_t)a.nexp * a.mbox_stride;
+    T *mrd = mbox + (par ? half : 0);
+    const int lo = a.window[2 * g], hi = a.window[2 * g + 1];
+    const int CH = RPT * nt;
+    // LDS: window [win*R] T, then two buffers of { vals[W][CH] T, dinv[CH] T, cols[W][CH], slot[CH], dst[CH] }
+    T *xl = reinterpret_cast<T *>(smem);
+    const size_t win_bytes = (((size_t)(hi - lo) * R * sizeof(T)) + 15) & ~(size_t)15;
+    const size_t buf_bytes = (size_t)CH * ((W + (UNIT ? 0 : 1)) * sizeof(T) + (W + 2) * sizeof(int));
+    auto bvals = [&](int b) { return reinterpret_cast<T *>(smem + win_bytes + b * buf_bytes); };
+    auto bdinv = [&](int b) { return bvals(b) + (size_t)W * CH; };
+    auto bcols = [&](int b) {
+        return reinterpret_cast<int *>(smem + win_bytes + b * buf_bytes + (size_t)CH * (W + (UNIT ? 0 : 1)) * sizeof(T));
+    };
+    auto bslot = [&](int b) { return bcols(b) + (size_t)W * CH; };
+    auto bdst = [&](int b) { return bslot(b) + CH; };
+
+    if (a.nexp > 0) {
+        T *other = mbox + (par ? 0 : half);
+        const size_t e0 = (size_t)a.exp_ptr[g] * a.mbox_stride, e1 = (size_t)a.exp_ptr[g + 1] * a.mbox_stride;
+        for (size_t i = e0 + tid; i < e1; i += nt) other[i] = sentinel<T>();
+    }
+    {
+        const int items = (hi - lo) * R;
+        for (int t = tid; t < items; t += nt) {
+            const int q = t / R, k = t - q * R;
+            const size_t src = (size_t)a.gather[lo + q] * R + k;
+            xl[t] = a.in_f64 ? static_cast<T>(static_cast<const double *>(a.bin)[src])
+                             : static_cast<T>(static_cast<const float *>(a.bin)[src]);
+        }
+    }
+    const T *ev = static_cast<const T *>(a.ell_val);
+    const T *dv = static_cast<const T *>(a.dinv);
+    // registers of one chunk prefetch
+    int rc[RPT][W];
+    T rv[RPT][W];
+    T rd[RPT];
+    int rs[RPT], rt[RPT];
+    auto chunk_rows = [&](int q, int &r0, int &r1) {
+        const int f = a.chunk_step[2 * q], e = a.chunk_step[2 * q + 1];
+        r0 = a.step_row[2 * f];
+        r1 = a.step_row[2 * (e - 1) + 1];
+    };
+    auto load_chunk = [&](int q) {
+        int r0, r1;
+        chunk_rows(q, r0, r1);
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            const int row = r0 + tid + i * nt;
+            if (row < r1) {
+#pragma unroll
+                for (int e = 0; e < W; ++e) {
+                    rc[i][e] = a.ell_col[(size_t)e * a.ld + row];
+                    rv[i][e] = ev[(size_t)e * a.ld + row];
+                }
+                if (!UNIT) rd[i] = dv[row];
+                rs[i] = a.exp_slot[row];
+                rt[i] = a.xout ? a.scatter[row] : -1;
+            }
+        }
+    };
+    auto store_chunk = [&](int q, int b) {
+        int r0, r1;
+        chunk_rows(q, r0, r1);
+        T *vb = bvals(b);
+        T *db = bdinv(b);
+        int *cb = bcols(b);
+        int *sb = bslot(b);
+        int *tb = bdst(b);
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            const int rr = tid + i * nt;
+            if (r0 + rr < r1) {
+#pragma unroll
+                for (int e = 0; e < W; ++e) {
+                    cb[e * CH + rr] = rc[i][e];
+                    vb[e * CH + rr] = rv[i][e];
+                }
+                if (!UNIT) db[rr] = rd[i];
+                sb[rr] = rs[i];
+                tb[rr] = rt[i];
+            }
+        }
+    };
+    const int c0 = a.chunk_ptr[g], c1 = a.chunk_ptr[g + 1];
+    if (c0 < c1) {
+        load_chunk(c0);
+        store_chunk(c0, 0);
+    }
+    __syncthreads();
+    bool aborted = false;
+    for (int q = c0; q < c1 && !aborted; ++q) {
+        const int b = (q - c0) & 1;
+        if (q + 1 < c1) load_chunk(q + 1);
+        int cr0, cr1;
+        chunk_rows(q, cr0, cr1);
+        const T *vb = bvals(b);
+        const T *db = bdinv(b);
+        const int *cb = bcols(b);
+        const int *sb = bslot(b);
+        const int *tb = bdst(b);
+        const int f = a.chunk_step[2 * q], e_ = a.chunk_step[2 * q + 1];
+        for (int s = f; s < e_; ++s) {
+            const int rb = a.step_row[2 * s], re = a.step_row[2 * s + 1];
+            const int items = (re - rb) * R;
+            for (int t = tid; t < items; t += nt) {
+                const int qq = t / R, k = t - qq * R;
+                const int x = rb + qq, i = x - cr0;
+                T sv = xl[(x - lo) * R + k];
+#pragma unroll
+                for (int e = 0; e < W; ++e) {
+                    const int c = cb[e * CH + i];
+                    if (c != n) {
+                        T dep;
+                        if (c > n)
+                            dep = poll_slot<T>(mrd + (size_t)(c - n - 1) * a.mbox_stride + k, a.err_dev, a.err_host,
+                                               &s_abort);
+                        else
+                            dep = xl[(c - lo) * R + k];
+                        sv -= vb[e * CH + i] * dep;
+                    }
+                }
+                if (!UNIT) sv *= db[i];
+                xl[(x - lo) * R + k] = sv;
+                if (a.write_xw) static_cast<T *>(a.xw)[(size_t)x * R + k] = sv;
+                const int slot = sb[i];
+                if (slot >= 0)
+                    __hip_atomic_store(mrd + (size_t)slot * a.mbox_stride + k, sv, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                const int dst = tb[i];
+                if (dst >= 0) {
+                    if (a.out_f64) static_cast<double *>(a.xout)[(size_t)dst * R + k] = static_cast<double>(sv);
+                    else static_cast<float *>(a.xout)[(size_t)dst * R + k] = static_cast<float>(sv);
+                }
+            }
+            __syncthreads();
+            if (s_abort) {
+                aborted = true;
+                break;
+            }
+        }
+        if (!aborted && q + 1 < c1) {
+            store_chunk(q + 1, b ^ 1);
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const unsigned done = __hip_atomic_fetch_add(&a.epoch[1], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (done == gridDim.x - 1) {
+            __hip_atomic_store(&a.epoch[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.epoch[0], s_epoch + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// LDS bytes of k_owner for a window of `win` rows.
+size_t owner_lds_bytes(int win, int R, int W, int rows_per_chunk, bool unit, size_t tsize)
+{
+    const size_t win_bytes = (((size_t)win * R * tsize) + 15) & ~(size_t)15;
+    const size_t buf = (size_t)rows_per_chunk * ((W + (unit ? 0 : 1)) * tsize + (W + 2) * sizeof(int));
+    return win_bytes + 2 * buf;
+}
+
+using OwnerKernel = void (*)(TriArgs);
+
+template <typename T, int W, int RPT>
+OwnerKernel owner_kernel_w(bool unit)
+{
+    return unit ? k_owner<T, W, RPT, true> : k_owner<T, W, RPT, false>;
+}
+
+template <typename T, int RPT>
+OwnerKernel owner_kernel_r(int w, bool unit)
+{
+    switch (w) {
+    case 1: return owner_kernel_w<T, 1, RPT>(unit);
+    case 2: return owner_kernel_w<T, 2, RPT>(unit);
+    case 3: return owner_kernel_w<T, 3, RPT>(unit);
+    case 4: return owner_kernel_w<T, 4, RPT>(unit);
+    case 5: return owner_kernel_w<T, 5, RPT>(unit);
+    case 6: return owner_kernel_w<T, 6, RPT>(unit);
+    case 7: return owner_kernel_w<T, 7, RPT>(unit);
+    case 8: return owner_kernel_w<T, 8, RPT>(unit);
+    default: return nullptr;
+    }
+}
+
+template <typename T>
+OwnerKernel owner_kernel(int w, int rpt, bool unit)
+{
+    if (rpt == 1) return owner_kernel_r<T, 1>(w, unit);
+    if (rpt == 2) return owner_kernel_r<T, 2>(w, unit);
+    return nullptr;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_fill_sentinel(T *p, size_t count)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = sentinel<T>();
 }
 
 template <typename T, typename TIn, typename TOut>
@@ -237,6 +512,17 @@ void launch_typed(DevTri &d, TriArgs a, hipStream_t st)
         hip_check(hipGetLastError(), "k_level launch");
         return;
     }
+    if (d.kind == HEC_SCHED_OWNER_PERSISTENT && !d.has_tail && d.max_lanes_one && d.w >= 1 && d.w <= 8 &&
+        d.chunk_rows > 0 && d.chunk_rows % d.block == 0) {
+        const int rpt = d.chunk_rows / d.block;
+        OwnerKernel k = owner_kernel<T>(d.w, rpt, d.unit);
+        const size_t lds = owner_lds_bytes(d.max_window, a.R, d.w, d.chunk_rows, d.unit, sizeof(T));
+        if (k && lds <= (size_t)device_max_lds() && capacity_of((const void *)k, d.block, lds) >= d.groups) {
+            hipLaunchKernelGGL(k, dim3(d.groups), dim3(d.block), lds, st, a);
+            hip_check(hipGetLastError(), "k_owner launch");
+            return;
+        }
+    }
     size_t lds = 0;
     bool use_lds = false;
     auto k_lds = k_persistent<T, TIn, TOut, true>;
@@ -248,7 +534,6 @@ void launch_typed(DevTri &d, TriArgs a, hipStream_t st)
     }
     if (!use_lds && capacity_of((const void *)k_glb, d.block, 0) < d.groups)
         fail(HEC_ERR_CAPACITY, "persistent grid exceeds the co-resident capacity");
-    a.use_lds = use_lds ? 1 : 0;
     if (use_lds)
         hipLaunchKernelGGL(k_lds, dim3(d.groups), dim3(d.block), lds, st, a);
     else
@@ -315,9 +600,22 @@ int32_t device_max_lds()
     return v;
 }
 
+void fill_sentinel(void *p, size_t count, hec_dtype_t dt)
+{
+    if (count == 0) return;
+    const unsigned grid = (unsigned)((count + 255) / 256);
+    if (dt == HEC_F64)
+        hipLaunchKernelGGL(k_fill_sentinel<double>, dim3(grid), dim3(256), 0, 0, static_cast<double *>(p), count);
+    else
+        hipLaunchKernelGGL(k_fill_sentinel<float>, dim3(grid), dim3(256), 0, 0, static_cast<float *>(p), count);
+    hip_check(hipGetLastError(), "k_fill_sentinel launch");
+    hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+}
+
 void launch_tri(DevTri &d, const void *bin, hec_dtype_t in_dt, const int32_t *gather, void *xw, void *xout,
                 hec_dtype_t out_dt, const int32_t *scatter, int32_t R, hipStream_t st)
 {
+    if (R > d.ws_R) fail(HEC_ERR_INVALID_ARG, "internal: workspace narrower than nrhs");
     TriArgs a{};
     a.n = d.n;
     a.w = d.w;
@@ -332,10 +630,12 @@ void launch_tri(DevTri &d, const void *bin, hec_dtype_t in_dt, const int32_t *ga
     a.step_ptr = d.step_ptr.as<int32_t>();
     a.step_row = d.step_row.as<int32_t>();
     a.step_lanes = d.step_lanes.as<int32_t>();
-    a.wait_ptr = d.wait_ptr.as<int32_t>();
-    a.waits = d.waits.as<int32_t>();
     a.window = d.window.as<int32_t>();
-    a.progress = d.progress.as<unsigned long long>();
+    a.exp_slot = d.exp_slot.as<int32_t>();
+    a.exp_ptr = d.exp_ptr.as<int32_t>();
+    a.mbox = d.mbox.p;
+    a.nexp = d.nexp;
+    a.mbox_stride = d.ws_R;
     a.epoch = d.epoch.as<unsigned int>();
     a.err_dev = d.err.as<int>();
     a.err_host = d.err_host;
@@ -344,6 +644,12 @@ void launch_tri(DevTri &d, const void *bin, hec_dtype_t in_dt, const int32_t *ga
     a.xw = xw;
     a.xout = xout;
     a.scatter = scatter;
+    a.write_xw = xout ? 0 : 1;
+    a.chunk_ptr = d.chunk_ptr.as<int32_t>();
+    a.chunk_step = d.chunk_step.as<int32_t>();
+    a.chunk_rows = d.chunk_rows;
+    a.in_f64 = in_dt == HEC_F64 ? 1 : 0;
+    a.out_f64 = out_dt == HEC_F64 ? 1 : 0;
     if (d.dt == HEC_F64) launch_in<double>(d, a, in_dt, out_dt, st);
     else launch_in<float>(d, a, in_dt, out_dt, st);
 }

@@ -152,3 +152,23 @@ def test_in_place_solve():
     H.tri_solve_lower(p, bt, bt)
     torch.cuda.synchronize()
     assert relerr(bt.cpu().numpy(), oracle.lower_solve(L, b)) <= FP64_TOL
+
+
+@pytest.mark.parametrize("block,chunk", [(64, 64), (64, 128), (256, 256), (256, 512)])
+@pytest.mark.parametrize("nrhs", [1, 3])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_owner_chunked_kernel_bit_identical_to_level_launch(block, chunk, nrhs, dt):
+    A = synth.diffusion3d(21, 19, 17, 1.0, seed=12)
+    L, U = oracle.iluk(A, 1)
+    if dt == "f32":
+        L, U = oracle.to_f32(L), oracle.to_f32(U)
+    b = synth.rhs(A.n, nrhs, 13).astype(np.float64 if dt == "f64" else np.float32)
+    ref_plan_l = H.tri_analyze(L, "lower", unit_diag=True, dtype=dt, tune=H.tune_default(schedule="level_launch"))
+    ref_plan_u = H.tri_analyze(U, "upper", dtype=dt, tune=H.tune_default(schedule="level_launch"))
+    t = H.tune_default(schedule="owner_persistent", block_threads=block, chunk_rows=chunk, max_nrhs=nrhs)
+    pl = H.tri_analyze(L, "lower", unit_diag=True, dtype=dt, tune=t)
+    pu = H.tri_analyze(U, "upper", dtype=dt, tune=t)
+    assert H.tri_plan_stats(pl)["nnz_tail"] == 0
+    for rep in range(3):  # alternating mailbox halves
+        assert np.array_equal(solve(pl, b), solve(ref_plan_l, b))
+        assert np.array_equal(solve(pu, b, upper=True), solve(ref_plan_u, b, upper=True))
