@@ -77,6 +77,160 @@ def measured_traffic(kernel, workload):
     return None
 
 
+def _time_apply(H, torch, f, r, z, steps, warmup, ras=False):
+    app = H.ras_apply if ras else H.ilu_apply
+    for _ in range(warmup):
+        app(f, r, z)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        app(f, r, z)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def _krylov(H, torch, M, Aop, b, method, rtol=1e-10, maxit=20000):
+    x = torch.zeros_like(b)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    st, info = H.krylov_solve(Aop, M, b, x, method=method, m=30, rtol=rtol, maxit=maxit)
+    torch.cuda.synchronize()
+    dt = time.time() - t0
+    return x, {"status": int(st), "seconds": round(dt, 4), "iters": [i.iters for i in info],
+               "precond_applies": [i.precond_applies for i in info],
+               "relres_max": max(i.relres for i in info)}
+
+
+def _block_diag(mats):
+    import numpy as np
+
+    from synth import CSR
+    rps, cis, vs, sys_ptr, off, nnz = [np.zeros(1, np.int64)], [], [], [0], 0, 0
+    for M in mats:
+        rps.append(M.rowptr[1:].astype(np.int64) + nnz)
+        cis.append(M.col.astype(np.int64) + off)
+        vs.append(M.val)
+        off += M.n
+        nnz += M.nnz
+        sys_ptr.append(off)
+    return CSR(off, np.concatenate(rps).astype(np.int32), np.concatenate(cis).astype(np.int32),
+               np.concatenate(vs)), np.array(sys_ptr, np.int32)
+
+
+def run_config(cfg, args):
+    """Secondary workloads (one JSON line each): 3 = mixed precision on
+    heterogeneous ILUT, 4 = RAS with 16 RHS, 5 = 256 batched systems."""
+    import numpy as np
+    import torch
+
+    import paper_1606_00541_amd as H
+    import synth
+
+    torch.cuda.set_device(0)
+    out = {"metric": "L+U solve GB/s & solves/s, FP64 vs FP32+refine/batched, at 1e-10 rel resid",
+           "unit": "GB/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic", "config": {}}
+    if cfg == 3:
+        A = synth.diffusion3d(100, None, None, 2.0, seed=3)
+        n = A.n
+        Aop = H.hec_from_csr(A)
+        b = torch.from_numpy(synth.rhs(n, 1, 3)).cuda()
+        res = {}
+        for fdt in ("f64", "f32"):
+            t0 = time.time()
+            f = H.ilu_setup(A, "ilut", p=10, tol=1e-3, factor_dtype=fdt,
+                            tune=H.tune_default(schedule=args.schedule))
+            setup = time.time() - t0
+            pl, pu = H.ilu_plans(f)
+            stl, stu = H.tri_plan_stats(pl), H.tri_plan_stats(pu)
+            sv = 8 if fdt == "f64" else 4
+            B = counted_bytes(n, stl["nnz_offdiag"], stu["nnz_offdiag"], 1, sv=sv)
+            z = torch.empty_like(b)
+            ms = _time_apply(H, torch, f, b, z, args.steps, args.warmup)
+            x, kr = _krylov(H, torch, f, Aop, b, "fgmres")
+            res[fdt] = {"apply_ms": round(ms, 4), "apply_GBps": round(B / (ms * 1e-3) / 1e9, 3),
+                        "nlev_L": stl["nlev"], "nlev_U": stu["nlev"], "nnz_offdiag_L": stl["nnz_offdiag"],
+                        "nnz_offdiag_U": stu["nnz_offdiag"], "setup_s": round(setup, 3), "fgmres": kr,
+                        "x": x}
+        d = (res["f32"]["x"] - res["f64"]["x"]).norm().item() / res["f64"]["x"].norm().item()
+        for k in res:
+            res[k].pop("x")
+        out.update({"value": res["f32"]["apply_GBps"], "dtype": "f32 factors, f64 refinement",
+                    "ms_per_step": res["f32"]["apply_ms"],
+                    "config": {"workload": "heterogeneous 3D 7-point diffusion 100^3, lognormal sigma=2 seed 3, "
+                                           "ILUT(tol 1e-3, p 10); FGMRES(30) to 1e-10"},
+                    "fp64": res["f64"], "fp32_refined": res["f32"], "rel_diff_fp32_vs_fp64_solution": d,
+                    "fp32_time_ratio_vs_fp64": round(res["f32"]["fgmres"]["seconds"] /
+                                                     res["f64"]["fgmres"]["seconds"], 4)})
+    elif cfg == 4:
+        A = synth.poisson3d(128)
+        n = A.n
+        owner, sizes = synth.subdomain_cuts(n, 64, 8192, 61440, seed=4)
+        t0 = time.time()
+        s = H.ras_setup(A, 64, owner, overlap=1, factor_dtype="f32", tune=H.tune_default(max_nrhs=16))
+        setup = time.time() - t0
+        nsub, tot, ext = H.ras_info(s)
+        pl, pu = H.ras_plans(s)
+        stl, stu = H.tri_plan_stats(pl), H.tri_plan_stats(pu)
+        R = 16
+        # FP32 factor side on the extended rows, FP64 gather of r and prolongation of z
+        B = (stl["nnz_offdiag"] + stu["nnz_offdiag"]) * 8 + tot * 4 + 2 * 4 * tot + R * (2 * tot * 4 + 2 * n * 8)
+        r = torch.from_numpy(synth.rhs(n, R, 4)).cuda()
+        z = torch.empty_like(r)
+        ms = _time_apply(H, torch, s, r, z, max(3, args.steps // 5), 2, ras=True)
+        Aop = H.hec_from_csr(A)
+        x, kr = _krylov(H, torch, s, Aop, r, "bicgstab")
+        out.update({"value": round(B / (ms * 1e-3) / 1e9, 3), "dtype": "f32 factors, f64 outer",
+                    "ms_per_step": round(ms, 4),
+                    "config": {"workload": "RAS on 128^3 Poisson: 64 seeded contiguous subdomains (8192..61440 "
+                                           "rows), overlap 1, ILU(0) per subdomain, 16 RHS; BiCGSTAB to 1e-10",
+                               "extended_rows": int(tot), "nlev_L": stl["nlev"], "nlev_U": stu["nlev"],
+                               "setup_s": round(setup, 3)},
+                    "solves_per_s": round(1000.0 * R / ms, 2), "bicgstab": kr})
+    elif cfg == 5:
+        shapes = synth.batch_systems(256, seed=5)
+        mats = []
+        for i, (dim, side) in enumerate(shapes):
+            if dim == 2:
+                mats.append(synth.diffusion2d(side, None, 1.0, seed=5000 + i))
+            else:
+                mats.append(synth.diffusion3d(side, None, None, 1.0, seed=5000 + i))
+        A, sys_ptr = _block_diag(mats)
+        n = A.n
+        R = 8
+        b = torch.from_numpy(synth.rhs(n, R, 5)).cuda()
+        Aop = H.hec_from_csr(A)
+        res = {}
+        for fdt in ("f64", "f32"):
+            t0 = time.time()
+            f = H.batch_setup(A, sys_ptr, "iluk", k=1, factor_dtype=fdt, tune=H.tune_default(max_nrhs=R))
+            setup = time.time() - t0
+            pl, pu = H.ilu_plans(f)
+            stl, stu = H.tri_plan_stats(pl), H.tri_plan_stats(pu)
+            sv = 8 if fdt == "f64" else 4
+            B = counted_bytes(n, stl["nnz_offdiag"], stu["nnz_offdiag"], R, sv=sv)
+            z = torch.empty_like(b)
+            ms = _time_apply(H, torch, f, b, z, max(3, args.steps // 5), 2)
+            x, kr = _krylov(H, torch, f, Aop, b, "fgmres")
+            res[fdt] = {"apply_ms": round(ms, 4), "apply_GBps": round(B / (ms * 1e-3) / 1e9, 3),
+                        "nlev_L": stl["nlev"], "nlev_U": stu["nlev"], "setup_s": round(setup, 3), "fgmres": kr,
+                        "systems_per_s": round(len(mats) * R / kr["seconds"], 3)}
+        out.update({"value": res["f32"]["apply_GBps"], "dtype": "f32 factors, f64 refinement",
+                    "ms_per_step": res["f32"]["apply_ms"],
+                    "config": {"workload": "256 independent systems (log-uniform 1e3..2e5 rows, 2D/3D lognormal "
+                                           "sigma=1), ILU(1), 8 RHS each; FGMRES(30) to 1e-10",
+                               "n_total": int(n), "systems": len(mats)},
+                    "fp64": res["f64"], "fp32_refined": res["f32"],
+                    "fp32_speedup_vs_fp64_time_to_1e-10": round(res["f64"]["fgmres"]["seconds"] /
+                                                                res["f32"]["fgmres"]["seconds"], 4)})
+    else:
+        raise SystemExit("unknown --config %d" % cfg)
+    print(json.dumps(out))
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,12 +244,17 @@ def main(argv=None):
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one device copy of this size (for counter calibration)")
+    ap.add_argument("--config", type=int, default=2,
+                    help="2 (default): 128^3 ILU(0) L+U; 3: mixed precision ILUT; 4: RAS 16 RHS; 5: batch")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
         print("bench.py measures one GPU: the level-scheduled solve of one system does not shard "
               "(see DESIGN.md); run with --gpus 1", file=sys.stderr)
         return 2
+
+    if args.config != 2:
+        return run_config(args.config, args)
 
     import numpy as np
     import torch

@@ -89,7 +89,13 @@ typedef struct hec_tune {
     int32_t max_nrhs;       /* workspace is allocated for up to this many RHS (grows on demand) */
     int32_t block_threads;  /* threads per workgroup (64..1024, multiple of 64) */
     int32_t chunk_rows;     /* owner schedule: rows of matrix data staged in LDS per chunk
-                               (a multiple of block_threads, at most 4x; 0 = 2x) */
+                               (1, 2 or 4 times block_threads; 0 = max(256, block_threads)) */
+    int32_t partition;      /* owner schedule parts: 0 = auto (blocks of a detected
+                               structured grid, else contiguous), 1 = contiguous ranges of the
+                               problem order, 2 = recursive graph bisection, 3 = grid blocks */
+    int32_t kernel_variant; /* persistent kernel: 0 = auto, 1 = generic row-per-thread kernel,
+                               2 = owner kernel with LDS-staged chunks, 3 = owner kernel with
+                               separate compute and fetch waves (one RHS) */
 } hec_tune_t;
 
 /* Per-RHS outcome of krylov_solve. */
@@ -109,6 +115,7 @@ typedef struct tri_stats {
     int64_t lds_rows;        /* largest per-workgroup LDS window, in rows */
     int64_t nremote;         /* dependency entries read across workgroups */
     int32_t unit_diag, dtype;
+    int32_t crit_hops;       /* most workgroup-to-workgroup handoffs along one dependency chain */
 } tri_stats_t;
 
 typedef struct hec_matrix_s *hec_matrix_t;
@@ -186,6 +193,13 @@ hec_status_t tri_plan_stats(tri_plan_t plan, tri_stats_t *stats);
 /* Execution order chosen for the device: xperm[n] (device position -> original
  * row) and the workgroup owning each device position (owner[n]); may be NULL. */
 hec_status_t tri_plan_layout(tri_plan_t plan, int32_t *xperm, int32_t *owner);
+
+/* Profiling hook: while `trace` is non-NULL, persistent launches of this plan
+ * write, for workgroup g and its j-th step, the shader clock at the step's
+ * start and end to trace[2*(g*stride + j)] and trace[2*(g*stride + j) + 1]
+ * (uint64, device memory of 2*groups*stride entries owned by the caller); steps
+ * beyond `stride` are not recorded.  Pass NULL to stop tracing. */
+hec_status_t tri_plan_trace(tri_plan_t plan, void *trace, int32_t stride);
 
 /* Solve L x = b (Algorithm 2): b is gathered into level order, the levels are
  * solved in order with all rows of a level computed simultaneously, and x is

@@ -45,7 +45,7 @@ class HecError(RuntimeError):
 class Tune(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int32) for f in (
         "ell_width", "schedule", "num_groups", "merge_rows", "group_lanes", "long_row", "part_rows",
-        "host_only", "max_nrhs", "block_threads", "chunk_rows")]
+        "host_only", "max_nrhs", "block_threads", "chunk_rows", "partition", "kernel_variant")]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -60,7 +60,8 @@ class TriStats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int32) for f in (
         "n", "nlev", "ell_width", "ld", "num_groups", "nsteps", "nexport", "schedule")] + [
         ("nnz_offdiag", ctypes.c_int64), ("nnz_tail", ctypes.c_int64), ("lds_rows", ctypes.c_int64),
-        ("nremote", ctypes.c_int64), ("unit_diag", ctypes.c_int32), ("dtype", ctypes.c_int32)]
+        ("nremote", ctypes.c_int64), ("unit_diag", ctypes.c_int32), ("dtype", ctypes.c_int32),
+        ("crit_hops", ctypes.c_int32)]
 
 
 class Precond(ctypes.Structure):
@@ -82,6 +83,7 @@ SIGNATURES = {
     "tri_plan_hec": (_i32, [_vp, _P(_i32), _P(_i32), _P(_i64), _vp, _vp, _vp, _vp, _vp]),
     "tri_plan_stats": (_i32, [_vp, _P(TriStats)]),
     "tri_plan_layout": (_i32, [_vp, _vp, _vp]),
+    "tri_plan_trace": (_i32, [_vp, _vp, _i32]),
     "tri_solve_lower": (_i32, [_vp, _vp, _vp, _i32, _i32, _vp]),
     "tri_solve_upper": (_i32, [_vp, _vp, _vp, _i32, _i32, _vp]),
     "tri_plan_destroy": (None, [_vp]),
@@ -301,6 +303,13 @@ def tri_plan_layout(plan):
     ow = np.empty(n, np.int32)
     _check(lib().tri_plan_layout(plan.ptr, _ptr(xp), _ptr(ow)))
     return xp, ow
+
+
+def tri_plan_trace(plan, trace=None, stride=0):
+    """Attach (or with None detach) a device uint64 tensor of
+    2*groups*stride entries receiving per-step start/end shader clocks."""
+    ptr = ctypes.c_void_p(trace.data_ptr()) if trace is not None else None
+    _check(lib().tri_plan_trace(plan.ptr, ptr, int(stride)))
 
 
 def tri_solve_lower(plan, b, x, stream=None):

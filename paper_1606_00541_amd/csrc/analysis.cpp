@@ -3,6 +3,7 @@
 // (Section 2.1), plus the device execution layout and the persistent
 // schedule built on top of the level sets.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -13,10 +14,20 @@ namespace hec {
 
 void fail(hec_status_t code, const std::string &msg) { throw Error{code, msg}; }
 
+Tune default_tune()
+{
+    hec_tune_t t;
+    std::memset(&t, 0, sizeof(t));
+    t.ell_width = -1;
+    t.max_nrhs = 1;
+    t.block_threads = 256;
+    return tune_from(&t);
+}
+
 Tune tune_from(const hec_tune_t *t)
 {
+    if (!t) return default_tune();
     Tune u;
-    if (!t) return u;
     u.ell_width = t->ell_width;
     u.schedule = t->schedule;
     u.num_groups = t->num_groups;
@@ -27,7 +38,11 @@ Tune tune_from(const hec_tune_t *t)
     u.host_only = t->host_only;
     u.max_nrhs = t->max_nrhs > 0 ? t->max_nrhs : 1;
     u.block_threads = t->block_threads > 0 ? t->block_threads : 256;
-    u.chunk_rows = t->chunk_rows > 0 ? t->chunk_rows : 2 * u.block_threads;
+    u.chunk_rows = t->chunk_rows > 0 ? t->chunk_rows : std::max(256, u.block_threads);
+    u.partition = t->partition;
+    u.variant = t->kernel_variant;
+    if (u.variant < 0 || u.variant > 3) fail(HEC_ERR_INVALID_ARG, "tune.kernel_variant out of range");
+    if (u.partition < 0 || u.partition > 3) fail(HEC_ERR_INVALID_ARG, "tune.partition out of range");
     if (u.schedule < HEC_SCHED_AUTO || u.schedule > HEC_SCHED_OWNER_PERSISTENT)
         fail(HEC_ERR_INVALID_ARG, "tune.schedule out of range");
     if (u.block_threads % 64 != 0 || u.block_threads > 1024)
@@ -38,7 +53,7 @@ Tune tune_from(const hec_tune_t *t)
     if (u.ell_width < -1 || u.ell_width > 64) fail(HEC_ERR_INVALID_ARG, "tune.ell_width out of range");
     if (u.num_groups < 0 || u.merge_rows < 0 || u.long_row < 0 || u.part_rows < 0)
         fail(HEC_ERR_INVALID_ARG, "negative tuning value");
-    if (u.chunk_rows % u.block_threads != 0 || u.chunk_rows > 4 * u.block_threads)
+    if (u.chunk_rows != u.block_threads && u.chunk_rows != 2 * u.block_threads && u.chunk_rows != 4 * u.block_threads)
         fail(HEC_ERR_INVALID_ARG, "tune.chunk_rows must be 1, 2 or 4 times block_threads");
     return u;
 }
@@ -293,6 +308,34 @@ void finish_schedule(Schedule &s, ExecHost &ex, const std::vector<std::vector<st
             s.chunk_ptr[g + 1] = (int32_t)(s.chunk_step.size() / 2);
         }
     }
+    // cross-group entry lists per step (owner schedule, ELL part; plans with
+    // a CSR tail do not use them)
+    s.rem_ptr.assign((size_t)S + 1, 0);
+    s.rem_ent.clear();
+    s.max_rem_window = 0;
+    if (s.kind == HEC_SCHED_OWNER_PERSISTENT) {
+        for (int32_t g = 0; g < G; ++g)
+            for (int32_t q = s.chunk_ptr[g]; q < s.chunk_ptr[g + 1]; ++q) {
+                const int32_t f = s.chunk_step[2 * q], e = s.chunk_step[2 * q + 1];
+                const int32_t r0 = s.step_row[2 * f];
+                for (int32_t sid = f; sid < e; ++sid) {
+                    for (int32_t x = s.step_row[2 * sid]; x < s.step_row[2 * sid + 1]; ++x)
+                        for (int32_t k = 0; k < ex.w; ++k) {
+                            const int32_t c = ex.ell_col[(size_t)k * ex.ld + x];
+                            if (c > ex.n) {
+                                s.rem_ent.push_back((x - r0) * ex.w + k);
+                                s.rem_ent.push_back(c - ex.n - 1);
+                            }
+                        }
+                    s.rem_ptr[sid + 1] = (int32_t)(s.rem_ent.size() / 2);
+                }
+            }
+        for (int32_t g = 0; g < G; ++g)
+            for (int32_t sid = s.step_ptr[g]; sid < s.step_ptr[g + 1]; ++sid) {
+                const int32_t e = std::min(s.step_ptr[g + 1], sid + 8);
+                s.max_rem_window = std::max(s.max_rem_window, s.rem_ptr[e] - s.rem_ptr[sid]);
+            }
+    }
     // LDS windows: a group's contiguous device-row span (owner schedule only)
     s.window.assign(2 * (size_t)G, 0);
     s.max_window = 0;
@@ -309,10 +352,222 @@ void finish_schedule(Schedule &s, ExecHost &ex, const std::vector<std::vector<st
 
 }  // namespace
 
+// Recursive bisection of the undirected graph of a triangle (its pattern
+// plus the transpose, diagonal dropped) into `parts` parts of near-equal
+// size.  A set is split by one breadth-first sweep from a pseudo-peripheral
+// vertex (found by repeated sweeps): the first vertices reached form the
+// first half.  Disconnected pieces are swept in ascending index order.
+// Sibling parts get consecutive ids, so nearby ids are nearby rows.
+std::vector<int32_t> bisect_parts(const Csr &a, int32_t P)
+{
+    const int32_t n = a.n;
+    std::vector<int32_t> part(n, 0);
+    if (P <= 1 || n == 0) return part;
+    std::vector<int32_t> aptr((size_t)n + 1, 0);
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t p = a.rp[i]; p < a.rp[i + 1]; ++p)
+            if (a.ci[p] != i) {
+                aptr[i + 1] += 1;
+                aptr[a.ci[p] + 1] += 1;
+            }
+    for (int32_t i = 0; i < n; ++i) aptr[i + 1] += aptr[i];
+    std::vector<int32_t> adj(aptr[n]), cur(aptr.begin(), aptr.end() - 1);
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t p = a.rp[i]; p < a.rp[i + 1]; ++p)
+            if (a.ci[p] != i) {
+                adj[cur[i]++] = a.ci[p];
+                adj[cur[a.ci[p]]++] = i;
+            }
+    for (int32_t i = 0; i < n; ++i) std::sort(adj.begin() + aptr[i], adj.begin() + aptr[i + 1]);
+    std::vector<int32_t> in_set(n, -1), seen(n, -1), order;
+    order.reserve(n);
+    int32_t set_tag = 0, seen_tag = 0;
+    struct Job {
+        std::vector<int32_t> mem;
+        int32_t k, first;
+    };
+    std::vector<Job> stack;
+    {
+        Job j;
+        j.mem.resize(n);
+        std::iota(j.mem.begin(), j.mem.end(), 0);
+        j.k = P;
+        j.first = 0;
+        stack.push_back(std::move(j));
+    }
+    // breadth-first sweep inside the current set from r; returns the last vertex
+    auto sweep = [&](int32_t r, bool append) {
+        const size_t head0 = order.size();
+        if (!append) order.resize(head0);
+        seen[r] = seen_tag;
+        order.push_back(r);
+        for (size_t h = head0; h < order.size(); ++h) {
+            const int32_t v = order[h];
+            for (int32_t q = aptr[v]; q < aptr[v + 1]; ++q) {
+                const int32_t w = adj[q];
+                if (in_set[w] == set_tag && seen[w] != seen_tag) {
+                    seen[w] = seen_tag;
+                    order.push_back(w);
+                }
+            }
+        }
+        return order.back();
+    };
+    while (!stack.empty()) {
+        Job job = std::move(stack.back());
+        stack.pop_back();
+        if (job.k <= 1 || job.mem.size() <= 1) {
+            for (int32_t v : job.mem) part[v] = job.first;
+            continue;
+        }
+        ++set_tag;
+        for (int32_t v : job.mem) in_set[v] = set_tag;
+        int32_t root = job.mem.front();
+        for (int it = 0; it < 2; ++it) {  // pseudo-peripheral vertex
+            ++seen_tag;
+            order.clear();
+            root = sweep(root, false);
+        }
+        ++seen_tag;
+        order.clear();
+        sweep(root, true);
+        for (int32_t v : job.mem)  // disconnected remainder, ascending index
+            if (seen[v] != seen_tag) sweep(v, true);
+        const int32_t k1 = job.k / 2, k2 = job.k - k1;
+        const size_t m1 = (size_t)((double)job.mem.size() * k1 / job.k + 0.5);
+        Job a1, a2;
+        a1.mem.assign(order.begin(), order.begin() + m1);
+        a2.mem.assign(order.begin() + m1, order.end());
+        a1.k = k1;
+        a1.first = job.first;
+        a2.k = k2;
+        a2.first = job.first + k1;
+        std::sort(a1.mem.begin(), a1.mem.end());
+        std::sort(a2.mem.begin(), a2.mem.end());
+        stack.push_back(std::move(a2));
+        stack.push_back(std::move(a1));
+    }
+    return part;
+}
+
+// Structured-grid detection: the natural order of a 2D/3D stencil matrix
+// shows up as dominant column offsets 1, nx and nx*ny.  Returns false when
+// the pattern does not look like a grid.
+bool detect_grid(const Csr &a, int32_t &nx, int32_t &ny, int32_t &nz)
+{
+    const int32_t n = a.n;
+    if (n < 64) return false;
+    std::vector<std::pair<int64_t, int32_t>> cnt;  // offset -> count (sparse)
+    {
+        std::vector<int32_t> offs;
+        offs.reserve(a.nnz());
+        for (int32_t i = 0; i < n; ++i)
+            for (int32_t p = a.rp[i]; p < a.rp[i + 1]; ++p)
+                if (a.ci[p] != i) offs.push_back(std::abs(a.ci[p] - i));
+        if (offs.empty()) return false;
+        std::sort(offs.begin(), offs.end());
+        for (size_t k = 0; k < offs.size();) {
+            size_t e = k;
+            while (e < offs.size() && offs[e] == offs[k]) ++e;
+            cnt.push_back({offs[k], (int32_t)(e - k)});
+            k = e;
+        }
+    }
+    auto freq = [&](int64_t o) {
+        for (auto &c : cnt)
+            if (c.first == o) return c.second;
+        return 0;
+    };
+    const int32_t dominant = n / 4;
+    // nx: the most frequent offset >= 2 that divides n
+    int64_t bx = 0;
+    int32_t fx = 0;
+    for (auto &c : cnt)
+        if (c.first >= 2 && c.second >= dominant && n % c.first == 0 && c.second > fx) {
+            bx = c.first;
+            fx = c.second;
+        }
+    if (bx == 0 || freq(1) < dominant) return false;
+    // nx*ny: the most frequent larger multiple of nx that divides n
+    int64_t bxy = 0;
+    int32_t fxy = 0;
+    for (auto &c : cnt)
+        if (c.first > bx && c.first % bx == 0 && n % c.first == 0 && c.second >= dominant && c.second > fxy) {
+            bxy = c.first;
+            fxy = c.second;
+        }
+    nx = (int32_t)bx;
+    if (bxy == 0) {
+        ny = n / nx;
+        nz = 1;
+    } else {
+        ny = (int32_t)(bxy / bx);
+        nz = (int32_t)(n / bxy);
+    }
+    return nx > 1 && ny > 1;
+}
+
+// Blocks of a detected grid: P = px*py*pz with the smallest px+py+pz (the
+// handoffs a monotone dependency chain can make), x split least so that rows
+// of a block stay long in memory.  Part ids run x fastest, then y, then z, so
+// consecutive ids are neighbouring blocks.
+std::vector<int32_t> grid_parts(int32_t n, int32_t nx, int32_t ny, int32_t nz, int32_t P)
+{
+    int32_t best[3] = {1, 1, P};
+    int64_t best_cost = INT64_MAX;
+    for (int32_t px = 1; px <= P; ++px) {
+        if (P % px || px > nx) continue;
+        for (int32_t py = 1; py <= P / px; ++py) {
+            if ((P / px) % py || py > ny) continue;
+            const int32_t pz = P / px / py;
+            if (pz > nz) continue;
+            const int64_t cost = (int64_t)(px + py + pz) * 4 + px;  // ties: fewer x cuts
+            if (cost < best_cost) {
+                best_cost = cost;
+                best[0] = px;
+                best[1] = py;
+                best[2] = pz;
+            }
+        }
+    }
+    std::vector<int32_t> part(n, 0);
+    if (best_cost == INT64_MAX) {
+        for (int32_t i = 0; i < n; ++i) part[i] = (int32_t)((int64_t)i * P / n);
+        return part;
+    }
+    const int32_t px = best[0], py = best[1], pz = best[2];
+    for (int32_t i = 0; i < n; ++i) {
+        const int32_t x = i % nx, y = (i / nx) % ny, z = i / (nx * ny);
+        const int32_t bx = (int32_t)((int64_t)x * px / nx), by = (int32_t)((int64_t)y * py / ny),
+                      bz = (int32_t)((int64_t)z * pz / nz);
+        part[i] = bx + px * (by + py * bz);
+    }
+    return part;
+}
+
+// Largest number of workgroup-to-workgroup handoffs along any dependency
+// chain of the triangle, given the owner of every row.
+int32_t critical_hops(const Csr &a, bool upper, const std::vector<int32_t> &own)
+{
+    const int32_t n = a.n;
+    std::vector<int32_t> hop(n, 0);
+    int32_t best = 0;
+    for (int32_t q = 0; q < n; ++q) {
+        const int32_t i = upper ? n - 1 - q : q;
+        int32_t h = 0;
+        for (int32_t p = a.rp[i]; p < a.rp[i + 1]; ++p) {
+            const int32_t j = a.ci[p];
+            if (j != i) h = std::max(h, hop[j] + (own[j] != own[i] ? 1 : 0));
+        }
+        hop[i] = h;
+        best = std::max(best, h);
+    }
+    return best;
+}
+
 void build_exec(TriHost &t, const Csr &a, const Tune &tune, const DeviceShape &dev,
                 const std::vector<int32_t> *sys_ptr)
 {
-    (void)a;
     (void)sys_ptr;
     const int32_t n = t.n;
     const Levels &lv = t.lev;
@@ -360,20 +615,38 @@ void build_exec(TriHost &t, const Csr &a, const Tune &tune, const DeviceShape &d
             }
         }
     } else {
-        // owner schedule: contiguous parts of the problem order (natural order
-        // for L, reversed for U), each solved level by level by one group
+        // owner schedule: each group owns one part of the rows and solves it
+        // level by level.  Parts come from recursive graph bisection (compact
+        // parts: few dependency edges and few group-to-group handoffs along
+        // any chain) or, on request, from contiguous ranges of the problem
+        // order (natural order for L, reversed for U).
         int32_t parts = G;
         if (tune.part_rows > 0) parts = std::min(G, std::max(1, (n + tune.part_rows - 1) / tune.part_rows));
         parts = std::max(1, std::min(parts, std::max(1, n)));
+        std::vector<int32_t> part_of;
+        int32_t gx = 0, gy = 0, gz = 0;
+        const bool grid = (tune.partition == 0 || tune.partition == 3) && detect_grid(a, gx, gy, gz);
+        if (grid) {
+            part_of = grid_parts(n, gx, gy, gz, parts);
+        } else if (tune.partition != 2) {
+            part_of.resize(n);
+            for (int32_t g = 0; g < parts; ++g) {
+                int32_t qb = (int32_t)((int64_t)n * g / parts), qe = (int32_t)((int64_t)n * (g + 1) / parts);
+                for (int32_t q = qb; q < qe; ++q) part_of[t.upper ? n - 1 - q : q] = g;
+            }
+        } else {
+            part_of = bisect_parts(a, parts);
+        }
+        std::vector<std::vector<int32_t>> members(parts);
+        for (int32_t q = 0; q < n; ++q) {
+            const int32_t i = t.upper ? n - 1 - q : q;  // problem order
+            members[part_of[i]].push_back(i);
+        }
         runs.assign(parts, {});
-        std::vector<int32_t> part_of_problem(n);
         int32_t x = 0;
         for (int32_t g = 0; g < parts; ++g) {
-            int32_t qb = (int32_t)((int64_t)n * g / parts), qe = (int32_t)((int64_t)n * (g + 1) / parts);
             // rows of the part in level order, ties by problem index
-            std::vector<int32_t> rows;
-            rows.reserve(qe - qb);
-            for (int32_t q = qb; q < qe; ++q) rows.push_back(t.upper ? n - 1 - q : q);
+            std::vector<int32_t> &rows = members[g];
             std::stable_sort(rows.begin(), rows.end(),
                              [&](int32_t i, int32_t j) { return lv.level[i] < lv.level[j]; });
             int32_t start = x;
@@ -388,7 +661,6 @@ void build_exec(TriHost &t, const Csr &a, const Tune &tune, const DeviceShape &d
             }
             if (x > start) runs[g].push_back({start, x});
         }
-        (void)part_of_problem;
         // Consecutive parts depend on each other; give them workgroups that
         // share an L2 domain (workgroup i runs on domain i % xcds), so that
         // most part-to-part handoffs stay inside one XCD.
@@ -440,6 +712,7 @@ void build_exec(TriHost &t, const Csr &a, const Tune &tune, const DeviceShape &d
     ex.sched = Schedule();
     ex.sched.kind = kind;
     if (kind == HEC_SCHED_OWNER_PERSISTENT) {
+        if (tune.chunk_rows <= 0) fail(HEC_ERR_INVALID_ARG, "internal: chunk_rows must be positive");
         // a step never exceeds one chunk: cut longer levels into pieces (rows
         // of one level are independent, so the extra barrier is harmless)
         for (auto &gr : runs) {
@@ -450,7 +723,12 @@ void build_exec(TriHost &t, const Csr &a, const Tune &tune, const DeviceShape &d
             gr.swap(cut);
         }
     }
-    if (kind != HEC_SCHED_LEVEL_LAUNCH) finish_schedule(ex.sched, ex, runs, tune);
+    if (kind != HEC_SCHED_LEVEL_LAUNCH) {
+        finish_schedule(ex.sched, ex, runs, tune);
+        std::vector<int32_t> own(n);
+        for (int32_t x2 = 0; x2 < n; ++x2) own[ex.orig[x2]] = ex.owner[x2];
+        ex.sched.crit_hops = critical_hops(a, t.upper, own);
+    }
 }
 
 TriHost analyze(const Csr &a, bool upper, bool unit, hec_dtype_t dt, const Tune &tune, const DeviceShape &dev,

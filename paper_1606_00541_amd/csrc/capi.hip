@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <new>
 
@@ -109,6 +110,10 @@ void upload_tri(DevTri &d, const TriHost &t, int32_t max_nrhs)
         upload(d.exp_ptr, s.exp_ptr);
         upload(d.chunk_ptr, s.chunk_ptr);
         upload(d.chunk_step, s.chunk_step);
+        upload(d.rem_ptr, s.rem_ptr);
+        std::vector<int32_t> re = s.rem_ent;
+        if (re.empty()) re.assign(2, 0);
+        upload(d.rem_ent, re);
         d.chunk_rows = s.chunk_rows;
         d.max_lanes_one = std::all_of(s.step_lanes.begin(), s.step_lanes.end(), [](int32_t v) { return v == 1; });
         d.epoch.alloc(2 * sizeof(unsigned int));
@@ -192,6 +197,7 @@ void build_plan(tri_plan_s &p, const Csr &a, bool upper, bool unit, hec_dtype_t 
     p.upper = upper;
     p.h = analyze(a, upper, unit, dt, tu, device_shape(tu, dt));
     p.d.block = tu.block_threads;
+    p.d.variant = tu.variant;
     if (!tu.host_only) {
         upload_tri(p.d, p.h, tu.max_nrhs);
         p.on_device = true;
@@ -238,14 +244,20 @@ void export_hec(const HecHost &h, int32_t *width, int32_t *ld, int64_t *tail_nnz
     if (csr_val) std::copy(h.csr_val.begin(), h.csr_val.end(), csr_val);
 }
 
-void factor(const Csr &a, hec_ilu_kind_t kind, int32_t k, double tol, int32_t p, Csr &L, Csr &U)
+void factor(const Csr &a, hec_ilu_kind_t kind, int32_t k, double tol, int32_t p, Csr &L, Csr &U,
+            const std::vector<int32_t> *blocks = nullptr)
 {
+    std::function<void(const Csr &, Csr &, Csr &)> fac;
     switch (kind) {
-    case HEC_ILU0: ilu0(a, L, U); break;
-    case HEC_ILUK: iluk(a, k, L, U); break;
-    case HEC_ILUT: ilut(a, p, tol, L, U); break;
+    case HEC_ILU0: fac = [](const Csr &m, Csr &l, Csr &u) { ilu0(m, l, u); }; break;
+    case HEC_ILUK: fac = [k](const Csr &m, Csr &l, Csr &u) { iluk(m, k, l, u); }; break;
+    case HEC_ILUT: fac = [p, tol](const Csr &m, Csr &l, Csr &u) { ilut(m, p, tol, l, u); }; break;
     default: fail(HEC_ERR_INVALID_ARG, "unknown ILU kind");
     }
+    if (blocks && blocks->size() > 2)
+        factor_blocks(a, *blocks, fac, L, U);
+    else
+        fac(a, L, U);
 }
 
 // Plans of L (unit lower) and U, and the map joining them: U's solve reads L's
@@ -401,6 +413,7 @@ hec_status_t tri_plan_stats(tri_plan_t p, tri_stats_t *s)
         s->nnz_offdiag = h.nnz_off;
         s->nnz_tail = h.nnz_tail;
         s->lds_rows = h.ex.sched.max_window;
+        s->crit_hops = h.ex.sched.crit_hops;
         s->unit_diag = h.unit ? 1 : 0;
         s->dtype = h.dt;
     });
@@ -412,6 +425,15 @@ hec_status_t tri_plan_layout(tri_plan_t p, int32_t *xperm, int32_t *owner)
         if (!p) fail(HEC_ERR_INVALID_ARG, "plan is NULL");
         if (xperm) std::copy(p->h.ex.orig.begin(), p->h.ex.orig.end(), xperm);
         if (owner) std::copy(p->h.ex.owner.begin(), p->h.ex.owner.end(), owner);
+    });
+}
+
+hec_status_t tri_plan_trace(tri_plan_t p, void *trace, int32_t stride)
+{
+    return guard([&] {
+        if (!p || stride < 0) fail(HEC_ERR_INVALID_ARG, "bad arguments");
+        p->d.trace = static_cast<unsigned long long *>(trace);
+        p->d.trace_stride = trace ? stride : 0;
     });
 }
 
@@ -464,7 +486,7 @@ hec_status_t batch_setup(int32_t n, const int32_t *rowptr, const int32_t *col, c
                         fail(HEC_ERR_INVALID_ARG, "an entry couples two systems (row " + std::to_string(i) + ")");
         auto f = std::make_unique<ilu_s>();
         f->sys_ptr.assign(sys_ptr, sys_ptr + nsys + 1);
-        factor(a, kind, k, tol, p, f->Lf, f->Uf);
+        factor(a, kind, k, tol, p, f->Lf, f->Uf, &f->sys_ptr);
         build_ilu(*f, f->Lf, f->Uf, fdt, tu);
         *out = f.release();
     });
@@ -512,7 +534,7 @@ hec_status_t ras_setup(int32_t n, const int32_t *rowptr, const int32_t *col, con
         s->nsub = nsub;
         s->lay = ras_layout(a, nsub, owner, overlap);
         ilu_s &f = s->f;
-        ilu0(s->lay.blockdiag, f.Lf, f.Uf);
+        factor(s->lay.blockdiag, HEC_ILU0, 0, 0.0, 0, f.Lf, f.Uf, &s->lay.ext_ptr);
         build_ilu(f, f.Lf, f.Uf, fdt, tu);
         if (!tu.host_only) {
             const int32_t m = s->lay.blockdiag.n;
@@ -629,16 +651,18 @@ hec_status_t tri_autotune(int32_t n, const int32_t *rowptr, const int32_t *col, 
         const int32_t w0 = auto_ell_width(a, upper);
         // candidate grid: schedule x block size x level-merge threshold x ELL width
         std::vector<Tune> cands;
-        Tune base;
+        Tune base = default_tune();
         base.max_nrhs = nrhs;
         for (int32_t blk : {256, 512}) {
             Tune t = base;
             t.block_threads = blk;
+            t.chunk_rows = std::max(256, blk);
             t.schedule = HEC_SCHED_OWNER_PERSISTENT;
             cands.push_back(t);
             for (int32_t mul : {1, 2, 4}) {
                 Tune u = base;
                 u.block_threads = blk;
+                u.chunk_rows = std::max(256, blk);
                 u.schedule = HEC_SCHED_LEVEL_PERSISTENT;
                 u.merge_rows = std::max(1, mul * blk / nrhs);
                 cands.push_back(u);
@@ -706,6 +730,9 @@ hec_status_t tri_autotune(int32_t n, const int32_t *rowptr, const int32_t *col, 
         best->part_rows = best_tune.part_rows;
         best->max_nrhs = best_tune.max_nrhs;
         best->block_threads = best_tune.block_threads;
+        best->chunk_rows = best_tune.chunk_rows;
+        best->partition = best_tune.partition;
+        best->kernel_variant = best_tune.variant;
         if (best_us) *best_us = best_t;
     });
 }

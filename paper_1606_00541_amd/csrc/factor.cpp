@@ -3,8 +3,11 @@
 // the level-of-fill rule) and ILUT(p, tol) (dual dropping), plus the
 // Restricted Additive Schwarz subdomain construction of eq. (4).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <functional>
 #include <numeric>
+#include <thread>
 
 #include "hec_host.h"
 
@@ -263,6 +266,67 @@ void ilut(const Csr &a, int32_t p, double tau, Csr &L, Csr &U)
             in[j] = 0;
         }
     }
+}
+
+// Factor a block-diagonal matrix block by block on host threads.  Block b
+// is rows block_ptr[b]..block_ptr[b+1]-1 and has no entry outside its own
+// columns, so every row's elimination stays inside its block and the result
+// equals factoring the whole matrix at once, bit for bit.
+void factor_blocks(const Csr &a, const std::vector<int32_t> &block_ptr,
+                   const std::function<void(const Csr &, Csr &, Csr &)> &fac, Csr &L, Csr &U)
+{
+    const int32_t nb = (int32_t)block_ptr.size() - 1;
+    std::vector<Csr> Ls(nb), Us(nb);
+    std::atomic<int32_t> next{0};
+    std::atomic<bool> failed{false};
+    Error first_err{HEC_OK, ""};
+    auto work = [&]() {
+        for (;;) {
+            const int32_t b = next.fetch_add(1);
+            if (b >= nb || failed.load()) return;
+            const int32_t r0 = block_ptr[b], r1 = block_ptr[b + 1];
+            Csr blk;
+            blk.n = r1 - r0;
+            blk.rp.resize((size_t)blk.n + 1);
+            const int32_t p0 = a.rp[r0];
+            for (int32_t i = r0; i <= r1; ++i) blk.rp[i - r0] = a.rp[i] - p0;
+            blk.ci.resize((size_t)(a.rp[r1] - p0));
+            blk.v.assign(a.v.begin() + p0, a.v.begin() + a.rp[r1]);
+            for (int32_t q = p0; q < a.rp[r1]; ++q) blk.ci[q - p0] = a.ci[q] - r0;
+            try {
+                fac(blk, Ls[b], Us[b]);
+            } catch (const Error &e) {
+                if (!failed.exchange(true)) first_err = Error{e.code, e.msg + " (block " + std::to_string(b) + ")"};
+                return;
+            }
+        }
+    };
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int32_t nt = (int32_t)std::min<unsigned>(std::min<unsigned>(hw, 16u), (unsigned)std::max(1, nb));
+    std::vector<std::thread> pool;
+    for (int32_t t = 1; t < nt; ++t) pool.emplace_back(work);
+    work();
+    for (auto &th : pool) th.join();
+    if (failed.load()) fail(first_err.code, first_err.msg);
+    auto join = [&](std::vector<Csr> &parts, Csr &out) {
+        out = Csr();
+        out.n = a.n;
+        out.rp.assign((size_t)a.n + 1, 0);
+        size_t total = 0;
+        for (auto &c : parts) total += c.ci.size();
+        out.ci.reserve(total);
+        out.v.reserve(total);
+        for (int32_t b = 0; b < nb; ++b) {
+            const int32_t r0 = block_ptr[b];
+            const int64_t base = (int64_t)out.ci.size();
+            for (int32_t q = 0; q < (int32_t)parts[b].ci.size(); ++q) out.ci.push_back(parts[b].ci[q] + r0);
+            out.v.insert(out.v.end(), parts[b].v.begin(), parts[b].v.end());
+            for (int32_t i = 0; i < parts[b].n; ++i) out.rp[r0 + i + 1] = (int32_t)(base + parts[b].rp[i + 1]);
+            parts[b] = Csr();
+        }
+    };
+    join(Ls, L);
+    join(Us, U);
 }
 
 // Subdomain s owns {i : owner[i] == s}; `overlap` rings of graph neighbours in

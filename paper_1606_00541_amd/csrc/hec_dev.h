@@ -91,6 +91,7 @@ struct TriArgs {
     const int32_t *step_ptr, *step_row, *step_lanes, *window;
     const int32_t *exp_slot, *exp_ptr;
     const int32_t *chunk_ptr, *chunk_step;  // owner schedule: LDS-staged chunks
+    const int32_t *rem_ptr, *rem_ent;       // owner schedule: cross-group entries per step
     int32_t chunk_rows;
     int32_t in_f64, out_f64;                // vector types of bin / xout
     void *mbox;          // [2][nexp][mbox_stride] values crossing workgroups
@@ -105,6 +106,8 @@ struct TriArgs {
     const int32_t *scatter;
     int32_t row_begin, row_end;  // level-launch row range
     int32_t write_xw;            // persistent: also store every row to xw
+    unsigned long long *trace;   // optional per-step clocks [groups][trace_stride][2]
+    int32_t trace_stride;
 };
 
 // Device copy of one triangular plan.
@@ -116,7 +119,8 @@ struct DevTri {
     int32_t groups = 0, block = 256, max_window = 0, nexp = 0;
     bool unit = false, has_tail = false;
     DevMem ell_col, ell_val, tail_ptr, tail_col, tail_val, dinv, orig;
-    DevMem step_ptr, step_row, step_lanes, window, exp_slot, exp_ptr, chunk_ptr, chunk_step;
+    DevMem step_ptr, step_row, step_lanes, window, exp_slot, exp_ptr, chunk_ptr, chunk_step, rem_ptr, rem_ent;
+    int32_t variant = 0;           // persistent kernel choice (hec_tune_t.kernel_variant)
     int32_t chunk_rows = 0;
     bool max_lanes_one = true;     // every step runs one thread per (row, rhs)
     DevMem epoch, err, mbox;
@@ -124,6 +128,8 @@ struct DevTri {
     std::vector<int32_t> levelptr;  // level-launch bounds (host)
     DevMem xw;                      // workspace [n][ws_R]
     int32_t ws_R = 0;
+    unsigned long long *trace = nullptr;  // caller-owned profiling buffer
+    int32_t trace_stride = 0;
     ~DevTri();
 };
 

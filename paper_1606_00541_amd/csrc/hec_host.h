@@ -4,6 +4,7 @@
 #pragma once
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -66,11 +67,17 @@ struct Schedule {
     std::vector<int32_t> exp_slot;   // [n]: device row -> mailbox slot, or -1
     std::vector<int32_t> exp_ptr;    // [groups+1]: mailbox slots of each group (contiguous)
     int64_t remote_reads = 0;        // dependency entries that cross workgroups
+    int32_t crit_hops = 0;           // most workgroup handoffs along one dependency chain
     // owner schedule: each group's steps are cut into chunks of at most
     // chunk_rows rows whose matrix data is staged in LDS one chunk ahead
-    int32_t chunk_rows = 0;
+    int32_t chunk_rows = 256;
     std::vector<int32_t> chunk_ptr;  // [groups+1] into chunk_step
     std::vector<int32_t> chunk_step; // [2*nchunks]: first step, end step
+    // owner schedule: per step, the cross-group ELL entries as (position in
+    // the chunk's entry grid (row - chunk start) * w + slot index, mailbox slot)
+    std::vector<int32_t> rem_ptr;    // [nsteps+1]
+    std::vector<int32_t> rem_ent;    // [2*nrem]
+    int32_t max_rem_window = 0;      // most entries in any 8 consecutive steps of a group
     int32_t nsteps() const { return (int32_t)step_lanes.size(); }
 };
 
@@ -115,8 +122,12 @@ struct Tune {
     int32_t host_only = 0;
     int32_t max_nrhs = 1;
     int32_t block_threads = 256;
-    int32_t chunk_rows = 0;
+    int32_t chunk_rows = 256;
+    int32_t partition = 0;   // owner parts: 0 auto (grid blocks, else contiguous), 1 contiguous, 2 bisection, 3 grid
+    int32_t variant = 0;     // persistent kernel: 0 auto, 1 generic, 2 owner chunked, 3 owner split waves
 };
+// Tuning with every field at its documented default.
+Tune default_tune();
 Tune tune_from(const hec_tune_t *t);
 
 // Algorithm 1 on one triangle.  `groups_cap` is the largest persistent grid
@@ -126,6 +137,10 @@ void validate_triangle(const Csr &a, bool upper, bool unit);
 Levels compute_levels(const Csr &a, bool upper);
 int32_t auto_ell_width(const Csr &a, bool upper);
 HecHost build_hec(const Csr &a, bool upper, bool unit, const Levels &lv, int32_t w);
+std::vector<int32_t> bisect_parts(const Csr &a, int32_t parts);
+bool detect_grid(const Csr &a, int32_t &nx, int32_t &ny, int32_t &nz);
+std::vector<int32_t> grid_parts(int32_t n, int32_t nx, int32_t ny, int32_t nz, int32_t parts);
+int32_t critical_hops(const Csr &a, bool upper, const std::vector<int32_t> &own);
 // Device facts the schedules are sized by (zeros when unknown / host-only).
 struct DeviceShape {
     int32_t groups_cap = 0;  // co-resident persistent workgroups
@@ -142,6 +157,8 @@ TriHost analyze(const Csr &a, bool upper, bool unit, hec_dtype_t dt, const Tune 
 void ilu0(const Csr &a, Csr &L, Csr &U);
 void iluk(const Csr &a, int32_t k, Csr &L, Csr &U);
 void ilut(const Csr &a, int32_t p, double tau, Csr &L, Csr &U);
+void factor_blocks(const Csr &a, const std::vector<int32_t> &block_ptr,
+                   const std::function<void(const Csr &, Csr &, Csr &)> &fac, Csr &L, Csr &U);
 
 // Restricted Additive Schwarz setup: extended subdomains (ascending global
 // rows) and the block-diagonal matrix of the A_s = A[ext_s, ext_s].

@@ -24,6 +24,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "hec_dev.h"
 
@@ -399,6 +402,9 @@ __global__ void __launch_bounds__(1024) k_owner(TriArgs a)
         for (int s = f; s < e_; ++s) {
             const int rb = a.step_row[2 * s], re = a.step_row[2 * s + 1];
             const int items = (re - rb) * R;
+            const int js = s - a.step_ptr[g];
+            const bool tr = a.trace && tid == 0 && js < a.trace_stride;
+            if (tr) a.trace[2 * ((size_t)g * a.trace_stride + js)] = __builtin_amdgcn_s_memtime();
             for (int t = tid; t < items; t += nt) {
                 const int qq = t / R, k = t - qq * R;
                 const int x = rb + qq, i = x - cr0;
@@ -430,6 +436,7 @@ __global__ void __launch_bounds__(1024) k_owner(TriArgs a)
                 }
             }
             __syncthreads();
+            if (tr) a.trace[2 * ((size_t)g * a.trace_stride + js) + 1] = __builtin_amdgcn_s_memtime();
             if (s_abort) {
                 aborted = true;
                 break;
@@ -487,7 +494,292 @@ OwnerKernel owner_kernel(int w, int rpt, bool unit)
 {
     if (rpt == 1) return owner_kernel_r<T, 1>(w, unit);
     if (rpt == 2) return owner_kernel_r<T, 2>(w, unit);
+    if (rpt == 4) return owner_kernel_r<T, 4>(w, unit);
     return nullptr;
+}
+
+// Owner-schedule kernel with one compute wave and one fetch wave (one RHS).
+// The compute wave only reads LDS, does the arithmetic and issues stores, so
+// it never waits on global memory.  The fetch wave (a) streams each chunk
+// (ELL columns and values, reciprocal diagonal, mailbox slot and scatter
+// target per row, the chunk's step bounds and its cross-group entry list)
+// into a ring of three LDS buffers, and (b) polls the mailbox slots of the
+// cross-group entries of the next steps, up to 64 * kWsPerLane entries at
+// once, writing arrived values into the buffer's staging grid and publishing
+// in LDS the last step whose entries have all arrived.  The compute wave
+// solves step s once that counter reaches s and reports each finished step,
+// which frees buffers for the fetch wave.  All waits in both roles are
+// bounded.
+constexpr int kWsBuffers = 3;
+constexpr int kWsPerLane = 16;
+constexpr int kWsHead = 8;  // ints: first step, end step, first row, first entry, end entry
+
+template <typename T, int W>
+struct WsLayout {
+    size_t win, buf;
+    size_t o_vals, o_dinv, o_stage, o_cols, o_slot, o_dst, o_ent, o_head, o_step;
+    __host__ __device__ WsLayout(int rows, int CH, bool unit)
+    {
+        win = (((size_t)rows * sizeof(T)) + 15) & ~(size_t)15;
+        o_vals = 0;
+        o_dinv = o_vals + (size_t)W * CH * sizeof(T);
+        o_stage = o_dinv + (unit ? 0 : (size_t)CH * sizeof(T));
+        o_cols = o_stage + (size_t)W * CH * sizeof(T);
+        o_slot = o_cols + (size_t)W * CH * sizeof(int);
+        o_dst = o_slot + (size_t)CH * sizeof(int);
+        o_ent = o_dst + (size_t)CH * sizeof(int);
+        o_head = o_ent + 2 * (size_t)W * CH * sizeof(int);
+        o_step = o_head + kWsHead * sizeof(int);
+        buf = (o_step + 3 * (size_t)CH * sizeof(int) + 15) & ~(size_t)15;
+    }
+    __host__ __device__ size_t total() const { return win + kWsBuffers * buf; }
+};
+
+template <typename T, int W, bool UNIT>
+__global__ void __launch_bounds__(128) k_owner_split(TriArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ unsigned s_epoch;
+    __shared__ int s_abort;
+    __shared__ int s_fetched;  // last step whose cross-group values are staged
+    __shared__ int s_done;     // last step the compute wave finished
+    const int g = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n = a.n, CH = a.chunk_rows;
+    const int s0 = a.step_ptr[g], s1 = a.step_ptr[g + 1];
+    const int c0 = a.chunk_ptr[g], c1 = a.chunk_ptr[g + 1];
+    if (tid == 0) {
+        s_epoch = __hip_atomic_load(a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_abort = 0;
+        s_fetched = s0 - 1;
+        s_done = s0 - 1;
+    }
+    __syncthreads();
+    const unsigned par = s_epoch & 1u;
+    T *mbox = static_cast<T *>(a.mbox);
+    const size_t half = (size_t)a.nexp * a.mbox_stride;
+    T *mrd = mbox + (par ? half : 0);
+    const int lo = a.window[2 * g], hi = a.window[2 * g + 1];
+    const WsLayout<T, W> L(hi - lo, CH, UNIT);
+    T *xl = reinterpret_cast<T *>(smem);
+    auto buf = [&](int q) { return smem + L.win + (size_t)((q - c0) % kWsBuffers) * L.buf; };
+    if (a.nexp > 0) {
+        T *other = mbox + (par ? 0 : half);
+        const size_t e0 = (size_t)a.exp_ptr[g] * a.mbox_stride, e1 = (size_t)a.exp_ptr[g + 1] * a.mbox_stride;
+        for (size_t i = e0 + tid; i < e1; i += blockDim.x) other[i] = sentinel<T>();
+    }
+    for (int t = tid; t < hi - lo; t += blockDim.x) {
+        const size_t src = (size_t)a.gather[lo + t];
+        xl[t] = a.in_f64 ? static_cast<T>(static_cast<const double *>(a.bin)[src])
+                         : static_cast<T>(static_cast<const float *>(a.bin)[src]);
+    }
+    __syncthreads();
+    volatile int *v_fetched = &s_fetched;
+    volatile int *v_done = &s_done;
+    volatile int *v_abort = &s_abort;
+    auto raise = [&]() {
+        *v_abort = 1;
+        __hip_atomic_store(a.err_dev, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(a.err_host, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    };
+    if (wave == 1) {
+        // ---------------- fetch wave ----------------
+        const T *ev = static_cast<const T *>(a.ell_val);
+        const T *dv = static_cast<const T *>(a.dinv);
+        int q_next = c0;          // next chunk to load
+        int loaded_end = s0;      // steps below this lie in loaded chunks
+        int pub = s0 - 1;         // last published step
+        int qa = c0;              // chunk holding step pub + 1
+        int e_cur = a.rem_ptr[s0];
+        unsigned idle = 0;
+        while (pub < s1 - 1 && !*v_abort) {
+            // keep chunk qa and the next one resident
+            while (q_next < c1 && q_next <= qa + 1) {
+                if (q_next - c0 >= kWsBuffers) {
+                    const int need = a.chunk_step[2 * (q_next - kWsBuffers) + 1] - 1;
+                    unsigned spins = 0;
+                    while (*v_done < need && !*v_abort) {
+                        if (++spins > kSpinLimit) raise();
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                    if (*v_abort) break;
+                }
+                unsigned char *B = buf(q_next);
+                T *vb = reinterpret_cast<T *>(B + L.o_vals);
+                T *db = reinterpret_cast<T *>(B + L.o_dinv);
+                int *cb = reinterpret_cast<int *>(B + L.o_cols);
+                int *sb = reinterpret_cast<int *>(B + L.o_slot);
+                int *tb = reinterpret_cast<int *>(B + L.o_dst);
+                int *eb = reinterpret_cast<int *>(B + L.o_ent);
+                int *hb = reinterpret_cast<int *>(B + L.o_head);
+                int *pb = reinterpret_cast<int *>(B + L.o_step);
+                const int f = a.chunk_step[2 * q_next], e = a.chunk_step[2 * q_next + 1];
+                const int r0 = a.step_row[2 * f], r1 = a.step_row[2 * (e - 1) + 1];
+                const int x0 = a.rem_ptr[f], x1 = a.rem_ptr[e];
+                for (int i = lane; i < r1 - r0; i += 64) {
+                    const int row = r0 + i;
+#pragma unroll
+                    for (int k = 0; k < W; ++k) {
+                        cb[k * CH + i] = a.ell_col[(size_t)k * a.ld + row];
+                        vb[k * CH + i] = ev[(size_t)k * a.ld + row];
+                    }
+                    if (!UNIT) db[i] = dv[row];
+                    sb[i] = a.exp_slot[row];
+                    tb[i] = a.xout ? a.scatter[row] : -1;
+                }
+                for (int i = lane; i < 2 * (x1 - x0); i += 64) eb[i] = a.rem_ent[2 * x0 + i];
+                for (int i = lane; i < e - f; i += 64) {
+                    pb[3 * i] = a.step_row[2 * (f + i)];
+                    pb[3 * i + 1] = a.step_row[2 * (f + i) + 1];
+                    pb[3 * i + 2] = a.rem_ptr[f + i + 1];
+                }
+                if (lane == 0) {
+                    hb[0] = f;
+                    hb[1] = e;
+                    hb[2] = r0;
+                    hb[3] = x0;
+                    hb[4] = x1;
+                }
+                loaded_end = e;
+                ++q_next;
+            }
+            if (*v_abort) break;
+            // resident chunks qa and (if loaded) qa + 1
+            const int *ha = reinterpret_cast<const int *>(buf(qa) + L.o_head);
+            const bool has_b = qa + 1 < q_next;
+            const int *hbn = reinterpret_cast<const int *>(buf(qa + 1) + L.o_head);
+            const int ent_split = has_b ? hbn[3] : ha[4];
+            const int e_lim = has_b ? hbn[4] : ha[4];
+            const int e_end = min(e_cur + 64 * kWsPerLane, e_lim);
+            int first_pending = e_end;
+#pragma unroll
+            for (int j = 0; j < kWsPerLane; ++j) {
+                const int idx = e_cur + lane + 64 * j;
+                if (idx < e_end) {
+                    const bool in_b = idx >= ent_split;
+                    unsigned char *B = in_b ? buf(qa + 1) : buf(qa);
+                    const int li = idx - (in_b ? hbn[3] : ha[3]);
+                    const int *eb = reinterpret_cast<const int *>(B + L.o_ent);
+                    const int pos = eb[2 * li], slot = eb[2 * li + 1];
+                    const T v = __hip_atomic_load(mrd + (size_t)slot * a.mbox_stride, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+                    if (is_sentinel(v)) first_pending = min(first_pending, idx);
+                    else reinterpret_cast<T *>(B + L.o_stage)[pos] = v;
+                }
+            }
+            for (int off = 32; off > 0; off >>= 1) first_pending = min(first_pending, __shfl_xor(first_pending, off));
+            // publish every step whose entries all lie before first_pending
+            int np = pub;
+            for (;;) {
+                const int s = np + 1;
+                if (s >= loaded_end) break;
+                const int *hs = (s < ha[1]) ? ha : hbn;
+                const int *ps = reinterpret_cast<const int *>(reinterpret_cast<const unsigned char *>(hs) - L.o_head +
+                                                              L.o_step);
+                if (ps[3 * (s - hs[0]) + 2] > first_pending) break;
+                np = s;
+            }
+            e_cur = first_pending;
+            if (np > pub) {
+                pub = np;
+                if (lane == 0) *v_fetched = pub;
+                idle = 0;
+                while (qa + 1 < q_next && a.chunk_step[2 * qa + 1] <= pub + 1) ++qa;
+            } else {
+                if (++idle > kSpinLimit) {
+                    raise();
+                    break;
+                }
+                if ((idle & 255u) == 0 && __hip_atomic_load(a.err_dev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                    *v_abort = 1;
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+    } else {
+        // ---------------- compute wave ----------------
+        int q = c0;
+        const unsigned char *B = buf(q);
+        const int *hb = reinterpret_cast<const int *>(B + L.o_head);
+        for (int s = s0; s < s1; ++s) {
+            const bool tr = a.trace && lane == 0 && (s - s0) < a.trace_stride;
+            if (tr) a.trace[2 * ((size_t)g * a.trace_stride + (s - s0))] = __builtin_amdgcn_s_memtime();
+            unsigned spins = 0;
+            while (*v_fetched < s) {
+                if (*v_abort) break;
+                if (++spins > (kSpinLimit << 4)) {
+                    raise();
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            if (*v_abort) break;
+            if (s >= hb[1]) {  // next chunk (its header is valid once step s is published)
+                ++q;
+                B = buf(q);
+                hb = reinterpret_cast<const int *>(B + L.o_head);
+            }
+            const T *vb = reinterpret_cast<const T *>(B + L.o_vals);
+            const T *db = reinterpret_cast<const T *>(B + L.o_dinv);
+            const T *st = reinterpret_cast<const T *>(B + L.o_stage);
+            const int *cb = reinterpret_cast<const int *>(B + L.o_cols);
+            const int *sb = reinterpret_cast<const int *>(B + L.o_slot);
+            const int *tb = reinterpret_cast<const int *>(B + L.o_dst);
+            const int *pb = reinterpret_cast<const int *>(B + L.o_step);
+            const int cr0 = hb[2];
+            const int js = s - hb[0];
+            const int rb = pb[3 * js], re = pb[3 * js + 1];
+            for (int x = rb + lane; x < re; x += 64) {
+                const int i = x - cr0;
+                T sv = xl[x - lo];
+#pragma unroll
+                for (int k = 0; k < W; ++k) {
+                    const int c = cb[k * CH + i];
+                    if (c != n) sv -= vb[k * CH + i] * (c > n ? st[i * W + k] : xl[c - lo]);
+                }
+                if (!UNIT) sv *= db[i];
+                xl[x - lo] = sv;
+                if (a.write_xw) static_cast<T *>(a.xw)[x] = sv;
+                const int slot = sb[i];
+                if (slot >= 0)
+                    __hip_atomic_store(mrd + (size_t)slot * a.mbox_stride, sv, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                const int dst = tb[i];
+                if (dst >= 0) {
+                    if (a.out_f64) static_cast<double *>(a.xout)[dst] = static_cast<double>(sv);
+                    else static_cast<float *>(a.xout)[dst] = static_cast<float>(sv);
+                }
+            }
+            if (tr) a.trace[2 * ((size_t)g * a.trace_stride + (s - s0)) + 1] = __builtin_amdgcn_s_memtime();
+            if (lane == 0) *v_done = s;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const unsigned done = __hip_atomic_fetch_add(&a.epoch[1], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (done == gridDim.x - 1) {
+            __hip_atomic_store(&a.epoch[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.epoch[0], s_epoch + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+template <typename T>
+OwnerKernel split_kernel(int w, bool unit, size_t &lds, int rows, int CH)
+{
+    switch (w) {
+#define HEC_SPLIT_CASE(WW)                                                                              \
+    case WW:                                                                                            \
+        lds = WsLayout<T, WW>(rows, CH, unit).total();                                                  \
+        return unit ? k_owner_split<T, WW, true> : k_owner_split<T, WW, false>;
+        HEC_SPLIT_CASE(1)
+        HEC_SPLIT_CASE(2)
+        HEC_SPLIT_CASE(3)
+        HEC_SPLIT_CASE(4)
+        HEC_SPLIT_CASE(5)
+        HEC_SPLIT_CASE(6)
+#undef HEC_SPLIT_CASE
+    default: return nullptr;
+    }
 }
 
 template <typename T>
@@ -512,8 +804,18 @@ void launch_typed(DevTri &d, TriArgs a, hipStream_t st)
         hip_check(hipGetLastError(), "k_level launch");
         return;
     }
-    if (d.kind == HEC_SCHED_OWNER_PERSISTENT && !d.has_tail && d.max_lanes_one && d.w >= 1 && d.w <= 8 &&
-        d.chunk_rows > 0 && d.chunk_rows % d.block == 0) {
+    if (d.kind == HEC_SCHED_OWNER_PERSISTENT && d.variant == 3 && a.R == 1 && !d.has_tail && d.max_lanes_one &&
+        d.w >= 1 && d.w <= 6 && d.chunk_rows > 0) {
+        size_t lds = 0;
+        OwnerKernel k = split_kernel<T>(d.w, d.unit, lds, d.max_window, d.chunk_rows);
+        if (k && lds <= (size_t)device_max_lds() && capacity_of((const void *)k, 128, lds) >= d.groups) {
+            hipLaunchKernelGGL(k, dim3(d.groups), dim3(128), lds, st, a);
+            hip_check(hipGetLastError(), "k_owner_split launch");
+            return;
+        }
+    }
+    if (d.kind == HEC_SCHED_OWNER_PERSISTENT && (d.variant == 0 || d.variant >= 2) && !d.has_tail &&
+        d.max_lanes_one && d.w >= 1 && d.w <= 8 && d.chunk_rows > 0 && d.chunk_rows % d.block == 0) {
         const int rpt = d.chunk_rows / d.block;
         OwnerKernel k = owner_kernel<T>(d.w, rpt, d.unit);
         const size_t lds = owner_lds_bytes(d.max_window, a.R, d.w, d.chunk_rows, d.unit, sizeof(T));
@@ -553,16 +855,39 @@ void launch_in(DevTri &d, const TriArgs &a, hec_dtype_t in_dt, hec_dtype_t out_d
     }
 }
 
-// Co-resident workgroups of one kernel instance on the current device.
+// Co-resident workgroups of one kernel instance on the current device
+// (cached: the occupancy query and the LDS attribute are set once per
+// kernel, block size, LDS size and device).
 int32_t capacity_of(const void *kern, int32_t block, size_t lds)
 {
-    int dev = 0, cus = 0, per = 0;
+    struct Key {
+        const void *k;
+        int32_t block;
+        size_t lds;
+        int dev;
+        bool operator<(const Key &o) const
+        {
+            return std::tie(k, block, lds, dev) < std::tie(o.k, o.block, o.lds, o.dev);
+        }
+    };
+    static std::mutex mu;
+    static std::map<Key, int32_t> cache;
+    int dev = 0;
     hip_check(hipGetDevice(&dev), "hipGetDevice");
+    const Key key{kern, block, lds, dev};
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    int cus = 0, per = 0;
     hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "attr CUs");
     if (lds > 0)
         hip_check(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
                   "hipFuncSetAttribute");
     hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, block, lds), "occupancy");
+    std::lock_guard<std::mutex> g(mu);
+    cache[key] = per * cus;
     return per * cus;
 }
 
@@ -584,21 +909,27 @@ int32_t persistent_capacity(hec_dtype_t dt, int32_t block, size_t lds)
     return lds ? capacity_all<float, true>(block, lds) : capacity_all<float, false>(block, 0);
 }
 
-int32_t device_cus()
+namespace {
+int32_t device_attr(hipDeviceAttribute_t attr)
 {
-    int dev = 0, cus = 0;
+    static std::mutex mu;
+    static std::map<std::pair<int, int>, int32_t> cache;
+    int dev = 0;
     hip_check(hipGetDevice(&dev), "hipGetDevice");
-    hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "attr CUs");
-    return cus;
-}
-
-int32_t device_max_lds()
-{
-    int dev = 0, v = 0;
-    hip_check(hipGetDevice(&dev), "hipGetDevice");
-    hip_check(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "attr LDS");
+    std::lock_guard<std::mutex> g(mu);
+    auto key = std::make_pair(dev, (int)attr);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int v = 0;
+    hip_check(hipDeviceGetAttribute(&v, attr, dev), "hipDeviceGetAttribute");
+    cache[key] = v;
     return v;
 }
+}  // namespace
+
+int32_t device_cus() { return device_attr(hipDeviceAttributeMultiprocessorCount); }
+
+int32_t device_max_lds() { return device_attr(hipDeviceAttributeMaxSharedMemoryPerBlock); }
 
 void fill_sentinel(void *p, size_t count, hec_dtype_t dt)
 {
@@ -646,8 +977,12 @@ void launch_tri(DevTri &d, const void *bin, hec_dtype_t in_dt, const int32_t *ga
     a.scatter = scatter;
     a.write_xw = xout ? 0 : 1;
     a.chunk_ptr = d.chunk_ptr.as<int32_t>();
+    a.rem_ptr = d.rem_ptr.as<int32_t>();
+    a.rem_ent = d.rem_ent.as<int32_t>();
     a.chunk_step = d.chunk_step.as<int32_t>();
     a.chunk_rows = d.chunk_rows;
+    a.trace = d.trace;
+    a.trace_stride = d.trace_stride;
     a.in_f64 = in_dt == HEC_F64 ? 1 : 0;
     a.out_f64 = out_dt == HEC_F64 ? 1 : 0;
     if (d.dt == HEC_F64) launch_in<double>(d, a, in_dt, out_dt, st);

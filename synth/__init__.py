@@ -104,10 +104,8 @@ def _stencil_matrix(shape, kappa=None) -> CSR:
         else:
             ka, kb = kappa[lo], kappa[hi]
             c = 2.0 * ka * kb / (ka + kb)
-            np.add.at(diag, lo, c)
-            np.add.at(diag, hi, c)
-            np.add.at(nfaces_int, lo, 1.0)
-            np.add.at(nfaces_int, hi, 1.0)
+            diag += np.bincount(lo, weights=c, minlength=n) + np.bincount(hi, weights=c, minlength=n)
+            nfaces_int += np.bincount(lo, minlength=n) + np.bincount(hi, minlength=n)
         rows += [lo, hi]
         cols += [hi, lo]
         vals += [-c, -c]

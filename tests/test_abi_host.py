@@ -43,6 +43,13 @@ def test_tune_defaults_and_validation():
     assert e.value.name == "INVALID_ARG"
     with pytest.raises(H.HecError):
         H.tri_analyze(L, tune=H.tune_default(host_only=1, group_lanes=3))
+    with pytest.raises(H.HecError):
+        H.tri_analyze(L, tune=H.tune_default(host_only=1, kernel_variant=4))
+    with pytest.raises(H.HecError):
+        H.tri_analyze(L, tune=H.tune_default(host_only=1, block_threads=256, chunk_rows=768))
+    # an owner plan with the default chunk size builds (steps are cut to chunks)
+    p = H.tri_analyze(L, tune=H.tune_default(host_only=1, schedule="owner_persistent", chunk_rows=0))
+    assert H.tri_plan_stats(p)["nsteps"] > 0
 
 
 def _transpose(T):
@@ -166,3 +173,26 @@ def test_ras_layout_matches_oracle():
     nsub, tot, sizes = H.ras_info(s)
     assert nsub == 5 and tot == sum(len(d.ext) for d in doms)
     assert list(sizes) == [len(d.ext) for d in doms]
+
+
+def test_owner_partitions():
+    A = synth.poisson3d(24)
+    L, _ = oracle.ilu0(A)
+    stats = {}
+    for part in (1, 2, 3):
+        t = H.tune_default(host_only=1, schedule="owner_persistent", partition=part, num_groups=64)
+        stats[part] = H.tri_plan_stats(H.tri_analyze(L, unit_diag=True, tune=t))
+    # grid blocks: far fewer group-to-group handoffs and exported rows than slabs
+    assert stats[3]["crit_hops"] < stats[1]["crit_hops"] // 2
+    assert stats[3]["nexport"] < stats[1]["nexport"] // 2
+    # auto picks grid blocks for a stencil matrix
+    auto = H.tri_plan_stats(H.tri_analyze(L, unit_diag=True, tune=H.tune_default(
+        host_only=1, schedule="owner_persistent", num_groups=64)))
+    assert auto["crit_hops"] == stats[3]["crit_hops"]
+    # an unstructured matrix falls back to contiguous parts
+    R = synth.random_lower(3000, 0.002, seed=3)
+    a1 = H.tri_plan_stats(H.tri_analyze(R, tune=H.tune_default(host_only=1, schedule="owner_persistent",
+                                                               num_groups=16)))
+    c1 = H.tri_plan_stats(H.tri_analyze(R, tune=H.tune_default(host_only=1, schedule="owner_persistent",
+                                                               num_groups=16, partition=1)))
+    assert a1["crit_hops"] == c1["crit_hops"] and a1["nexport"] == c1["nexport"]

@@ -172,3 +172,25 @@ def test_owner_chunked_kernel_bit_identical_to_level_launch(block, chunk, nrhs, 
     for rep in range(3):  # alternating mailbox halves
         assert np.array_equal(solve(pl, b), solve(ref_plan_l, b))
         assert np.array_equal(solve(pu, b, upper=True), solve(ref_plan_u, b, upper=True))
+
+
+def test_autotune_returns_a_working_tuning():
+    A = synth.poisson3d(24)
+    L, U = oracle.ilu0(A)
+    best, us = H.tri_autotune(U, "upper", nrhs=2)
+    assert us > 0 and best.schedule in (2, 3) and best.max_nrhs == 2
+    p = H.tri_analyze(U, "upper", tune=best)
+    b = synth.rhs(A.n, 2, 3)
+    assert relerr(solve(p, b, upper=True), oracle.upper_solve(U, b)) <= FP64_TOL
+
+
+def test_mailbox_recovers_across_rhs_widths():
+    # a plan used with growing then shrinking RHS counts keeps its mailbox
+    # halves consistent (resets cover the widest layout ever allocated)
+    A = synth.poisson3d(20)
+    L, _ = oracle.ilu0(A)
+    for sched in ("level_persistent", "owner_persistent"):
+        p = H.tri_analyze(L, "lower", unit_diag=True, tune=H.tune_default(schedule=sched))
+        for R in (1, 4, 1, 2, 4, 1):
+            b = synth.rhs(A.n, R, R)
+            assert relerr(solve(p, b), oracle.lower_solve(L, b, unit=True)) <= FP64_TOL
