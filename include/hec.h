@@ -195,10 +195,14 @@ hec_status_t tri_plan_stats(tri_plan_t plan, tri_stats_t *stats);
 hec_status_t tri_plan_layout(tri_plan_t plan, int32_t *xperm, int32_t *owner);
 
 /* Profiling hook: while `trace` is non-NULL, persistent launches of this plan
- * write, for workgroup g and its j-th step, the shader clock at the step's
- * start and end to trace[2*(g*stride + j)] and trace[2*(g*stride + j) + 1]
+ * write, for workgroup g and its j-th step, the device's constant-rate
+ * real-time counter (100 MHz on gfx950, one time base for all CUs) at the
+ * step's start and end to trace[2*(g*stride + j)] and trace[2*(g*stride + j) + 1]
  * (uint64, device memory of 2*groups*stride entries owned by the caller); steps
- * beyond `stride` are not recorded.  Pass NULL to stop tracing. */
+ * beyond `stride` are not recorded.  The dataflow kernel keeps entry stride-1
+ * of each workgroup for the times its set-up ended and its last step finished
+ * (steps beyond stride-1 are not recorded) and needs 16 bytes of LDS per
+ * recorded step.  Pass NULL to stop tracing. */
 hec_status_t tri_plan_trace(tri_plan_t plan, void *trace, int32_t stride);
 
 /* Solve L x = b (Algorithm 2): b is gathered into level order, the levels are

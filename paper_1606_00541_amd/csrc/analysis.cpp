@@ -41,7 +41,7 @@ Tune tune_from(const hec_tune_t *t)
     u.chunk_rows = t->chunk_rows > 0 ? t->chunk_rows : std::max(256, u.block_threads);
     u.partition = t->partition;
     u.variant = t->kernel_variant;
-    if (u.variant < 0 || u.variant > 3) fail(HEC_ERR_INVALID_ARG, "tune.kernel_variant out of range");
+    if (u.variant < 0 || u.variant > 4) fail(HEC_ERR_INVALID_ARG, "tune.kernel_variant out of range");
     if (u.partition < 0 || u.partition > 3) fail(HEC_ERR_INVALID_ARG, "tune.partition out of range");
     if (u.schedule < HEC_SCHED_AUTO || u.schedule > HEC_SCHED_OWNER_PERSISTENT)
         fail(HEC_ERR_INVALID_ARG, "tune.schedule out of range");
@@ -565,6 +565,110 @@ int32_t critical_hops(const Csr &a, bool upper, const std::vector<int32_t> &own)
     return best;
 }
 
+size_t dataflow_lds_bytes(int32_t rows, int32_t ints, int32_t R, size_t tsize)
+{
+    const size_t vals = (size_t)rows * R * tsize;
+    return ((vals + 15) & ~(size_t)15) + (((size_t)ints * 4 + 15) & ~(size_t)15);
+}
+
+namespace {
+
+// Prepare an owner schedule for the dataflow kernel.  Each group's exported
+// rows get their mailbox slots in level order and each group numbers the
+// slots it reads in level order of their first consumer: the kernel's export
+// and import wavefronts walk these lists in order, and a list ordered by
+// level never waits on an entry whose producer depends on a later entry.
+// Then every column becomes a row of the group's LDS value area.
+void make_dataflow(Schedule &s, ExecHost &ex, const std::vector<int32_t> &xlev,
+                   const std::vector<std::vector<int32_t>> &run_wave, int32_t waves)
+{
+    const int32_t G = s.groups, n = ex.n;
+    auto each_col = [&](int32_t x, const std::function<void(int32_t &)> &f) {
+        for (int32_t e = 0; e < ex.w; ++e) f(ex.ell_col[(size_t)e * ex.ld + x]);
+        if (!ex.tail_ptr.empty())
+            for (int32_t p = ex.tail_ptr[x]; p < ex.tail_ptr[x + 1]; ++p) f(ex.tail_col[p]);
+    };
+    // 1. export slots in level order within each group
+    std::vector<int32_t> remap((size_t)s.nexp, -1);
+    for (int32_t g = 0; g < G; ++g) {
+        std::vector<int32_t> rows;
+        for (int32_t x = s.window[2 * g]; x < s.window[2 * g + 1]; ++x)
+            if (s.exp_slot[x] >= 0) rows.push_back(x);
+        std::stable_sort(rows.begin(), rows.end(), [&](int32_t p, int32_t q) { return xlev[p] < xlev[q]; });
+        for (size_t k = 0; k < rows.size(); ++k) remap[s.exp_slot[rows[k]]] = s.exp_ptr[g] + (int32_t)k;
+    }
+    for (int32_t x = 0; x < n; ++x) {
+        if (s.exp_slot[x] >= 0) s.exp_slot[x] = remap[s.exp_slot[x]];
+        each_col(x, [&](int32_t &c) {
+            if (c > n) c = n + 1 + remap[c - n - 1];
+        });
+    }
+    s.exp_row.assign((size_t)s.nexp, 0);
+    for (int32_t x = 0; x < n; ++x)
+        if (s.exp_slot[x] >= 0) s.exp_row[s.exp_slot[x]] = x;
+    // 2. imports per group, ordered by the level of their first consumer
+    s.imp_ptr.assign((size_t)G + 1, 0);
+    s.imp_slot.clear();
+    s.max_imp = 0;
+    std::vector<int32_t> first_lev((size_t)s.nexp, INT32_MAX), stamp((size_t)s.nexp, -1), local((size_t)s.nexp, -1);
+    for (int32_t g = 0; g < G; ++g) {
+        std::vector<int32_t> slots;
+        for (int32_t x = s.window[2 * g]; x < s.window[2 * g + 1]; ++x)
+            each_col(x, [&](int32_t &c) {
+                if (c <= n) return;
+                const int32_t slot = c - n - 1;
+                if (stamp[slot] != g) {
+                    stamp[slot] = g;
+                    first_lev[slot] = xlev[x];
+                    slots.push_back(slot);
+                } else {
+                    first_lev[slot] = std::min(first_lev[slot], xlev[x]);
+                }
+            });
+        std::stable_sort(slots.begin(), slots.end(),
+                         [&](int32_t p, int32_t q) { return first_lev[p] < first_lev[q]; });
+        s.imp_ptr[g] = (int32_t)s.imp_slot.size();
+        for (size_t k = 0; k < slots.size(); ++k) {
+            local[slots[k]] = (int32_t)k;
+            s.imp_slot.push_back(slots[k]);
+        }
+        s.imp_ptr[g + 1] = (int32_t)s.imp_slot.size();
+        const int32_t ni = s.imp_ptr[g + 1] - s.imp_ptr[g];
+        s.max_imp = std::max(s.max_imp, ni);
+        s.df_rows = std::max(s.df_rows, 2 * (s.window[2 * g + 1] - s.window[2 * g]) + ni + 1);
+        s.df_ints = std::max(s.df_ints, ni + (s.exp_ptr[g + 1] - s.exp_ptr[g]) +
+                                            2 * (s.step_ptr[g + 1] - s.step_ptr[g]));
+        // 3. columns become rows of the group's LDS value area: its own rows
+        // 0..win-1, imports from 2*win (after the right-hand-side copy), and a
+        // zero row 2*win + nimp for ELL padding (padding then subtracts 0 * 0,
+        // which leaves every value unchanged, so no test is needed)
+        const int32_t lo = s.window[2 * g], hi = s.window[2 * g + 1], win = hi - lo;
+        for (int32_t x = lo; x < hi; ++x)
+            each_col(x, [&](int32_t &c) {
+                if (c < n) c -= lo;
+                else if (c == n) c = 2 * win + ni;
+                else c = 2 * win + local[c - n - 1];
+            });
+    }
+    // 4. the steps of each group's wavefronts (contiguous, in wavefront order)
+    s.df_waves = waves;
+    s.wave_ptr.assign((size_t)G * waves + 1, 0);
+    for (int32_t g = 0; g < G; ++g) {
+        const int32_t s0 = s.step_ptr[g], ns = s.step_ptr[g + 1] - s0;
+        if ((int32_t)run_wave[g].size() != ns) fail(HEC_ERR_INVALID_ARG, "internal: wavefront list mismatch");
+        int32_t k = 0;
+        for (int32_t w2 = 0; w2 < waves; ++w2) {
+            s.wave_ptr[(size_t)g * waves + w2] = s0 + k;
+            while (k < ns && run_wave[g][k] == w2) ++k;
+        }
+        if (k != ns) fail(HEC_ERR_INVALID_ARG, "internal: wavefront pieces out of order");
+    }
+    s.wave_ptr[(size_t)G * waves] = s.step_ptr[G];
+    s.dataflow = true;
+}
+
+}  // namespace
+
 void build_exec(TriHost &t, const Csr &a, const Tune &tune, const DeviceShape &dev,
                 const std::vector<int32_t> *sys_ptr)
 {
@@ -591,6 +695,10 @@ void build_exec(TriHost &t, const Csr &a, const Tune &tune, const DeviceShape &d
     G = std::max(1, G);
     const int32_t R = std::max(1, tune.max_nrhs);
     const int32_t merge = tune.merge_rows > 0 ? tune.merge_rows : std::max(1, tune.block_threads / R);
+    // the dataflow owner kernel: one wavefront per piece of a part
+    const bool want_df = kind == HEC_SCHED_OWNER_PERSISTENT && tune.variant == 4;
+    const int32_t df_waves = std::max(1, tune.block_threads / 64);
+    std::vector<std::vector<int32_t>> run_wave;  // dataflow: wavefront of each run
 
     // 1. device-row order and owner of each row
     ex.xord.resize(n);
@@ -643,23 +751,37 @@ void build_exec(TriHost &t, const Csr &a, const Tune &tune, const DeviceShape &d
             members[part_of[i]].push_back(i);
         }
         runs.assign(parts, {});
+        run_wave.assign(parts, {});
         int32_t x = 0;
         for (int32_t g = 0; g < parts; ++g) {
-            // rows of the part in level order, ties by problem index
+            // rows of the part in level order, ties by problem index.  For the
+            // dataflow kernel the part is first cut into one contiguous piece
+            // (in problem order) per compute wavefront, each in level order:
+            // a wavefront then walks its own piece, and only dependencies
+            // between pieces need a wait.
             std::vector<int32_t> &rows = members[g];
-            std::stable_sort(rows.begin(), rows.end(),
-                             [&](int32_t i, int32_t j) { return lv.level[i] < lv.level[j]; });
-            int32_t start = x;
-            for (size_t u = 0; u < rows.size(); ++u) {
-                ex.xord[x] = lv.iperm[rows[u]];
-                ex.owner[x] = g;
-                if (u > 0 && lv.level[rows[u]] != lv.level[rows[u - 1]]) {
-                    runs[g].push_back({start, x});
-                    start = x;
+            const int32_t pieces = want_df ? df_waves : 1;
+            const size_t m = rows.size();
+            for (int32_t w2 = 0; w2 < pieces; ++w2) {
+                const size_t pb = m * w2 / pieces, pe = m * (w2 + 1) / pieces;
+                std::stable_sort(rows.begin() + pb, rows.begin() + pe,
+                                 [&](int32_t i, int32_t j) { return lv.level[i] < lv.level[j]; });
+                int32_t start = x;
+                for (size_t u = pb; u < pe; ++u) {
+                    ex.xord[x] = lv.iperm[rows[u]];
+                    ex.owner[x] = g;
+                    if (u > pb && lv.level[rows[u]] != lv.level[rows[u - 1]]) {
+                        runs[g].push_back({start, x});
+                        run_wave[g].push_back(w2);
+                        start = x;
+                    }
+                    ++x;
                 }
-                ++x;
+                if (x > start) {
+                    runs[g].push_back({start, x});
+                    run_wave[g].push_back(w2);
+                }
             }
-            if (x > start) runs[g].push_back({start, x});
         }
         // Consecutive parts depend on each other; give them workgroups that
         // share an L2 domain (workgroup i runs on domain i % xcds), so that
@@ -670,8 +792,13 @@ void build_exec(TriHost &t, const Csr &a, const Tune &tune, const DeviceShape &d
             std::vector<int32_t> gid(parts);
             for (int32_t p = 0; p < parts; ++p) gid[p] = (p % per) * X + p / per;
             std::vector<std::vector<std::pair<int32_t, int32_t>>> relabeled(parts);
-            for (int32_t p = 0; p < parts; ++p) relabeled[gid[p]] = std::move(runs[p]);
+            std::vector<std::vector<int32_t>> rw(parts);
+            for (int32_t p = 0; p < parts; ++p) {
+                relabeled[gid[p]] = std::move(runs[p]);
+                rw[gid[p]] = std::move(run_wave[p]);
+            }
             runs.swap(relabeled);
+            run_wave.swap(rw);
             for (int32_t x2 = 0; x2 < n; ++x2) ex.owner[x2] = gid[ex.owner[x2]];
         }
     }
@@ -711,20 +838,44 @@ void build_exec(TriHost &t, const Csr &a, const Tune &tune, const DeviceShape &d
     // 3. schedule
     ex.sched = Schedule();
     ex.sched.kind = kind;
+    // the dataflow owner kernel runs each step as one wavefront's unit (at
+    // most 64 (row, rhs) items); the other owner kernels cut steps to chunks
+    if (want_df && w > 8) fail(HEC_ERR_INVALID_ARG, "dataflow kernel: ELL width above 8");
+    if (want_df && R > 64) fail(HEC_ERR_INVALID_ARG, "dataflow kernel: max_nrhs above 64");
+    if (want_df && tune.block_threads > 640)
+        fail(HEC_ERR_INVALID_ARG, "dataflow kernel: block_threads above 640 (two more wavefronts are added)");
     if (kind == HEC_SCHED_OWNER_PERSISTENT) {
-        if (tune.chunk_rows <= 0) fail(HEC_ERR_INVALID_ARG, "internal: chunk_rows must be positive");
-        // a step never exceeds one chunk: cut longer levels into pieces (rows
-        // of one level are independent, so the extra barrier is harmless)
-        for (auto &gr : runs) {
+        const int32_t piece = want_df ? std::max(1, 64 / R) : tune.chunk_rows;
+        if (piece <= 0) fail(HEC_ERR_INVALID_ARG, "internal: chunk_rows must be positive");
+        // cut longer levels into pieces (rows of one level are independent)
+        for (size_t g = 0; g < runs.size(); ++g) {
             std::vector<std::pair<int32_t, int32_t>> cut;
-            for (auto &r : gr)
-                for (int32_t b = r.first; b < r.second; b += tune.chunk_rows)
-                    cut.push_back({b, std::min(r.second, b + tune.chunk_rows)});
-            gr.swap(cut);
+            std::vector<int32_t> cw;
+            for (size_t k = 0; k < runs[g].size(); ++k) {
+                const auto &r = runs[g][k];
+                for (int32_t b = r.first; b < r.second; b += piece) {
+                    cut.push_back({b, std::min(r.second, b + piece)});
+                    if (want_df) cw.push_back(run_wave[g][k]);
+                }
+            }
+            runs[g].swap(cut);
+            if (want_df) run_wave[g].swap(cw);
         }
     }
     if (kind != HEC_SCHED_LEVEL_LAUNCH) {
-        finish_schedule(ex.sched, ex, runs, tune);
+        Tune tu = tune;
+        if (want_df) tu.group_lanes = 1;  // one lane per (row, rhs): tails are summed serially
+        finish_schedule(ex.sched, ex, runs, tu);
+        if (want_df) {
+            std::vector<int32_t> xlev(n);
+            for (int32_t x2 = 0; x2 < n; ++x2) xlev[x2] = lv.level[ex.orig[x2]];
+            make_dataflow(ex.sched, ex, xlev, run_wave, df_waves);
+            const size_t lds_cap = dev.lds > 0 ? (size_t)dev.lds : 163840;
+            const size_t need = dataflow_lds_bytes(ex.sched.df_rows, ex.sched.df_ints, R, t.dt == HEC_F64 ? 8 : 4);
+            if (need > lds_cap)
+                fail(HEC_ERR_CAPACITY, "dataflow kernel: a group needs " + std::to_string(need) +
+                                           " bytes of LDS (use more groups or fewer right-hand sides)");
+        }
         std::vector<int32_t> own(n);
         for (int32_t x2 = 0; x2 < n; ++x2) own[ex.orig[x2]] = ex.owner[x2];
         ex.sched.crit_hops = critical_hops(a, t.upper, own);
@@ -742,6 +893,11 @@ TriHost analyze(const Csr &a, bool upper, bool unit, hec_dtype_t dt, const Tune 
     t.dt = dt;
     t.lev = compute_levels(a, upper);
     int32_t w = tune.ell_width >= 0 ? tune.ell_width : auto_ell_width(a, upper);
+    // the dataflow kernel holds 1 to 8 ELL slots per row in registers
+    if (tune.variant == 4 && tune.schedule == HEC_SCHED_OWNER_PERSISTENT) {
+        if (tune.ell_width < 0) w = std::min(w, 8);
+        w = std::max(w, 1);
+    }
     t.hec = build_hec(a, upper, unit, t.lev, w);
     int64_t off = 0;
     for (int32_t i = 0; i < a.n; ++i) off += offdiag_count(a, i);

@@ -115,6 +115,23 @@ void upload_tri(DevTri &d, const TriHost &t, int32_t max_nrhs)
         if (re.empty()) re.assign(2, 0);
         upload(d.rem_ent, re);
         d.chunk_rows = s.chunk_rows;
+        d.dataflow = s.dataflow;
+        if (s.dataflow) {
+            upload(d.imp_ptr, s.imp_ptr);
+            std::vector<int32_t> v = s.imp_slot;
+            if (v.empty()) v.assign(1, 0);
+            upload(d.imp_slot, v);
+            v = s.exp_row;
+            if (v.empty()) v.assign(1, 0);
+            upload(d.exp_row, v);
+            d.df_rows = s.df_rows;
+            d.df_ints = s.df_ints;
+            d.df_waves = s.df_waves;
+            upload(d.wave_ptr, s.wave_ptr);
+            d.df_step_rows = 0;
+            for (int32_t q = 0; q < s.nsteps(); ++q)
+                d.df_step_rows = std::max(d.df_step_rows, s.step_row[2 * q + 1] - s.step_row[2 * q]);
+        }
         d.max_lanes_one = std::all_of(s.step_lanes.begin(), s.step_lanes.end(), [](int32_t v) { return v == 1; });
         d.epoch.alloc(2 * sizeof(unsigned int));
         hip_check(hipMemset(d.epoch.p, 0, d.epoch.bytes), "hipMemset");
@@ -189,6 +206,7 @@ DeviceShape device_shape(const Tune &tu, hec_dtype_t dt)
     s.groups_cap = persistent_capacity(dt, tu.block_threads, 0);
     s.cus = device_cus();
     s.xcds = 8;
+    s.lds = device_max_lds();
     return s;
 }
 

@@ -92,6 +92,8 @@ struct TriArgs {
     const int32_t *exp_slot, *exp_ptr;
     const int32_t *chunk_ptr, *chunk_step;  // owner schedule: LDS-staged chunks
     const int32_t *rem_ptr, *rem_ent;       // owner schedule: cross-group entries per step
+    const int32_t *imp_ptr, *imp_slot, *exp_row;  // dataflow owner kernel: imports and exports
+    const int32_t *wave_ptr;                      // dataflow owner kernel: steps per wavefront
     int32_t chunk_rows;
     int32_t in_f64, out_f64;                // vector types of bin / xout
     void *mbox;          // [2][nexp][mbox_stride] values crossing workgroups
@@ -121,6 +123,11 @@ struct DevTri {
     DevMem ell_col, ell_val, tail_ptr, tail_col, tail_val, dinv, orig;
     DevMem step_ptr, step_row, step_lanes, window, exp_slot, exp_ptr, chunk_ptr, chunk_step, rem_ptr, rem_ent;
     int32_t variant = 0;           // persistent kernel choice (hec_tune_t.kernel_variant)
+    bool dataflow = false;         // columns encode group-local imports (dataflow kernel only)
+    DevMem imp_ptr, imp_slot, exp_row, wave_ptr;
+    int32_t df_waves = 0;          // compute wavefronts per group (block = 64 * df_waves + 128)
+    int32_t df_rows = 0, df_ints = 0;
+    int32_t df_step_rows = 0;      // longest step (one wavefront covers step rows x nrhs)
     int32_t chunk_rows = 0;
     bool max_lanes_one = true;     // every step runs one thread per (row, rhs)
     DevMem epoch, err, mbox;

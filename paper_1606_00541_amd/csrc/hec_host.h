@@ -78,6 +78,20 @@ struct Schedule {
     std::vector<int32_t> rem_ptr;    // [nsteps+1]
     std::vector<int32_t> rem_ent;    // [2*nrem]
     int32_t max_rem_window = 0;      // most entries in any 8 consecutive steps of a group
+    // dataflow owner kernel: every step is one wavefront's unit of rows of one
+    // level; a column is a row of the group's LDS value area (own rows, then
+    // imports after the right-hand-side copy, then a zero row for padding).
+    // Import j of group g reads mailbox slot imp_slot[imp_ptr[g] + j]
+    // (imports ordered by first use, so in level order).
+    bool dataflow = false;
+    std::vector<int32_t> imp_ptr;    // [groups+1]
+    std::vector<int32_t> imp_slot;   // [nimp]
+    std::vector<int32_t> exp_row;    // [nexp]: device row of each mailbox slot
+    int32_t max_imp = 0;             // most imports of one group
+    int32_t df_rows = 0;             // max over groups of 2 * window rows + imports + 1
+    int32_t df_ints = 0;             // max over groups of imports + exports + 2 * steps
+    int32_t df_waves = 0;            // compute wavefronts per group
+    std::vector<int32_t> wave_ptr;   // [groups*df_waves+1]: steps of wavefront w of group g
     int32_t nsteps() const { return (int32_t)step_lanes.size(); }
 };
 
@@ -124,8 +138,13 @@ struct Tune {
     int32_t block_threads = 256;
     int32_t chunk_rows = 256;
     int32_t partition = 0;   // owner parts: 0 auto (grid blocks, else contiguous), 1 contiguous, 2 bisection, 3 grid
-    int32_t variant = 0;     // persistent kernel: 0 auto, 1 generic, 2 owner chunked, 3 owner split waves
+    int32_t variant = 0;     // persistent kernel: 0 auto, 1 generic, 2 owner chunked, 3 owner split waves,
+                             // 4 owner dataflow
 };
+// LDS bytes of the dataflow owner kernel: `rows` value rows (x window, b
+// window and imports) of R right-hand sides, then `ints` int32 entries
+// (import slots, export rows, step bounds).
+size_t dataflow_lds_bytes(int32_t rows, int32_t ints, int32_t R, size_t tsize);
 // Tuning with every field at its documented default.
 Tune default_tune();
 Tune tune_from(const hec_tune_t *t);
@@ -146,6 +165,7 @@ struct DeviceShape {
     int32_t groups_cap = 0;  // co-resident persistent workgroups
     int32_t cus = 0;         // compute units
     int32_t xcds = 8;        // L2 domains; workgroup i runs on domain i % xcds
+    int32_t lds = 0;         // LDS bytes one workgroup may use (0: 160 KiB)
 };
 void build_exec(TriHost &t, const Csr &a, const Tune &tune, const DeviceShape &dev,
                 const std::vector<int32_t> *sys_ptr);

@@ -404,7 +404,7 @@ __global__ void __launch_bounds__(1024) k_owner(TriArgs a)
             const int items = (re - rb) * R;
             const int js = s - a.step_ptr[g];
             const bool tr = a.trace && tid == 0 && js < a.trace_stride;
-            if (tr) a.trace[2 * ((size_t)g * a.trace_stride + js)] = __builtin_amdgcn_s_memtime();
+            if (tr) a.trace[2 * ((size_t)g * a.trace_stride + js)] = __builtin_amdgcn_s_memrealtime();
             for (int t = tid; t < items; t += nt) {
                 const int qq = t / R, k = t - qq * R;
                 const int x = rb + qq, i = x - cr0;
@@ -436,7 +436,7 @@ __global__ void __launch_bounds__(1024) k_owner(TriArgs a)
                 }
             }
             __syncthreads();
-            if (tr) a.trace[2 * ((size_t)g * a.trace_stride + js) + 1] = __builtin_amdgcn_s_memtime();
+            if (tr) a.trace[2 * ((size_t)g * a.trace_stride + js) + 1] = __builtin_amdgcn_s_memrealtime();
             if (s_abort) {
                 aborted = true;
                 break;
@@ -702,7 +702,7 @@ __global__ void __launch_bounds__(128) k_owner_split(TriArgs a)
         const int *hb = reinterpret_cast<const int *>(B + L.o_head);
         for (int s = s0; s < s1; ++s) {
             const bool tr = a.trace && lane == 0 && (s - s0) < a.trace_stride;
-            if (tr) a.trace[2 * ((size_t)g * a.trace_stride + (s - s0))] = __builtin_amdgcn_s_memtime();
+            if (tr) a.trace[2 * ((size_t)g * a.trace_stride + (s - s0))] = __builtin_amdgcn_s_memrealtime();
             unsigned spins = 0;
             while (*v_fetched < s) {
                 if (*v_abort) break;
@@ -749,7 +749,7 @@ __global__ void __launch_bounds__(128) k_owner_split(TriArgs a)
                     else static_cast<float *>(a.xout)[dst] = static_cast<float>(sv);
                 }
             }
-            if (tr) a.trace[2 * ((size_t)g * a.trace_stride + (s - s0)) + 1] = __builtin_amdgcn_s_memtime();
+            if (tr) a.trace[2 * ((size_t)g * a.trace_stride + (s - s0)) + 1] = __builtin_amdgcn_s_memrealtime();
             if (lane == 0) *v_done = s;
         }
     }
@@ -761,6 +761,375 @@ __global__ void __launch_bounds__(128) k_owner_split(TriArgs a)
             __hip_atomic_store(&a.epoch[0], s_epoch + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
+}
+
+// Dataflow owner kernel.  A workgroup owns a part of the rows (a contiguous
+// device-row window in level order) and runs three kinds of wavefronts:
+//   compute waves  take the group's steps round-robin; a step is one level
+//                  piece of at most 64 (row, rhs) items, solved one item per
+//                  lane.  Each dependency is read from LDS and re-read until
+//                  it no longer holds the sentinel, so a row starts as soon
+//                  as its own inputs exist: there is no per-level barrier.
+//                  The matrix data of a wave's next step is loaded into
+//                  registers while the current one is solved; compute waves
+//                  issue no global stores, so their waits cover loads only.
+//   import wave    polls the mailbox slots this group reads (lane l takes
+//                  imports l, l+64, ... in order of first use) and copies
+//                  each value into LDS when it arrives;
+//   export wave    watches the group's exported rows in LDS and writes each
+//                  one to its mailbox slot as soon as it is solved.
+// Any row waits only on rows of lower levels, and every wave handles its
+// items in level order, so the row of lowest level not yet solved can always
+// proceed: the grid drains as long as all workgroups are co-resident.
+// The summation order (ELL slots, then the CSR tail, then the reciprocal
+// diagonal) is the one of k_level, so results are bit-identical to it.
+template <typename T> __device__ __forceinline__ T lds_get(const T *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <typename T> __device__ __forceinline__ void lds_put(T *p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+constexpr int kDfDepth = 3;  // steps per compute wave with loads in flight
+
+template <typename T, int W> struct DfRegs {
+    int rb, re;
+    int c[W];
+    T v[W];
+    T d;
+};
+
+template <typename T, int W, bool UNIT, bool TAIL, bool R1>
+__global__ void __launch_bounds__(768) k_dataflow(TriArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ unsigned s_epoch;
+    __shared__ int s_abort;
+    const int g = blockIdx.x;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nwc = (nt >> 6) - 2;
+    const int R = R1 ? 1 : a.R;
+    if (tid == 0) {
+        s_epoch = __hip_atomic_load(a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_abort = 0;
+    }
+    __syncthreads();
+    const unsigned par = s_epoch & 1u;
+    T *mbox = static_cast<T *>(a.mbox);
+    const size_t half = (size_t)a.nexp * a.mbox_stride;
+    T *mrd = mbox + (par ? half : 0);
+    const int lo = a.window[2 * g], hi = a.window[2 * g + 1], win = hi - lo;
+    const int i0 = a.imp_ptr[g], nimp = a.imp_ptr[g + 1] - i0;
+    const int e0 = a.exp_ptr[g], nex = a.exp_ptr[g + 1] - e0;
+    const int s0 = a.step_ptr[g], ns = a.step_ptr[g + 1] - s0;
+    // LDS value rows: x [win][R], b [win][R], imports [nimp][R], one zero
+    // row (the target of ELL padding); then import slots, export rows
+    // (window offsets) and step bounds (window offsets)
+    T *xl = reinterpret_cast<T *>(smem);
+    T *bl = xl + (size_t)win * R;
+    T *im = bl + (size_t)win * R;
+    const size_t ib = (((size_t)2 * win + nimp + 1) * R * sizeof(T) + 15) & ~(size_t)15;
+    int *isl = reinterpret_cast<int *>(smem + ib);
+    int *erl = isl + nimp;
+    int *stl = erl + nex;
+    // when tracing: 2*ns clocks after the ints, at an 8-byte boundary
+    unsigned long long *ltr =
+        reinterpret_cast<unsigned long long *>(smem + ((ib + (size_t)(nimp + nex + 2 * ns) * 4 + 7) & ~(size_t)7));
+
+    if (a.nexp > 0) {
+        T *other = mbox + (par ? 0 : half);
+        const size_t m0 = (size_t)e0 * a.mbox_stride, m1 = (size_t)(e0 + nex) * a.mbox_stride;
+        for (size_t i = m0 + tid; i < m1; i += nt) other[i] = sentinel<T>();
+    }
+    // Fill LDS.  Every thread keeps kFill independent loads in flight (the
+    // start-up of all groups delays the first rows of the solve).
+    constexpr int kFill = 8;
+    for (int t = tid; t < win * R; t += nt) xl[t] = sentinel<T>();
+    for (int t = tid; t < (nimp + 1) * R; t += nt) im[t] = t < nimp * R ? sentinel<T>() : T(0);
+    auto fill_b = [&](const auto *bin) {
+        for (int t0 = tid; t0 < win * R; t0 += kFill * nt) {
+            int gi[kFill];
+#pragma unroll
+            for (int u = 0; u < kFill; ++u) {
+                const int t = min(t0 + u * nt, win * R - 1);
+                gi[u] = a.gather[lo + (R1 ? t : t / R)];
+            }
+            T bv[kFill];
+#pragma unroll
+            for (int u = 0; u < kFill; ++u) {
+                const int t = min(t0 + u * nt, win * R - 1);
+                bv[u] = static_cast<T>(bin[(size_t)gi[u] * R + (R1 ? 0 : t % R)]);
+            }
+#pragma unroll
+            for (int u = 0; u < kFill; ++u)
+                if (t0 + u * nt < win * R) bl[t0 + u * nt] = bv[u];
+        }
+    };
+    if (a.in_f64) fill_b(static_cast<const double *>(a.bin));
+    else fill_b(static_cast<const float *>(a.bin));
+    auto copy_ints = [&](int *dst, const int32_t *src, int count, int add) {
+        for (int t0 = tid; t0 < count; t0 += kFill * nt) {
+            int v[kFill];
+#pragma unroll
+            for (int u = 0; u < kFill; ++u) v[u] = src[min(t0 + u * nt, count - 1)];
+#pragma unroll
+            for (int u = 0; u < kFill; ++u)
+                if (t0 + u * nt < count) dst[t0 + u * nt] = v[u] + add;
+        }
+    };
+    copy_ints(isl, a.imp_slot + i0, nimp, 0);
+    copy_ints(erl, a.exp_row + e0, nex, -lo);
+    copy_ints(stl, a.step_row + 2 * s0, 2 * ns, -lo);
+    __syncthreads();
+    const unsigned long long t_fill = a.trace ? __builtin_amdgcn_s_memrealtime() : 0ull;
+
+    if (wv < nwc) {
+        const T *ev = static_cast<const T *>(a.ell_val);
+        const T *dv = static_cast<const T *>(a.dinv);
+        const T *tv = static_cast<const T *>(a.tail_val);
+        // Lanes past the step's items repeat its last item, so loads and
+        // their uses are unconditional and the compiler's load waits stay
+        // exact (DEPTH steps' loads stay in flight while one is solved).
+        auto load = [&](DfRegs<T, W> &u, int rb, int re) {
+            u.rb = rb;
+            u.re = re;
+            const int it = min(lane, (re - rb) * R - 1);
+            const int x = lo + rb + (R1 ? it : it / R);
+#pragma unroll
+            for (int e = 0; e < W; ++e) {
+                u.c[e] = a.ell_col[(size_t)e * a.ld + x];
+                u.v[e] = ev[(size_t)e * a.ld + x];
+            }
+            if (!UNIT) u.d = dv[x];
+        };
+        const int ntr = a.trace ? min(ns, a.trace_stride - 1) : 0;
+        bool aborted = false;
+        // solve step j from registers u; `nj` is the step whose bounds are
+        // read (returned in nb, ne) while this one waits for LDS
+        auto process = [&](const DfRegs<T, W> &u, int j, int nj, int &nb, int &ne) {
+            if (j < ntr && lane == 0) ltr[2 * j] = __builtin_amdgcn_s_memrealtime();
+            nb = stl[2 * nj];
+            ne = stl[2 * nj + 1];
+            const int items = (u.re - u.rb) * R;
+            const int it = min(lane, items - 1);
+            const int q = R1 ? it : it / R, k = it - q * R;
+            const int r = u.rb + q;  // window offset of the row
+            T sv = bl[r * R + k];
+            // columns are LDS value rows (ELL padding names the zero row)
+            T dep[W];
+            int off[W];
+#pragma unroll
+            for (int e = 0; e < W; ++e) {
+                off[e] = u.c[e] * R + k;
+                dep[e] = lds_get(xl + off[e]);
+            }
+            bool pend = false;
+#pragma unroll
+            for (int e = 0; e < W; ++e) pend |= is_sentinel(dep[e]);
+            unsigned spins = 0;
+            while (pend) {
+                // re-read every input (one LDS round trip per poll; inputs
+                // already present do not change)
+#pragma unroll
+                for (int e = 0; e < W; ++e) dep[e] = lds_get(xl + off[e]);
+                pend = false;
+#pragma unroll
+                for (int e = 0; e < W; ++e) pend |= is_sentinel(dep[e]);
+                if (pend && (++spins & 63u) == 0) {
+                    if (lds_get(&s_abort)) {
+                        aborted = true;
+                        break;
+                    }
+                    if (spins > (kSpinLimit << 4)) {
+                        lds_put(&s_abort, 2);
+                        aborted = true;
+                        break;
+                    }
+                }
+            }
+            // padding subtracts 0 * 0, which leaves sv unchanged bit for bit
+#pragma unroll
+            for (int e = 0; e < W; ++e) sv -= u.v[e] * dep[e];
+            if (TAIL) {
+                const int x = lo + r;
+                for (int p = a.tail_ptr[x]; p < a.tail_ptr[x + 1]; ++p) {
+                    const int o = a.tail_col[p] * R + k;
+                    T dd = lds_get(xl + o);
+                    unsigned sp = 0;
+                    while (is_sentinel(dd)) {
+                        dd = lds_get(xl + o);
+                        if ((++sp & 63u) == 0) {
+                            if (lds_get(&s_abort)) {
+                                aborted = true;
+                                break;
+                            }
+                            if (sp > (kSpinLimit << 4)) {
+                                lds_put(&s_abort, 2);
+                                aborted = true;
+                                break;
+                            }
+                        }
+                    }
+                    sv -= tv[p] * dd;
+                }
+            }
+            if (!UNIT) sv *= u.d;
+            // lanes past the items store the same value as the last item's lane
+            lds_put(xl + r * R + k, sv);
+            if (j < ntr && lane == 0) ltr[2 * j + 1] = __builtin_amdgcn_s_memrealtime();
+        };
+        // The wave walks its own steps [j, jend) in order.  kDfDepth steps
+        // have their loads in flight; loads past the last step repeat it, so
+        // every path issues the same loads and the compiler's waits stay
+        // exact.  The loop is written out per register set (no register
+        // moves, no merged paths with skipped loads) and its exit test is
+        // wave-uniform.
+        int j = a.wave_ptr[g * nwc + wv] - s0;
+        const int jend = a.wave_ptr[g * nwc + wv + 1] - s0;
+        const int last = jend - 1;
+        DfRegs<T, W> A, B, C;
+        auto first = [&](DfRegs<T, W> &u, int q) {
+            q = min(q, last);
+            load(u, stl[2 * q], stl[2 * q + 1]);
+        };
+        auto run = [&](DfRegs<T, W> &u) {
+            int nb, ne;
+            process(u, j, min(j + kDfDepth, last), nb, ne);
+            load(u, nb, ne);
+            j += 1;
+        };
+        if (j < jend) {
+            first(A, j);
+            first(B, j + 1);
+            first(C, j + 2);
+            // whole triples in a loop with one exit at the bottom, so the
+            // loop is entered and repeated with the same loads in flight
+            const int triples = (jend - j) / 3, rest = (jend - j) - 3 * triples;
+            for (int t3 = 0; t3 < triples; ++t3) {
+                run(A);
+                run(B);
+                run(C);
+                if (__ballot(aborted) != 0) break;
+            }
+            if (rest > 0 && __ballot(aborted) == 0) run(A);
+            if (rest > 1 && __ballot(aborted) == 0) run(B);
+        }
+    } else if (wv == nwc) {
+        // import wave
+        const int items = nimp * R;
+        const int xoff = 2 * win * R;
+        int it = lane;
+        unsigned idle = 0;
+        while (__ballot(it < items) != 0) {
+            if (it < items) {
+                const int q = it / R, k = it - q * R;
+                const T v = __hip_atomic_load(mrd + (size_t)isl[q] * a.mbox_stride + k, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+                if (!is_sentinel(v)) {
+                    lds_put(xl + xoff + it, v);
+                    it += 64;
+                    idle = 0;
+                } else if (++idle > kSpinLimit) {
+                    lds_put(&s_abort, 2);
+                    it = items;
+                } else if ((idle & 255u) == 0 &&
+                           __hip_atomic_load(a.err_dev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                    lds_put(&s_abort, 1);  // another workgroup gave up
+                    it = items;
+                }
+            }
+            if (lds_get(&s_abort)) break;
+        }
+    } else {
+        // export wave
+        const int items = nex * R;
+        int it = lane;
+        unsigned idle = 0;
+        while (__ballot(it < items) != 0) {
+            if (it < items) {
+                const int q = it / R, k = it - q * R;
+                const T v = lds_get(xl + erl[q] * R + k);
+                if (!is_sentinel(v)) {
+                    __hip_atomic_store(mrd + (size_t)(e0 + q) * a.mbox_stride + k, v, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    it += 64;
+                    idle = 0;
+                } else if (++idle > (kSpinLimit << 4)) {
+                    lds_put(&s_abort, 2);
+                    it = items;
+                }
+            }
+            if (lds_get(&s_abort)) break;
+        }
+    }
+    __syncthreads();
+    const unsigned long long t_done = a.trace ? __builtin_amdgcn_s_memrealtime() : 0ull;
+    if (tid == 0 && s_abort == 2) {
+        __hip_atomic_store(a.err_dev, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(a.err_host, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    if (a.trace) {
+        const int ntr = min(ns, a.trace_stride - 1);
+        for (int t = tid; t < 2 * ntr; t += nt) a.trace[2 * (size_t)g * a.trace_stride + t] = ltr[t];
+        if (tid == 0) {
+            a.trace[2 * ((size_t)g * a.trace_stride + a.trace_stride - 1)] = t_fill;
+            a.trace[2 * ((size_t)g * a.trace_stride + a.trace_stride - 1) + 1] = t_done;
+        }
+    }
+    if (!s_abort) {
+        for (int t = tid; t < win * R; t += nt) {
+            const int q = t / R, k = t - q * R;
+            const int x = lo + q;
+            const T v = xl[t];
+            if (a.write_xw) static_cast<T *>(a.xw)[(size_t)x * R + k] = v;
+            if (a.xout) {
+                const size_t dst = (size_t)a.scatter[x] * R + k;
+                if (a.out_f64) static_cast<double *>(a.xout)[dst] = static_cast<double>(v);
+                else static_cast<float *>(a.xout)[dst] = static_cast<float>(v);
+            }
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const unsigned done = __hip_atomic_fetch_add(&a.epoch[1], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (done == gridDim.x - 1) {
+            __hip_atomic_store(&a.epoch[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.epoch[0], s_epoch + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+template <typename T, bool UNIT, bool TAIL, bool R1>
+OwnerKernel dataflow_kernel_w(int w)
+{
+    switch (w) {
+    case 1: return k_dataflow<T, 1, UNIT, TAIL, R1>;
+    case 2: return k_dataflow<T, 2, UNIT, TAIL, R1>;
+    case 3: return k_dataflow<T, 3, UNIT, TAIL, R1>;
+    case 4: return k_dataflow<T, 4, UNIT, TAIL, R1>;
+    case 5: return k_dataflow<T, 5, UNIT, TAIL, R1>;
+    case 6: return k_dataflow<T, 6, UNIT, TAIL, R1>;
+    case 7: return k_dataflow<T, 7, UNIT, TAIL, R1>;
+    case 8: return k_dataflow<T, 8, UNIT, TAIL, R1>;
+    default: return nullptr;
+    }
+}
+
+template <typename T, bool R1>
+OwnerKernel dataflow_kernel_r(int w, bool unit, bool tail)
+{
+    if (unit) return tail ? dataflow_kernel_w<T, true, true, R1>(w) : dataflow_kernel_w<T, true, false, R1>(w);
+    return tail ? dataflow_kernel_w<T, false, true, R1>(w) : dataflow_kernel_w<T, false, false, R1>(w);
+}
+
+template <typename T>
+OwnerKernel dataflow_kernel(int w, bool unit, bool tail, int R)
+{
+    return R == 1 ? dataflow_kernel_r<T, true>(w, unit, tail) : dataflow_kernel_r<T, false>(w, unit, tail);
 }
 
 template <typename T>
@@ -802,6 +1171,24 @@ void launch_typed(DevTri &d, TriArgs a, hipStream_t st)
             hipLaunchKernelGGL((k_level<T, TIn, TOut>), dim3(grid), dim3(256), 0, st, a);
         }
         hip_check(hipGetLastError(), "k_level launch");
+        return;
+    }
+    if (d.dataflow) {
+        // the plan's columns name group-local imports: only this kernel reads them
+        OwnerKernel k = dataflow_kernel<T>(d.w, d.unit, d.has_tail, a.R);
+        if (!k) fail(HEC_ERR_INVALID_ARG, "internal: dataflow plan with an unsupported ELL width");
+        if ((int64_t)d.df_step_rows * a.R > 64)
+            fail(HEC_ERR_INVALID_ARG, "dataflow plan: nrhs exceeds the plan's max_nrhs (steps are sized for it)");
+        size_t lds = dataflow_lds_bytes(d.df_rows, d.df_ints, a.R, sizeof(T));
+        if (a.trace) lds += 8 + 16 * (size_t)std::min(d.df_ints / 2, a.trace_stride);  // per-step clocks
+        const int block = 64 * d.df_waves + 128;
+        if (block > 768) fail(HEC_ERR_INVALID_ARG, "dataflow kernel: block too large");
+        if (lds > (size_t)device_max_lds())
+            fail(HEC_ERR_CAPACITY, "dataflow kernel: LDS need exceeds the device limit at this nrhs");
+        if (capacity_of((const void *)k, block, lds) < d.groups)
+            fail(HEC_ERR_CAPACITY, "dataflow grid exceeds the co-resident capacity");
+        hipLaunchKernelGGL(k, dim3(d.groups), dim3(block), lds, st, a);
+        hip_check(hipGetLastError(), "k_dataflow launch");
         return;
     }
     if (d.kind == HEC_SCHED_OWNER_PERSISTENT && d.variant == 3 && a.R == 1 && !d.has_tail && d.max_lanes_one &&
@@ -981,6 +1368,10 @@ void launch_tri(DevTri &d, const void *bin, hec_dtype_t in_dt, const int32_t *ga
     a.rem_ent = d.rem_ent.as<int32_t>();
     a.chunk_step = d.chunk_step.as<int32_t>();
     a.chunk_rows = d.chunk_rows;
+    a.imp_ptr = d.imp_ptr.as<int32_t>();
+    a.imp_slot = d.imp_slot.as<int32_t>();
+    a.exp_row = d.exp_row.as<int32_t>();
+    a.wave_ptr = d.wave_ptr.as<int32_t>();
     a.trace = d.trace;
     a.trace_stride = d.trace_stride;
     a.in_f64 = in_dt == HEC_F64 ? 1 : 0;

@@ -44,7 +44,7 @@ def test_tune_defaults_and_validation():
     with pytest.raises(H.HecError):
         H.tri_analyze(L, tune=H.tune_default(host_only=1, group_lanes=3))
     with pytest.raises(H.HecError):
-        H.tri_analyze(L, tune=H.tune_default(host_only=1, kernel_variant=4))
+        H.tri_analyze(L, tune=H.tune_default(host_only=1, kernel_variant=5))
     with pytest.raises(H.HecError):
         H.tri_analyze(L, tune=H.tune_default(host_only=1, block_threads=256, chunk_rows=768))
     # an owner plan with the default chunk size builds (steps are cut to chunks)
@@ -70,10 +70,13 @@ def _cases():
 
 
 @pytest.mark.parametrize("case", range(6))
-@pytest.mark.parametrize("sched", ["level_launch", "level_persistent", "owner_persistent"])
+@pytest.mark.parametrize("sched", ["level_launch", "level_persistent", "owner_persistent", "owner_dataflow"])
 def test_levels_map_and_hec_bit_exact(case, sched):
     name, T, upper, unit = _cases()[case]
-    t = H.tune_default(host_only=1, schedule=sched, num_groups=16)
+    if sched == "owner_dataflow":
+        t = H.tune_default(host_only=1, schedule="owner_persistent", kernel_variant=4, num_groups=16)
+    else:
+        t = H.tune_default(host_only=1, schedule=sched, num_groups=16)
     p = H.tri_analyze(T, "upper" if upper else "lower", unit_diag=unit, tune=t)
     nlev, lp, perm = H.tri_plan_info(p)
     lev, nl = oracle.levels(T, upper=upper)
@@ -103,6 +106,15 @@ def test_levels_map_and_hec_bit_exact(case, sched):
         for g in np.unique(owner):
             rows = xperm[owner == g]
             assert np.all(np.diff(lev[rows]) >= 0)  # level order inside a group
+    if sched.startswith("owner"):
+        # every dependency inside a group comes earlier in the group's order
+        pos = np.empty(T.n, np.int64)
+        pos[xperm] = np.arange(T.n)
+        rows = np.repeat(np.arange(T.n), np.diff(T.rowptr))
+        dep = T.col != rows
+        i, j = rows[dep], T.col[dep]
+        same = owner[pos[i]] == owner[pos[j]]
+        assert np.all(pos[j][same] < pos[i][same])
     st = H.tri_plan_stats(p)
     assert st["nlev"] == nl and st["n"] == T.n
 
@@ -173,6 +185,28 @@ def test_ras_layout_matches_oracle():
     nsub, tot, sizes = H.ras_info(s)
     assert nsub == 5 and tot == sum(len(d.ext) for d in doms)
     assert list(sizes) == [len(d.ext) for d in doms]
+
+
+def test_dataflow_plan_limits():
+    L = synth.random_lower(400, 0.01, seed=2)
+    # the dataflow kernel sizes its steps for max_nrhs; more than 64 cannot fit a wavefront
+    with pytest.raises(H.HecError):
+        H.tri_analyze(L, tune=H.tune_default(host_only=1, schedule="owner_persistent", kernel_variant=4,
+                                             max_nrhs=65))
+    with pytest.raises(H.HecError):
+        H.tri_analyze(L, tune=H.tune_default(host_only=1, schedule="owner_persistent", kernel_variant=4,
+                                             block_threads=704))
+    # one group holding every row of a large system does not fit in LDS
+    A = synth.poisson2d(160)
+    Lp, _ = oracle.ilu0(A)
+    with pytest.raises(H.HecError) as e:
+        H.tri_analyze(Lp, unit_diag=True, tune=H.tune_default(host_only=1, schedule="owner_persistent",
+                                                              kernel_variant=4, num_groups=1))
+    assert e.value.name == "CAPACITY"
+    p = H.tri_analyze(Lp, unit_diag=True, tune=H.tune_default(host_only=1, schedule="owner_persistent",
+                                                              kernel_variant=4, num_groups=8))
+    st = H.tri_plan_stats(p)
+    assert st["num_groups"] == 8 and st["nsteps"] >= st["nlev"]
 
 
 def test_owner_partitions():

@@ -12,8 +12,16 @@ pytestmark = pytest.mark.gpu
 
 import paper_1606_00541_amd as H  # noqa: E402
 
-SCHEDS = ["level_launch", "level_persistent", "owner_persistent"]
+SCHEDS = ["level_launch", "level_persistent", "owner_persistent", "owner_dataflow"]
 FP64_TOL = 1e-12
+
+
+def tune(sched, **kw):
+    """Tuning for a schedule name; "owner_dataflow" is the owner schedule run
+    by the dataflow kernel (no per-level barrier)."""
+    if sched == "owner_dataflow":
+        return H.tune_default(schedule="owner_persistent", kernel_variant=4, **kw)
+    return H.tune_default(schedule=sched, **kw)
 
 
 def dev(a):
@@ -43,7 +51,7 @@ def test_config1_poisson64_ilu0(sched):
     A = synth.poisson2d(64)
     L, U = oracle.ilu0(A)
     b = synth.rhs(A.n, 1, 1)
-    t = H.tune_default(schedule=sched)
+    t = tune(sched)
     pl = H.tri_analyze(L, "lower", unit_diag=True, tune=t)
     pu = H.tri_analyze(U, "upper", tune=t)
     for plan, T, up in ((pl, L, False), (pu, U, True)):
@@ -64,7 +72,7 @@ def test_schedules_are_bit_identical():
     b = synth.rhs(L.n, 2, 22)
     outs = []
     for s in SCHEDS:
-        p = H.tri_analyze(L, "lower", tune=H.tune_default(schedule=s, max_nrhs=2))
+        p = H.tri_analyze(L, "lower", tune=tune(s, max_nrhs=2))
         outs.append(solve(p, b))
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
@@ -81,7 +89,7 @@ def test_random_triangles(sched, upper, nrhs, seed):
     b = synth.rhs(n, nrhs, 200 + seed)
     # ELL width 1 pushes most entries into the CSR remainder
     for w in (-1, 1):
-        p = H.tri_analyze(T, "upper" if upper else "lower", tune=H.tune_default(schedule=sched, ell_width=w))
+        p = H.tri_analyze(T, "upper" if upper else "lower", tune=tune(sched, ell_width=w))
         x = solve(p, b, upper)
         ref = (oracle.upper_solve if upper else oracle.lower_solve)(T, b)
         assert relerr(x, ref) <= FP64_TOL
@@ -102,7 +110,7 @@ def test_fp32_plans(sched):
     A = synth.diffusion3d(12, 11, 10, 1.0, seed=3)
     L, U = oracle.ilu0(A)
     b = synth.rhs(A.n, 2, 4)
-    t = H.tune_default(schedule=sched)
+    t = tune(sched)
     pl = H.tri_analyze(oracle.to_f32(L), "lower", unit_diag=True, dtype="f32", tune=t)
     pu = H.tri_analyze(oracle.to_f32(U), "upper", dtype="f32", tune=t)
     ref32 = oracle.upper_solve_f32(oracle.to_f32(U), oracle.lower_solve_f32(oracle.to_f32(L), b, unit=True))
@@ -121,7 +129,7 @@ def test_empty_and_single_row():
     for n in (0, 1):
         T = CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.full(n, 2.0))
         for s in SCHEDS:
-            p = H.tri_analyze(T, "lower", tune=H.tune_default(schedule=s))
+            p = H.tri_analyze(T, "lower", tune=tune(s))
             if n:
                 assert np.array_equal(solve(p, np.array([3.0])), np.array([1.5]))
 
@@ -139,15 +147,16 @@ def test_diagonal_and_bidiagonal_closed_forms():
     v = np.concatenate([[1.0]] + [[-1.0, 1.0] for _ in range(1, n)])
     B = CSR(n, rp, ci, v)
     for s in SCHEDS:
-        p = H.tri_analyze(B, "lower", tune=H.tune_default(schedule=s))
+        p = H.tri_analyze(B, "lower", tune=tune(s))
         assert H.tri_plan_info(p)[0] == n
         assert np.array_equal(solve(p, np.ones(n)), np.arange(1, n + 1, dtype=float))
 
 
-def test_in_place_solve():
+@pytest.mark.parametrize("sched", ["owner_persistent", "owner_dataflow"])
+def test_in_place_solve(sched):
     L = synth.random_lower(1500, 0.003, seed=8)
     b = synth.rhs(L.n, 1, 9)[:, 0]
-    p = H.tri_analyze(L, "lower", tune=H.tune_default(schedule="owner_persistent"))
+    p = H.tri_analyze(L, "lower", tune=tune(sched))
     bt = dev(b)
     H.tri_solve_lower(p, bt, bt)
     torch.cuda.synchronize()
@@ -189,8 +198,42 @@ def test_mailbox_recovers_across_rhs_widths():
     # halves consistent (resets cover the widest layout ever allocated)
     A = synth.poisson3d(20)
     L, _ = oracle.ilu0(A)
-    for sched in ("level_persistent", "owner_persistent"):
-        p = H.tri_analyze(L, "lower", unit_diag=True, tune=H.tune_default(schedule=sched))
+    for sched in ("level_persistent", "owner_persistent", "owner_dataflow"):
+        p = H.tri_analyze(L, "lower", unit_diag=True, tune=tune(sched, max_nrhs=4))
         for R in (1, 4, 1, 2, 4, 1):
             b = synth.rhs(A.n, R, R)
             assert relerr(solve(p, b), oracle.lower_solve(L, b, unit=True)) <= FP64_TOL
+
+
+@pytest.mark.parametrize("groups", [0, 7, 64])
+@pytest.mark.parametrize("nrhs", [1, 3])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("part", [1, 3])
+def test_dataflow_kernel_bit_identical_to_level_launch(groups, nrhs, dt, part):
+    A = synth.diffusion3d(21, 19, 17, 1.0, seed=12)
+    L, U = oracle.iluk(A, 1)
+    if dt == "f32":
+        L, U = oracle.to_f32(L), oracle.to_f32(U)
+    b = synth.rhs(A.n, nrhs, 13).astype(np.float64 if dt == "f64" else np.float32)
+    ref_l = H.tri_analyze(L, "lower", unit_diag=True, dtype=dt, tune=H.tune_default(schedule="level_launch"))
+    ref_u = H.tri_analyze(U, "upper", dtype=dt, tune=H.tune_default(schedule="level_launch"))
+    t = tune("owner_dataflow", num_groups=groups, max_nrhs=nrhs, partition=part)
+    pl = H.tri_analyze(L, "lower", unit_diag=True, dtype=dt, tune=t)
+    pu = H.tri_analyze(U, "upper", dtype=dt, tune=t)
+    for rep in range(3):  # alternating mailbox halves
+        assert np.array_equal(solve(pl, b), solve(ref_l, b))
+        assert np.array_equal(solve(pu, b, upper=True), solve(ref_u, b, upper=True))
+
+
+def test_dataflow_kernel_with_csr_tails():
+    # ILUT rows overflow a narrow ELL part into the CSR remainder
+    A = synth.diffusion3d(14, 13, 12, 2.0, seed=5)
+    L, U = oracle.ilut(A, 10, 1e-3)
+    b = synth.rhs(A.n, 2, 6)
+    for T, up, unit in ((L, False, True), (U, True, False)):
+        ref = H.tri_analyze(T, "upper" if up else "lower", unit_diag=unit,
+                            tune=H.tune_default(schedule="level_launch", ell_width=2))
+        p = H.tri_analyze(T, "upper" if up else "lower", unit_diag=unit,
+                          tune=tune("owner_dataflow", ell_width=2, max_nrhs=2))
+        assert H.tri_plan_stats(p)["nnz_tail"] > 0
+        assert np.array_equal(solve(p, b, up), solve(ref, b, up))
