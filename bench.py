@@ -120,6 +120,11 @@ def _block_diag(mats):
                np.concatenate(vs)), np.array(sys_ptr, np.int32)
 
 
+def _tune(H, args, **kw):
+    sched = 0 if args.schedule == "auto" else args.schedule
+    return H.tune_default(schedule=sched, kernel_variant=args.kernel_variant, **kw)
+
+
 def run_config(cfg, args):
     """Secondary workloads (one JSON line each): 3 = mixed precision on
     heterogeneous ILUT, 4 = RAS with 16 RHS, 5 = 256 batched systems."""
@@ -140,8 +145,7 @@ def run_config(cfg, args):
         res = {}
         for fdt in ("f64", "f32"):
             t0 = time.time()
-            f = H.ilu_setup(A, "ilut", p=10, tol=1e-3, factor_dtype=fdt,
-                            tune=H.tune_default(schedule=args.schedule))
+            f = H.ilu_setup(A, "ilut", p=10, tol=1e-3, factor_dtype=fdt, tune=_tune(H, args))
             setup = time.time() - t0
             pl, pu = H.ilu_plans(f)
             stl, stu = H.tri_plan_stats(pl), H.tri_plan_stats(pu)
@@ -153,7 +157,8 @@ def run_config(cfg, args):
             res[fdt] = {"apply_ms": round(ms, 4), "apply_GBps": round(B / (ms * 1e-3) / 1e9, 3),
                         "nlev_L": stl["nlev"], "nlev_U": stu["nlev"], "nnz_offdiag_L": stl["nnz_offdiag"],
                         "nnz_offdiag_U": stu["nnz_offdiag"], "setup_s": round(setup, 3), "fgmres": kr,
-                        "x": x}
+                        "dataflow": stl["dataflow"], "ell_width_L": stl["ell_width"],
+                        "nnz_tail_L": stl["nnz_tail"], "x": x}
         d = (res["f32"]["x"] - res["f64"]["x"]).norm().item() / res["f64"]["x"].norm().item()
         for k in res:
             res[k].pop("x")
@@ -169,7 +174,7 @@ def run_config(cfg, args):
         n = A.n
         owner, sizes = synth.subdomain_cuts(n, 64, 8192, 61440, seed=4)
         t0 = time.time()
-        s = H.ras_setup(A, 64, owner, overlap=1, factor_dtype="f32", tune=H.tune_default(max_nrhs=16))
+        s = H.ras_setup(A, 64, owner, overlap=1, factor_dtype="f32", tune=_tune(H, args, max_nrhs=16))
         setup = time.time() - t0
         nsub, tot, ext = H.ras_info(s)
         pl, pu = H.ras_plans(s)
@@ -187,7 +192,8 @@ def run_config(cfg, args):
                     "config": {"workload": "RAS on 128^3 Poisson: 64 seeded contiguous subdomains (8192..61440 "
                                            "rows), overlap 1, ILU(0) per subdomain, 16 RHS; BiCGSTAB to 1e-10",
                                "extended_rows": int(tot), "nlev_L": stl["nlev"], "nlev_U": stu["nlev"],
-                               "setup_s": round(setup, 3)},
+                               "setup_s": round(setup, 3), "dataflow": stl["dataflow"],
+                               "workgroups": stl["num_groups"]},
                     "solves_per_s": round(1000.0 * R / ms, 2), "bicgstab": kr})
     elif cfg == 5:
         shapes = synth.batch_systems(256, seed=5)
@@ -205,7 +211,7 @@ def run_config(cfg, args):
         res = {}
         for fdt in ("f64", "f32"):
             t0 = time.time()
-            f = H.batch_setup(A, sys_ptr, "iluk", k=1, factor_dtype=fdt, tune=H.tune_default(max_nrhs=R))
+            f = H.batch_setup(A, sys_ptr, "iluk", k=1, factor_dtype=fdt, tune=_tune(H, args, max_nrhs=R))
             setup = time.time() - t0
             pl, pu = H.ilu_plans(f)
             stl, stu = H.tri_plan_stats(pl), H.tri_plan_stats(pu)
@@ -216,6 +222,7 @@ def run_config(cfg, args):
             x, kr = _krylov(H, torch, f, Aop, b, "fgmres")
             res[fdt] = {"apply_ms": round(ms, 4), "apply_GBps": round(B / (ms * 1e-3) / 1e9, 3),
                         "nlev_L": stl["nlev"], "nlev_U": stu["nlev"], "setup_s": round(setup, 3), "fgmres": kr,
+                        "dataflow": stl["dataflow"], "workgroups": stl["num_groups"],
                         "systems_per_s": round(len(mats) * R / kr["seconds"], 3)}
         out.update({"value": res["f32"]["apply_GBps"], "dtype": "f32 factors, f64 refinement",
                     "ms_per_step": res["f32"]["apply_ms"],
@@ -237,8 +244,10 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--grid", type=int, default=128)
-    ap.add_argument("--schedule", default="owner_persistent",
-                    choices=["level_launch", "level_persistent", "owner_persistent"])
+    ap.add_argument("--schedule", default="auto",
+                    choices=["auto", "level_launch", "level_persistent", "owner_persistent"])
+    ap.add_argument("--kernel-variant", type=int, default=0,
+                    help="hec_tune_t.kernel_variant (0 = auto: the dataflow kernel when it fits)")
     ap.add_argument("--no-krylov", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -267,7 +276,7 @@ def main(argv=None):
     A = synth.poisson3d(s)
     n = A.n
     t0 = time.time()
-    f = H.ilu_setup(A, "ilu0", tune=H.tune_default(schedule=args.schedule))
+    f = H.ilu_setup(A, "ilu0", tune=_tune(H, args))
     setup_s = time.time() - t0
     pl, pu = H.ilu_plans(f)
     stl, stu = H.tri_plan_stats(pl), H.tri_plan_stats(pu)
@@ -293,16 +302,21 @@ def main(argv=None):
     bl = per_launch_bytes(n, stl["nnz_offdiag"], 1, diag=False)
     bu = per_launch_bytes(n, stu["nnz_offdiag"], 1, diag=True)
     if args.schedule == "level_launch":
-        kname = "k_level"
+        kname, tag = "k_level", "launch"
         launches = stl["nlev"] + stu["nlev"]
+    elif stl["dataflow"] and stu["dataflow"]:
+        kname, tag = "k_dataflow", "dataflow"
+        launches = 2
+    elif stl["schedule"] == 3 and stl["nnz_tail"] == 0 and stu["nnz_tail"] == 0:
+        kname, tag = "k_owner", "owner"
+        launches = 2
     else:
-        kname = "k_persistent"
+        kname, tag = "k_persistent", "level" if stl["schedule"] == 2 else "owner"
         launches = 2
     per_launch = (bl + bu) / launches
     kernel_ms = ms / launches
     achieved = per_launch / (kernel_ms * 1e-3) / 1e9
-    sched_tag = {"owner_persistent": "owner", "level_persistent": "level", "level_launch": "launch"}[args.schedule]
-    traffic = measured_traffic(kname, "poisson%d_ilu0_f64_%s" % (s, sched_tag))
+    traffic = measured_traffic(kname, "poisson%d_ilu0_f64_%s" % (s, tag))
     roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
                 "algorithmic_bytes_per_launch": int(per_launch),
@@ -325,6 +339,7 @@ def main(argv=None):
                                "seed 2; step = one L+U preconditioner application" % (s, n, stl["ell_width"]),
                    "n": n, "nnz_offdiag_L": stl["nnz_offdiag"], "nnz_offdiag_U": stu["nnz_offdiag"],
                    "nlev_L": stl["nlev"], "nlev_U": stu["nlev"], "schedule": args.schedule,
+                   "kernel": kname, "crit_hops_L": stl["crit_hops"],
                    "workgroups": stl["num_groups"], "counted_bytes_per_step": int(B),
                    "setup_s": round(setup_s, 3)},
         "solves_per_s": round(1000.0 / ms, 2),

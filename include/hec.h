@@ -56,10 +56,11 @@ typedef enum hec_uplo { HEC_LOWER = 0, HEC_UPPER = 1 } hec_uplo_t;
 /* How the level sets are executed on the device (all give bit-identical
  * results for the same plan, since every row is computed the same way). */
 typedef enum hec_schedule {
-    HEC_SCHED_AUTO = 0,
+    HEC_SCHED_AUTO = 0,              /* the owner schedule (kernel chosen by kernel_variant) */
     HEC_SCHED_LEVEL_LAUNCH = 1,      /* one kernel launch per level (Algorithm 2 shape) */
     HEC_SCHED_LEVEL_PERSISTENT = 2,  /* one persistent launch; each level split into
-                                        per-workgroup chunks, chunk-to-chunk waits */
+                                        per-workgroup chunks; a chunk polls the values it
+                                        reads from other chunks */
     HEC_SCHED_OWNER_PERSISTENT = 3   /* one persistent launch; each workgroup owns a
                                         connected set of rows across all levels and
                                         keeps their solution in LDS */
@@ -86,16 +87,21 @@ typedef struct hec_tune {
                                group_lanes cooperating lanes per row */
     int32_t part_rows;      /* owner schedule: target rows per owned part (0 = auto) */
     int32_t host_only;      /* 1 = build the host plan only (no device upload) */
-    int32_t max_nrhs;       /* workspace is allocated for up to this many RHS (grows on demand) */
+    int32_t max_nrhs;       /* workspace is allocated for up to this many RHS (grows on demand);
+                               plans run by the dataflow kernel accept at most this many */
     int32_t block_threads;  /* threads per workgroup (64..1024, multiple of 64) */
     int32_t chunk_rows;     /* owner schedule: rows of matrix data staged in LDS per chunk
                                (1, 2 or 4 times block_threads; 0 = max(256, block_threads)) */
     int32_t partition;      /* owner schedule parts: 0 = auto (blocks of a detected
                                structured grid, else contiguous), 1 = contiguous ranges of the
                                problem order, 2 = recursive graph bisection, 3 = grid blocks */
-    int32_t kernel_variant; /* persistent kernel: 0 = auto, 1 = generic row-per-thread kernel,
+    int32_t kernel_variant; /* persistent kernel: 0 = auto (owner schedule: the dataflow kernel
+                               when its LDS fits, else 2), 1 = generic row-per-thread kernel,
                                2 = owner kernel with LDS-staged chunks, 3 = owner kernel with
-                               separate compute and fetch waves (one RHS) */
+                               separate compute and fetch waves (one RHS), 4 = dataflow owner
+                               kernel: no per-level barrier, each row waits only for its own
+                               inputs; block_threads (at most 640) sets its compute wavefronts,
+                               ELL width 1..8 (auto width capped at 8), max_nrhs at most 64 */
 } hec_tune_t;
 
 /* Per-RHS outcome of krylov_solve. */
@@ -116,6 +122,7 @@ typedef struct tri_stats {
     int64_t nremote;         /* dependency entries read across workgroups */
     int32_t unit_diag, dtype;
     int32_t crit_hops;       /* most workgroup-to-workgroup handoffs along one dependency chain */
+    int32_t dataflow;        /* 1 when the plan runs on the dataflow owner kernel */
 } tri_stats_t;
 
 typedef struct hec_matrix_s *hec_matrix_t;

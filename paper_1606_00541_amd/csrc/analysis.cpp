@@ -892,17 +892,37 @@ TriHost analyze(const Csr &a, bool upper, bool unit, hec_dtype_t dt, const Tune 
     t.unit = unit;
     t.dt = dt;
     t.lev = compute_levels(a, upper);
-    int32_t w = tune.ell_width >= 0 ? tune.ell_width : auto_ell_width(a, upper);
-    // the dataflow kernel holds 1 to 8 ELL slots per row in registers
-    if (tune.variant == 4 && tune.schedule == HEC_SCHED_OWNER_PERSISTENT) {
-        if (tune.ell_width < 0) w = std::min(w, 8);
-        w = std::max(w, 1);
-    }
-    t.hec = build_hec(a, upper, unit, t.lev, w);
     int64_t off = 0;
     for (int32_t i = 0; i < a.n; ++i) off += offdiag_count(a, i);
     t.nnz_off = off;
-    build_exec(t, a, tune, dev, sys_ptr);
+    auto attempt = [&](const Tune &u) {
+        int32_t w = u.ell_width >= 0 ? u.ell_width : auto_ell_width(a, upper);
+        // the dataflow kernel holds 1 to 8 ELL slots per row in registers
+        if (u.variant == 4 && u.schedule == HEC_SCHED_OWNER_PERSISTENT) {
+            if (u.ell_width < 0) w = std::min(w, 8);
+            w = std::max(w, 1);
+        }
+        t.hec = build_hec(a, upper, unit, t.lev, w);
+        build_exec(t, a, u, dev, sys_ptr);
+    };
+    // automatic choices: the owner schedule, run by the dataflow kernel when
+    // its LDS fits, else by the LDS-chunked owner kernel
+    Tune tu = tune;
+    if (tu.schedule == HEC_SCHED_AUTO) tu.schedule = HEC_SCHED_OWNER_PERSISTENT;
+    if (tu.schedule == HEC_SCHED_OWNER_PERSISTENT && tu.variant == 0) {
+        Tune d = tu;
+        d.variant = 4;
+        if (d.block_threads <= 640 && d.max_nrhs <= 64 && d.ell_width <= 8) {
+            try {
+                attempt(d);
+                return t;
+            } catch (const Error &e) {
+                if (e.code != HEC_ERR_CAPACITY) throw;
+            }
+        }
+        tu.variant = 2;
+    }
+    attempt(tu);
     return t;
 }
 

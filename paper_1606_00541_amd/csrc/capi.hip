@@ -432,6 +432,7 @@ hec_status_t tri_plan_stats(tri_plan_t p, tri_stats_t *s)
         s->nnz_tail = h.nnz_tail;
         s->lds_rows = h.ex.sched.max_window;
         s->crit_hops = h.ex.sched.crit_hops;
+        s->dataflow = h.ex.sched.dataflow ? 1 : 0;
         s->unit_diag = h.unit ? 1 : 0;
         s->dtype = h.dt;
     });
@@ -671,11 +672,19 @@ hec_status_t tri_autotune(int32_t n, const int32_t *rowptr, const int32_t *col, 
         std::vector<Tune> cands;
         Tune base = default_tune();
         base.max_nrhs = nrhs;
+        for (int32_t blk : {256, 384}) {  // dataflow owner kernel (64 * blk / 64 compute lanes)
+            Tune t = base;
+            t.block_threads = blk;
+            t.schedule = HEC_SCHED_OWNER_PERSISTENT;
+            t.variant = 4;
+            if (nrhs <= 64) cands.push_back(t);
+        }
         for (int32_t blk : {256, 512}) {
             Tune t = base;
             t.block_threads = blk;
             t.chunk_rows = std::max(256, blk);
             t.schedule = HEC_SCHED_OWNER_PERSISTENT;
+            t.variant = 2;
             cands.push_back(t);
             for (int32_t mul : {1, 2, 4}) {
                 Tune u = base;
@@ -692,8 +701,10 @@ hec_status_t tri_autotune(int32_t n, const int32_t *rowptr, const int32_t *col, 
             const size_t m = cands.size();
             for (size_t q = 0; q < m; ++q) {
                 Tune t = cands[q];
-                t.ell_width = std::min(64, w0 + 2);
-                cands.push_back(t);
+                const bool df = t.variant == 4;  // one lane per row, ELL width at most 8
+                t.ell_width = std::min(df ? 8 : 64, w0 + 2);
+                if (t.ell_width > w0) cands.push_back(t);
+                if (df) continue;
                 Tune u = cands[q];
                 u.group_lanes = 4;
                 u.long_row = 8;

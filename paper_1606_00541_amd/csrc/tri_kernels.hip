@@ -1087,9 +1087,12 @@ __global__ void __launch_bounds__(768) k_dataflow(TriArgs a)
             const T v = xl[t];
             if (a.write_xw) static_cast<T *>(a.xw)[(size_t)x * R + k] = v;
             if (a.xout) {
-                const size_t dst = (size_t)a.scatter[x] * R + k;
-                if (a.out_f64) static_cast<double *>(a.xout)[dst] = static_cast<double>(v);
-                else static_cast<float *>(a.xout)[dst] = static_cast<float>(v);
+                const int d = a.scatter[x];  // negative: the row is not written (RAS overlap rows)
+                if (d >= 0) {
+                    const size_t dst = (size_t)d * R + k;
+                    if (a.out_f64) static_cast<double *>(a.xout)[dst] = static_cast<double>(v);
+                    else static_cast<float *>(a.xout)[dst] = static_cast<float>(v);
+                }
             }
         }
     }

@@ -75,6 +75,8 @@ def test_levels_map_and_hec_bit_exact(case, sched):
     name, T, upper, unit = _cases()[case]
     if sched == "owner_dataflow":
         t = H.tune_default(host_only=1, schedule="owner_persistent", kernel_variant=4, num_groups=16)
+    elif sched == "owner_persistent":  # the LDS-chunked owner kernel's layout
+        t = H.tune_default(host_only=1, schedule=sched, kernel_variant=2, num_groups=16)
     else:
         t = H.tune_default(host_only=1, schedule=sched, num_groups=16)
     p = H.tri_analyze(T, "upper" if upper else "lower", unit_diag=unit, tune=t)
@@ -185,6 +187,18 @@ def test_ras_layout_matches_oracle():
     nsub, tot, sizes = H.ras_info(s)
     assert nsub == 5 and tot == sum(len(d.ext) for d in doms)
     assert list(sizes) == [len(d.ext) for d in doms]
+
+
+def test_auto_tuning_picks_the_dataflow_kernel_when_it_fits():
+    A = synth.poisson3d(12)
+    L, _ = oracle.ilu0(A)
+    st = H.tri_plan_stats(H.tri_analyze(L, unit_diag=True, tune=HOST))
+    assert st["schedule"] == 3 and st["dataflow"] == 1
+    # one group cannot hold every row in LDS: the chunked owner layout is used
+    A = synth.poisson2d(160)
+    L, _ = oracle.ilu0(A)
+    st = H.tri_plan_stats(H.tri_analyze(L, unit_diag=True, tune=H.tune_default(host_only=1, num_groups=1)))
+    assert st["schedule"] == 3 and st["dataflow"] == 0
 
 
 def test_dataflow_plan_limits():

@@ -21,6 +21,8 @@ def tune(sched, **kw):
     by the dataflow kernel (no per-level barrier)."""
     if sched == "owner_dataflow":
         return H.tune_default(schedule="owner_persistent", kernel_variant=4, **kw)
+    if sched == "owner_persistent":  # the LDS-chunked owner kernel (or its generic fallback)
+        return H.tune_default(schedule=sched, kernel_variant=2, **kw)
     return H.tune_default(schedule=sched, **kw)
 
 
@@ -100,7 +102,7 @@ def test_cooperative_lanes_for_long_rows():
     L = synth.random_lower(n, 0.01, seed=5, dense_row=1500)
     b = synth.rhs(n, 2, 6)
     for sched in ("level_persistent", "owner_persistent"):
-        t = H.tune_default(schedule=sched, group_lanes=8, long_row=4, ell_width=2)
+        t = tune(sched, group_lanes=8, long_row=4, ell_width=2)
         p = H.tri_analyze(L, "lower", tune=t)
         assert relerr(solve(p, b), oracle.lower_solve(L, b)) <= FP64_TOL
 
@@ -174,7 +176,7 @@ def test_owner_chunked_kernel_bit_identical_to_level_launch(block, chunk, nrhs, 
     b = synth.rhs(A.n, nrhs, 13).astype(np.float64 if dt == "f64" else np.float32)
     ref_plan_l = H.tri_analyze(L, "lower", unit_diag=True, dtype=dt, tune=H.tune_default(schedule="level_launch"))
     ref_plan_u = H.tri_analyze(U, "upper", dtype=dt, tune=H.tune_default(schedule="level_launch"))
-    t = H.tune_default(schedule="owner_persistent", block_threads=block, chunk_rows=chunk, max_nrhs=nrhs)
+    t = tune("owner_persistent", block_threads=block, chunk_rows=chunk, max_nrhs=nrhs)
     pl = H.tri_analyze(L, "lower", unit_diag=True, dtype=dt, tune=t)
     pu = H.tri_analyze(U, "upper", dtype=dt, tune=t)
     assert H.tri_plan_stats(pl)["nnz_tail"] == 0
