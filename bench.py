@@ -120,6 +120,11 @@ def _block_diag(mats):
                np.concatenate(vs)), np.array(sys_ptr, np.int32)
 
 
+def _log(msg):
+    """Progress to stderr (the JSON line alone goes to stdout)."""
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
 def _tune(H, args, **kw):
     sched = 0 if args.schedule == "auto" else args.schedule
     return H.tune_default(schedule=sched, kernel_variant=args.kernel_variant, **kw)
@@ -144,6 +149,7 @@ def run_config(cfg, args):
         b = torch.from_numpy(synth.rhs(n, 1, 3)).cuda()
         res = {}
         for fdt in ("f64", "f32"):
+            _log("config 3: ILUT setup, %s factors" % fdt)
             t0 = time.time()
             f = H.ilu_setup(A, "ilut", p=10, tol=1e-3, factor_dtype=fdt, tune=_tune(H, args))
             setup = time.time() - t0
@@ -152,7 +158,9 @@ def run_config(cfg, args):
             sv = 8 if fdt == "f64" else 4
             B = counted_bytes(n, stl["nnz_offdiag"], stu["nnz_offdiag"], 1, sv=sv)
             z = torch.empty_like(b)
+            _log("config 3: timing applies (%s)" % fdt)
             ms = _time_apply(H, torch, f, b, z, args.steps, args.warmup)
+            _log("config 3: FGMRES (%s)" % fdt)
             x, kr = _krylov(H, torch, f, Aop, b, "fgmres")
             res[fdt] = {"apply_ms": round(ms, 4), "apply_GBps": round(B / (ms * 1e-3) / 1e9, 3),
                         "nlev_L": stl["nlev"], "nlev_U": stu["nlev"], "nnz_offdiag_L": stl["nnz_offdiag"],
@@ -173,6 +181,7 @@ def run_config(cfg, args):
         A = synth.poisson3d(128)
         n = A.n
         owner, sizes = synth.subdomain_cuts(n, 64, 8192, 61440, seed=4)
+        _log("config 4: RAS setup")
         t0 = time.time()
         s = H.ras_setup(A, 64, owner, overlap=1, factor_dtype="f32", tune=_tune(H, args, max_nrhs=16))
         setup = time.time() - t0
@@ -184,8 +193,10 @@ def run_config(cfg, args):
         B = (stl["nnz_offdiag"] + stu["nnz_offdiag"]) * 8 + tot * 4 + 2 * 4 * tot + R * (2 * tot * 4 + 2 * n * 8)
         r = torch.from_numpy(synth.rhs(n, R, 4)).cuda()
         z = torch.empty_like(r)
+        _log("config 4: timing applies")
         ms = _time_apply(H, torch, s, r, z, max(3, args.steps // 5), 2, ras=True)
         Aop = H.hec_from_csr(A)
+        _log("config 4: BiCGSTAB")
         x, kr = _krylov(H, torch, s, Aop, r, "bicgstab")
         out.update({"value": round(B / (ms * 1e-3) / 1e9, 3), "dtype": "f32 factors, f64 outer",
                     "ms_per_step": round(ms, 4),
@@ -196,6 +207,7 @@ def run_config(cfg, args):
                                "workgroups": stl["num_groups"]},
                     "solves_per_s": round(1000.0 * R / ms, 2), "bicgstab": kr})
     elif cfg == 5:
+        _log("config 5: generating systems")
         shapes = synth.batch_systems(256, seed=5)
         mats = []
         for i, (dim, side) in enumerate(shapes):
@@ -210,6 +222,7 @@ def run_config(cfg, args):
         Aop = H.hec_from_csr(A)
         res = {}
         for fdt in ("f64", "f32"):
+            _log("config 5: batch ILU(1) setup, %s factors" % fdt)
             t0 = time.time()
             f = H.batch_setup(A, sys_ptr, "iluk", k=1, factor_dtype=fdt, tune=_tune(H, args, max_nrhs=R))
             setup = time.time() - t0
@@ -218,7 +231,9 @@ def run_config(cfg, args):
             sv = 8 if fdt == "f64" else 4
             B = counted_bytes(n, stl["nnz_offdiag"], stu["nnz_offdiag"], R, sv=sv)
             z = torch.empty_like(b)
+            _log("config 5: timing applies (%s)" % fdt)
             ms = _time_apply(H, torch, f, b, z, max(3, args.steps // 5), 2)
+            _log("config 5: FGMRES (%s)" % fdt)
             x, kr = _krylov(H, torch, f, Aop, b, "fgmres")
             res[fdt] = {"apply_ms": round(ms, 4), "apply_GBps": round(B / (ms * 1e-3) / 1e9, 3),
                         "nlev_L": stl["nlev"], "nlev_U": stu["nlev"], "setup_s": round(setup, 3), "fgmres": kr,
