@@ -565,6 +565,17 @@ int32_t critical_hops(const Csr &a, bool upper, const std::vector<int32_t> &own)
     return best;
 }
 
+int32_t dataflow_width(int32_t w)
+{
+    if (w <= 8) return w;
+    if (w <= 10) return 10;
+    if (w <= 12) return 12;
+    if (w <= 16) return 16;
+    return -1;
+}
+
+int32_t dataflow_max_block(int32_t w) { return w > 8 ? 512 : 768; }
+
 size_t dataflow_lds_bytes(int32_t rows, int32_t ints, int32_t R, size_t tsize)
 {
     const size_t vals = (size_t)rows * R * tsize;
@@ -734,14 +745,25 @@ void build_exec(TriHost &t, const Csr &a, const Tune &tune, const DeviceShape &d
         std::vector<int32_t> part_of;
         int32_t gx = 0, gy = 0, gz = 0;
         const bool grid = (tune.partition == 0 || tune.partition == 3) && detect_grid(a, gx, gy, gz);
-        if (grid) {
-            part_of = grid_parts(n, gx, gy, gz, parts);
-        } else if (tune.partition != 2) {
-            part_of.resize(n);
+        auto contiguous = [&]() {
+            std::vector<int32_t> po(n);
             for (int32_t g = 0; g < parts; ++g) {
                 int32_t qb = (int32_t)((int64_t)n * g / parts), qe = (int32_t)((int64_t)n * (g + 1) / parts);
-                for (int32_t q = qb; q < qe; ++q) part_of[t.upper ? n - 1 - q : q] = g;
+                for (int32_t q = qb; q < qe; ++q) po[t.upper ? n - 1 - q : q] = g;
             }
+            return po;
+        };
+        if (grid) {
+            part_of = grid_parts(n, gx, gy, gz, parts);
+            if (tune.partition == 0) {
+                // automatic: grid blocks unless contiguous ranges put fewer
+                // workgroup handoffs on the longest dependency chain (fill-in
+                // can make chains wander across block faces)
+                std::vector<int32_t> po = contiguous();
+                if (critical_hops(a, t.upper, po) < critical_hops(a, t.upper, part_of)) part_of.swap(po);
+            }
+        } else if (tune.partition != 2) {
+            part_of = contiguous();
         } else {
             part_of = bisect_parts(a, parts);
         }
@@ -840,10 +862,12 @@ void build_exec(TriHost &t, const Csr &a, const Tune &tune, const DeviceShape &d
     ex.sched.kind = kind;
     // the dataflow owner kernel runs each step as one wavefront's unit (at
     // most 64 (row, rhs) items); the other owner kernels cut steps to chunks
-    if (want_df && w > 8) fail(HEC_ERR_INVALID_ARG, "dataflow kernel: ELL width above 8");
+    if (want_df && dataflow_width(w) != w)
+        fail(HEC_ERR_INVALID_ARG, "dataflow kernel: ELL width must be 1..8, 10, 12 or 16");
     if (want_df && R > 64) fail(HEC_ERR_INVALID_ARG, "dataflow kernel: max_nrhs above 64");
-    if (want_df && tune.block_threads > 640)
-        fail(HEC_ERR_INVALID_ARG, "dataflow kernel: block_threads above 640 (two more wavefronts are added)");
+    if (want_df && tune.block_threads > dataflow_max_block(w) - 128)
+        fail(HEC_ERR_CAPACITY, "dataflow kernel: block_threads above " + std::to_string(dataflow_max_block(w) - 128) +
+                                   " for ELL width " + std::to_string(w) + " (two more wavefronts are added)");
     if (kind == HEC_SCHED_OWNER_PERSISTENT) {
         const int32_t piece = want_df ? std::max(1, 64 / R) : tune.chunk_rows;
         if (piece <= 0) fail(HEC_ERR_INVALID_ARG, "internal: chunk_rows must be positive");
@@ -897,10 +921,17 @@ TriHost analyze(const Csr &a, bool upper, bool unit, hec_dtype_t dt, const Tune 
     t.nnz_off = off;
     auto attempt = [&](const Tune &u) {
         int32_t w = u.ell_width >= 0 ? u.ell_width : auto_ell_width(a, upper);
-        // the dataflow kernel holds 1 to 8 ELL slots per row in registers
+        // The dataflow kernel holds the ELL slots of a row in registers (widths
+        // 1..8, 10, 12, 16).  Its CSR tail is read with an exposed load
+        // latency on the dependency chain, so the automatic width covers the
+        // longest row when that fits; padding costs bytes, not latency.
         if (u.variant == 4 && u.schedule == HEC_SCHED_OWNER_PERSISTENT) {
-            if (u.ell_width < 0) w = std::min(w, 8);
-            w = std::max(w, 1);
+            if (u.ell_width < 0) {
+                int32_t wmax = 0;
+                for (int32_t i = 0; i < a.n; ++i) wmax = std::max(wmax, offdiag_count(a, i));
+                w = std::min(std::max(w, wmax), 16);
+            }
+            w = dataflow_width(std::min(std::max(w, 1), 16));
         }
         t.hec = build_hec(a, upper, unit, t.lev, w);
         build_exec(t, a, u, dev, sys_ptr);
@@ -912,7 +943,7 @@ TriHost analyze(const Csr &a, bool upper, bool unit, hec_dtype_t dt, const Tune 
     if (tu.schedule == HEC_SCHED_OWNER_PERSISTENT && tu.variant == 0) {
         Tune d = tu;
         d.variant = 4;
-        if (d.block_threads <= 640 && d.max_nrhs <= 64 && d.ell_width <= 8) {
+        if (d.block_threads <= 640 && d.max_nrhs <= 64 && d.ell_width <= 16) {
             try {
                 attempt(d);
                 return t;

@@ -701,8 +701,8 @@ hec_status_t tri_autotune(int32_t n, const int32_t *rowptr, const int32_t *col, 
             const size_t m = cands.size();
             for (size_t q = 0; q < m; ++q) {
                 Tune t = cands[q];
-                const bool df = t.variant == 4;  // one lane per row, ELL width at most 8
-                t.ell_width = std::min(df ? 8 : 64, w0 + 2);
+                const bool df = t.variant == 4;  // one lane per row, ELL width at most 16
+                t.ell_width = df ? dataflow_width(std::min(16, w0 + 2)) : std::min(64, w0 + 2);
                 if (t.ell_width > w0) cands.push_back(t);
                 if (df) continue;
                 Tune u = cands[q];

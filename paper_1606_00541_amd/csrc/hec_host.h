@@ -145,6 +145,10 @@ struct Tune {
 // window and imports) of R right-hand sides, then `ints` int32 entries
 // (import slots, export rows, step bounds).
 size_t dataflow_lds_bytes(int32_t rows, int32_t ints, int32_t R, size_t tsize);
+// Smallest ELL width >= w the dataflow kernel is built for (1..8, 10, 12,
+// 16), or -1 above 16; and its largest workgroup (threads) at that width.
+int32_t dataflow_width(int32_t w);
+int32_t dataflow_max_block(int32_t w);
 // Tuning with every field at its documented default.
 Tune default_tune();
 Tune tune_from(const hec_tune_t *t);

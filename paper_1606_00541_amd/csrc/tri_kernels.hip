@@ -802,7 +802,7 @@ template <typename T, int W> struct DfRegs {
 };
 
 template <typename T, int W, bool UNIT, bool TAIL, bool R1>
-__global__ void __launch_bounds__(768) k_dataflow(TriArgs a)
+__global__ void __launch_bounds__(W > 8 ? 512 : 768) k_dataflow(TriArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ unsigned s_epoch;
@@ -1118,6 +1118,9 @@ OwnerKernel dataflow_kernel_w(int w)
     case 6: return k_dataflow<T, 6, UNIT, TAIL, R1>;
     case 7: return k_dataflow<T, 7, UNIT, TAIL, R1>;
     case 8: return k_dataflow<T, 8, UNIT, TAIL, R1>;
+    case 10: return k_dataflow<T, 10, UNIT, TAIL, R1>;
+    case 12: return k_dataflow<T, 12, UNIT, TAIL, R1>;
+    case 16: return k_dataflow<T, 16, UNIT, TAIL, R1>;
     default: return nullptr;
     }
 }
@@ -1185,7 +1188,7 @@ void launch_typed(DevTri &d, TriArgs a, hipStream_t st)
         size_t lds = dataflow_lds_bytes(d.df_rows, d.df_ints, a.R, sizeof(T));
         if (a.trace) lds += 8 + 16 * (size_t)std::min(d.df_ints / 2, a.trace_stride);  // per-step clocks
         const int block = 64 * d.df_waves + 128;
-        if (block > 768) fail(HEC_ERR_INVALID_ARG, "dataflow kernel: block too large");
+        if (block > dataflow_max_block(d.w)) fail(HEC_ERR_INVALID_ARG, "dataflow kernel: block too large");
         if (lds > (size_t)device_max_lds())
             fail(HEC_ERR_CAPACITY, "dataflow kernel: LDS need exceeds the device limit at this nrhs");
         if (capacity_of((const void *)k, block, lds) < d.groups)

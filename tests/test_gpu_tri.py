@@ -239,3 +239,23 @@ def test_dataflow_kernel_with_csr_tails():
                           tune=tune("owner_dataflow", ell_width=2, max_nrhs=2))
         assert H.tri_plan_stats(p)["nnz_tail"] > 0
         assert np.array_equal(solve(p, b, up), solve(ref, b, up))
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("nrhs", [1, 2])
+def test_dataflow_wide_rows_bit_identical(dt, nrhs):
+    # ILUT rows of up to 12 entries: the dataflow kernel's automatic width
+    # covers the longest row (widths 10, 12 or 16), so no CSR tail is left
+    A = synth.diffusion3d(13, 12, 11, 2.0, seed=8)
+    L, U = oracle.ilut(A, 12, 1e-4)
+    if dt == "f32":
+        L, U = oracle.to_f32(L), oracle.to_f32(U)
+    b = synth.rhs(A.n, nrhs, 9).astype(np.float64 if dt == "f64" else np.float32)
+    for T, up, unit in ((L, False, True), (U, True, False)):
+        uplo = "upper" if up else "lower"
+        ref = H.tri_analyze(T, uplo, unit_diag=unit, dtype=dt, tune=H.tune_default(schedule="level_launch"))
+        p = H.tri_analyze(T, uplo, unit_diag=unit, dtype=dt, tune=tune("owner_dataflow", max_nrhs=nrhs))
+        st = H.tri_plan_stats(p)
+        assert st["ell_width"] in (10, 12, 16) and st["nnz_tail"] == 0 and st["dataflow"] == 1
+        for rep in range(2):
+            assert np.array_equal(solve(p, b, up), solve(ref, b, up))
