@@ -161,7 +161,7 @@ def run_config(cfg, args):
             _log("config 3: timing applies (%s)" % fdt)
             ms = _time_apply(H, torch, f, b, z, args.steps, args.warmup)
             _log("config 3: FGMRES (%s)" % fdt)
-            x, kr = _krylov(H, torch, f, Aop, b, "fgmres")
+            x, kr = (torch.zeros_like(b), None) if args.no_krylov else _krylov(H, torch, f, Aop, b, "fgmres")
             res[fdt] = {"apply_ms": round(ms, 4), "apply_GBps": round(B / (ms * 1e-3) / 1e9, 3),
                         "nlev_L": stl["nlev"], "nlev_U": stu["nlev"], "nnz_offdiag_L": stl["nnz_offdiag"],
                         "nnz_offdiag_U": stu["nnz_offdiag"], "setup_s": round(setup, 3), "fgmres": kr,
@@ -175,8 +175,8 @@ def run_config(cfg, args):
                     "config": {"workload": "heterogeneous 3D 7-point diffusion 100^3, lognormal sigma=2 seed 3, "
                                            "ILUT(tol 1e-3, p 10); FGMRES(30) to 1e-10"},
                     "fp64": res["f64"], "fp32_refined": res["f32"], "rel_diff_fp32_vs_fp64_solution": d,
-                    "fp32_time_ratio_vs_fp64": round(res["f32"]["fgmres"]["seconds"] /
-                                                     res["f64"]["fgmres"]["seconds"], 4)})
+                    "fp32_time_ratio_vs_fp64": None if args.no_krylov else
+                    round(res["f32"]["fgmres"]["seconds"] / res["f64"]["fgmres"]["seconds"], 4)})
     elif cfg == 4:
         A = synth.poisson3d(128)
         n = A.n
@@ -197,7 +197,7 @@ def run_config(cfg, args):
         ms = _time_apply(H, torch, s, r, z, max(3, args.steps // 5), 2, ras=True)
         Aop = H.hec_from_csr(A)
         _log("config 4: BiCGSTAB")
-        x, kr = _krylov(H, torch, s, Aop, r, "bicgstab")
+        x, kr = (None, None) if args.no_krylov else _krylov(H, torch, s, Aop, r, "bicgstab")
         out.update({"value": round(B / (ms * 1e-3) / 1e9, 3), "dtype": "f32 factors, f64 outer",
                     "ms_per_step": round(ms, 4),
                     "config": {"workload": "RAS on 128^3 Poisson: 64 seeded contiguous subdomains (8192..61440 "
@@ -234,19 +234,19 @@ def run_config(cfg, args):
             _log("config 5: timing applies (%s)" % fdt)
             ms = _time_apply(H, torch, f, b, z, max(3, args.steps // 5), 2)
             _log("config 5: FGMRES (%s)" % fdt)
-            x, kr = _krylov(H, torch, f, Aop, b, "fgmres")
+            x, kr = (None, None) if args.no_krylov else _krylov(H, torch, f, Aop, b, "fgmres")
             res[fdt] = {"apply_ms": round(ms, 4), "apply_GBps": round(B / (ms * 1e-3) / 1e9, 3),
                         "nlev_L": stl["nlev"], "nlev_U": stu["nlev"], "setup_s": round(setup, 3), "fgmres": kr,
                         "dataflow": stl["dataflow"], "workgroups": stl["num_groups"],
-                        "systems_per_s": round(len(mats) * R / kr["seconds"], 3)}
+                        "systems_per_s": None if kr is None else round(len(mats) * R / kr["seconds"], 3)}
         out.update({"value": res["f32"]["apply_GBps"], "dtype": "f32 factors, f64 refinement",
                     "ms_per_step": res["f32"]["apply_ms"],
                     "config": {"workload": "256 independent systems (log-uniform 1e3..2e5 rows, 2D/3D lognormal "
                                            "sigma=1), ILU(1), 8 RHS each; FGMRES(30) to 1e-10",
                                "n_total": int(n), "systems": len(mats)},
                     "fp64": res["f64"], "fp32_refined": res["f32"],
-                    "fp32_speedup_vs_fp64_time_to_1e-10": round(res["f64"]["fgmres"]["seconds"] /
-                                                                res["f32"]["fgmres"]["seconds"], 4)})
+                    "fp32_speedup_vs_fp64_time_to_1e-10": None if args.no_krylov else
+                    round(res["f64"]["fgmres"]["seconds"] / res["f32"]["fgmres"]["seconds"], 4)})
     else:
         raise SystemExit("unknown --config %d" % cfg)
     print(json.dumps(out))

@@ -56,7 +56,9 @@ typedef enum hec_uplo { HEC_LOWER = 0, HEC_UPPER = 1 } hec_uplo_t;
 /* How the level sets are executed on the device (all give bit-identical
  * results for the same plan, since every row is computed the same way). */
 typedef enum hec_schedule {
-    HEC_SCHED_AUTO = 0,              /* the owner schedule (kernel chosen by kernel_variant) */
+    HEC_SCHED_AUTO = 0,              /* the owner schedule on the dataflow kernel when its LDS
+                                        holds every part for max_nrhs right-hand sides, else
+                                        one launch per level */
     HEC_SCHED_LEVEL_LAUNCH = 1,      /* one kernel launch per level (Algorithm 2 shape) */
     HEC_SCHED_LEVEL_PERSISTENT = 2,  /* one persistent launch; each level split into
                                         per-workgroup chunks; a chunk polls the values it
@@ -78,7 +80,8 @@ typedef struct hec_tune {
     int32_t ell_width;      /* HEC ELL width w; -1 = smallest w with at most half the
                                rows having more than w off-diagonals */
     int32_t schedule;       /* hec_schedule_t */
-    int32_t num_groups;     /* persistent workgroups; 0 = the device's co-resident capacity */
+    int32_t num_groups;     /* persistent workgroups; 0 = one per compute unit (at most the
+                               co-resident capacity; larger requests fail with CAPACITY) */
     int32_t merge_rows;     /* level-merge threshold: a level with fewer rows than this
                                is not split across workgroups */
     int32_t group_lanes;    /* lanes cooperating on one row when a step holds long
@@ -96,7 +99,8 @@ typedef struct hec_tune {
                                structured grid, else contiguous), 1 = contiguous ranges of the
                                problem order, 2 = recursive graph bisection, 3 = grid blocks */
     int32_t kernel_variant; /* persistent kernel: 0 = auto (owner schedule: the dataflow kernel
-                               when its LDS fits, else 2), 1 = generic row-per-thread kernel,
+                               when its LDS fits, else 2; with schedule AUTO the fallback is one
+                               launch per level), 1 = generic row-per-thread kernel,
                                2 = owner kernel with LDS-staged chunks, 3 = owner kernel with
                                separate compute and fetch waves (one RHS), 4 = dataflow owner
                                kernel: no per-level barrier, each row waits only for its own

@@ -697,9 +697,10 @@ void build_exec(TriHost &t, const Csr &a, const Tune &tune, const DeviceShape &d
     const int32_t groups_cap = dev.groups_cap;
     const int32_t cap = groups_cap > 0 ? groups_cap : 256;
     const int32_t cus = dev.cus > 0 ? dev.cus : 256;
-    // level schedule: as many groups as fit; owner schedule: one part per CU
-    int32_t G = tune.num_groups > 0 ? tune.num_groups
-                                    : (kind == HEC_SCHED_OWNER_PERSISTENT ? std::min(cap, cus) : cap);
+    // one workgroup per CU by default: every workgroup of a persistent grid
+    // must be resident at once, and one per CU does not lean on the last
+    // wavefront slot the occupancy query promises
+    int32_t G = tune.num_groups > 0 ? tune.num_groups : std::min(cap, cus);
     if (tune.num_groups > 0 && groups_cap > 0 && tune.num_groups > groups_cap)
         fail(HEC_ERR_CAPACITY, "num_groups " + std::to_string(tune.num_groups) +
                                    " exceeds the co-resident capacity " + std::to_string(groups_cap));
@@ -936,10 +937,14 @@ TriHost analyze(const Csr &a, bool upper, bool unit, hec_dtype_t dt, const Tune 
         t.hec = build_hec(a, upper, unit, t.lev, w);
         build_exec(t, a, u, dev, sys_ptr);
     };
-    // automatic choices: the owner schedule, run by the dataflow kernel when
-    // its LDS fits, else by the LDS-chunked owner kernel
+    // Automatic schedule: the owner schedule on the dataflow kernel when its
+    // LDS holds every part (rows x right-hand sides); otherwise the system is
+    // large, its levels are wide, and one launch per level keeps the whole
+    // GPU busy without any cross-workgroup waits.  An explicit owner
+    // schedule without a kernel choice falls back to the LDS-chunked kernel.
     Tune tu = tune;
-    if (tu.schedule == HEC_SCHED_AUTO) tu.schedule = HEC_SCHED_OWNER_PERSISTENT;
+    const bool auto_sched = tu.schedule == HEC_SCHED_AUTO;
+    if (auto_sched) tu.schedule = HEC_SCHED_OWNER_PERSISTENT;
     if (tu.schedule == HEC_SCHED_OWNER_PERSISTENT && tu.variant == 0) {
         Tune d = tu;
         d.variant = 4;
@@ -951,7 +956,8 @@ TriHost analyze(const Csr &a, bool upper, bool unit, hec_dtype_t dt, const Tune 
                 if (e.code != HEC_ERR_CAPACITY) throw;
             }
         }
-        tu.variant = 2;
+        if (auto_sched) tu.schedule = HEC_SCHED_LEVEL_LAUNCH;
+        else tu.variant = 2;
     }
     attempt(tu);
     return t;

@@ -194,10 +194,14 @@ def test_auto_tuning_picks_the_dataflow_kernel_when_it_fits():
     L, _ = oracle.ilu0(A)
     st = H.tri_plan_stats(H.tri_analyze(L, unit_diag=True, tune=HOST))
     assert st["schedule"] == 3 and st["dataflow"] == 1
-    # one group cannot hold every row in LDS: the chunked owner layout is used
+    # one group cannot hold every row in LDS: one launch per level
     A = synth.poisson2d(160)
     L, _ = oracle.ilu0(A)
     st = H.tri_plan_stats(H.tri_analyze(L, unit_diag=True, tune=H.tune_default(host_only=1, num_groups=1)))
+    assert st["schedule"] == 1 and st["dataflow"] == 0
+    # an explicit owner schedule falls back to the LDS-chunked owner kernel
+    st = H.tri_plan_stats(H.tri_analyze(L, unit_diag=True, tune=H.tune_default(
+        host_only=1, schedule="owner_persistent", num_groups=1)))
     assert st["schedule"] == 3 and st["dataflow"] == 0
 
 
