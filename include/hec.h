@@ -278,9 +278,10 @@ void ras_destroy(ras_t ras);
  * Batched independent systems (eq. (4)): the block-diagonal matrix
  * diag(A_1..A_s) given as one CSR of n = sum n_i rows whose rows
  * sys_ptr[i]..sys_ptr[i+1]-1 form system i (no coupling across systems),
- * factored block by block (ILU kind as ilu_setup) and solved in one persistent
- * launch per triangle with one scheduling group per system.  The returned
- * handle is an ilu_t: ilu_apply, ilu_plans, ilu_factor and krylov_solve apply.
+ * factored block by block (ILU kind as ilu_setup) and solved with one launch
+ * per triangle (or per level, see HEC_SCHED_AUTO) for all systems together.  The
+ * returned handle is an ilu_t: ilu_apply, ilu_plans, ilu_factor, krylov_solve
+ * and krylov_solve_batch apply.
  * ------------------------------------------------------------------------- */
 hec_status_t batch_setup(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val,
                          int32_t nsys, const int32_t *sys_ptr, hec_ilu_kind_t kind, int32_t k,
@@ -302,6 +303,20 @@ hec_status_t batch_setup(int32_t n, const int32_t *rowptr, const int32_t *col, c
 hec_status_t krylov_solve(hec_matrix_t A, hec_precond_t M, hec_krylov_t method, int32_t m,
                           const double *b, double *x, int32_t nrhs, double rtol, int32_t maxit,
                           hec_krylov_info_t *info, hipStream_t stream);
+
+/* Independent systems solved together (eq. (4) form): A (and M) block-diagonal
+ * with blocks sys_ptr[s]..sys_ptr[s+1]-1 (host array of nsys+1 entries, 0 to n;
+ * an entry of A coupling two blocks is INVALID_ARG).  Every (system, rhs) pair is
+ * its own Krylov problem: its own inner products, Hessenberg matrix, step sizes
+ * and stopping test ||b_s - A_s x_s|| / ||b_s|| <= rtol, as if each system were
+ * solved alone, while every operator and preconditioner application covers all
+ * systems at once.  info: host array of nsys*nrhs entries, entry s*nrhs + k for
+ * system s and right-hand side k.  At most 16384 pairs.  Other arguments and
+ * errors as krylov_solve. */
+hec_status_t krylov_solve_batch(hec_matrix_t A, hec_precond_t M, hec_krylov_t method, int32_t m,
+                                int32_t nsys, const int32_t *sys_ptr, const double *b, double *x,
+                                int32_t nrhs, double rtol, int32_t maxit, hec_krylov_info_t *info,
+                                hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * HIP graph of one preconditioner application (kind HEC_PRECOND_ILU or

@@ -99,6 +99,7 @@ SIGNATURES = {
     "ras_destroy": (None, [_vp]),
     "batch_setup": (_i32, [_i32, _vp, _vp, _vp, _i32, _vp, _i32, _i32, _f64, _i32, _i32, _P(Tune), _P(_vp)]),
     "krylov_solve": (_i32, [_vp, Precond, _i32, _i32, _vp, _vp, _i32, _f64, _i32, _vp, _vp]),
+    "krylov_solve_batch": (_i32, [_vp, Precond, _i32, _i32, _i32, _vp, _vp, _vp, _i32, _f64, _i32, _vp, _vp]),
     "hec_graph_capture": (_i32, [Precond, _vp, _vp, _i32, _i32, _vp, _P(_vp)]),
     "hec_graph_launch": (_i32, [_vp, _vp]),
     "hec_graph_destroy": (None, [_vp]),
@@ -449,6 +450,25 @@ def krylov_solve(A: HecMatrix, M, b, x, method="fgmres", m=30, rtol=1e-10, maxit
     infos = (KrylovInfo * R)()
     st = lib().krylov_solve(A.ptr, _precond(M), KRYLOV[method], int(m), pb, px, R, float(rtol), int(maxit),
                             ctypes.cast(infos, ctypes.c_void_p), _stream(stream))
+    if st != HEC_OK and (raise_on_fail or st not in (8, 9)):
+        _check(st)
+    return st, list(infos)
+
+
+def krylov_solve_batch(A: HecMatrix, M, sys_ptr, b, x, method="fgmres", m=30, rtol=1e-10, maxit=10000,
+                       stream=None, raise_on_fail=False):
+    """Solve the independent systems of a block-diagonal A (blocks given by
+    sys_ptr) together, each (system, rhs) pair as its own Krylov problem.
+    Returns (status, [KrylovInfo per pair, system-major])."""
+    pb, R, db = _vec(b, A.n)
+    px, R2, dx = _vec(x, A.n)
+    if R != R2 or db != HEC_F64 or dx != HEC_F64:
+        raise ValueError("krylov_solve_batch takes FP64 b and x of equal shape")
+    sp = _np(sys_ptr, np.int32)
+    nsys = len(sp) - 1
+    infos = (KrylovInfo * (nsys * R))()
+    st = lib().krylov_solve_batch(A.ptr, _precond(M), KRYLOV[method], int(m), nsys, sp.ctypes.data, pb, px, R,
+                                  float(rtol), int(maxit), ctypes.cast(infos, ctypes.c_void_p), _stream(stream))
     if st != HEC_OK and (raise_on_fail or st not in (8, 9)):
         _check(st)
     return st, list(infos)

@@ -495,7 +495,6 @@ hec_status_t batch_setup(int32_t n, const int32_t *rowptr, const int32_t *col, c
         for (int32_t s = 0; s < nsys; ++s)
             if (sys_ptr[s + 1] < sys_ptr[s]) fail(HEC_ERR_INVALID_ARG, "sys_ptr not monotone");
         Tune tu = tune_from(tune);
-        if (tu.schedule == HEC_SCHED_AUTO) tu.schedule = HEC_SCHED_OWNER_PERSISTENT;
         Csr a = csr_copy(n, rowptr, col, val, HEC_F64);
         // eq. (4): the systems must not couple
         for (int32_t s = 0; s < nsys; ++s)
@@ -546,7 +545,6 @@ hec_status_t ras_setup(int32_t n, const int32_t *rowptr, const int32_t *col, con
         if (!out) fail(HEC_ERR_INVALID_ARG, "out is NULL");
         if (fdt != HEC_F64 && fdt != HEC_F32) fail(HEC_ERR_INVALID_ARG, "bad factor dtype");
         Tune tu = tune_from(tune);
-        if (tu.schedule == HEC_SCHED_AUTO) tu.schedule = HEC_SCHED_OWNER_PERSISTENT;
         Csr a = csr_copy(n, rowptr, col, val, HEC_F64);
         auto s = std::make_unique<ras_s>();
         s->n = n;

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <string>
 #include <vector>
 
 #include "hec_dev.h"
@@ -56,19 +57,31 @@ struct DotArgs {
     int np;
 };
 
-// partial[blk][pair][k] = sum over this block's rows of a_pair * b_pair.
-// Threads of a block are arranged as (rows x R): thread t owns rhs t % R.
-__global__ void __launch_bounds__(256) k_dot_partial(DotArgs d, long n, int R, int rows_per_iter, double *partial)
+// Column of vector element t of an [n][R] vector: the right-hand side k, or
+// for a batch of independent systems (seg = system of each row) the problem
+// (system, k) numbered system-major.
+__device__ __forceinline__ int col_of(long t, int R, const int32_t *seg)
+{
+    const long row = t / R;
+    const int k = (int)(t - row * R);
+    return seg ? seg[row] * R + k : k;
+}
+
+// partial[blk][pair][k] = sum over the block's rows [brow[2 blk], brow[2 blk + 1])
+// of a_pair * b_pair (a block never spans two systems).  Threads of a block
+// are arranged as (rows x R): thread t owns rhs t % R.
+__global__ void __launch_bounds__(256) k_dot_partial(DotArgs d, int R, int rows_per_iter, const int32_t *brow,
+                                                     double *partial)
 {
     __shared__ double red[256];
     const int tid = threadIdx.x;
     const int used = rows_per_iter * R;
     const int k = tid % R, r0 = tid / R;
+    const long row0 = brow[2 * blockIdx.x], row1 = brow[2 * blockIdx.x + 1];
     for (int p = 0; p < d.np; ++p) {
         double acc = 0.0;
         if (tid < used)
-            for (long row = (long)blockIdx.x * rows_per_iter + r0; row < n; row += (long)gridDim.x * rows_per_iter)
-                acc += d.a[p][row * R + k] * d.b[p][row * R + k];
+            for (long row = row0 + r0; row < row1; row += rows_per_iter) acc += d.a[p][row * R + k] * d.b[p][row * R + k];
         red[tid] = acc;
         __syncthreads();
         // fold the rows dimension: threads with the same k
@@ -83,56 +96,58 @@ __global__ void __launch_bounds__(256) k_dot_partial(DotArgs d, long n, int R, i
     }
 }
 
-__global__ void k_dot_final(const double *partial, int nblk, int np, int R, double *out)
+// out[p][col] = sum of the partials of the blocks of col's system, in block order
+__global__ void k_dot_final(const double *partial, const int32_t *bptr, int np, int R, int P, double *out)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= np * R) return;
+    if (t >= np * P) return;
+    const int p = t / P, col = t - p * P, sys = col / R, k = col - sys * R;
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += partial[(size_t)b * np * R + t];
+    for (int b = bptr[sys]; b < bptr[sys + 1]; ++b) s += partial[((size_t)b * np + p) * R + k];
     out[t] = s;
 }
 
 struct LinArgs {
     const double *in[kMaxTerms];
     int nt;
-    const double *coef;  // [nt][R]
+    const double *coef;  // [nt][P]
     double *out;
     double *out2;        // optional second output receiving the same value
 };
 
-// out[:,k] = sum_t coef[t][k] * in_t[:,k]
-__global__ void __launch_bounds__(256) k_lincomb(LinArgs a, long total, int R)
+// out[:,c] = sum_t coef[t][c] * in_t[:,c]
+__global__ void __launch_bounds__(256) k_lincomb(LinArgs a, long total, int R, int P, const int32_t *seg)
 {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total) return;
-    const int k = (int)(t % R);
+    const int c = col_of(t, R, seg);
     double s = 0.0;
-    for (int q = 0; q < a.nt; ++q) s += a.coef[q * R + k] * a.in[q][t];
+    for (int q = 0; q < a.nt; ++q) s += a.coef[q * P + c] * a.in[q][t];
     a.out[t] = s;
     if (a.out2) a.out2[t] = s;
 }
 
-// w[:,k] -= sum_{i<nv} h[i][k] * V_i[:,k]   (V_i = V + i*stride)
+// w[:,c] -= sum_{i<nv} h[i][c] * V_i[:,c]   (V_i = V + i*stride)
 __global__ void __launch_bounds__(256) k_gs_update(double *w, const double *V, long stride, const double *h, int nv,
-                                                  long total, int R)
+                                                  long total, int R, int P, const int32_t *seg)
 {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total) return;
-    const int k = (int)(t % R);
+    const int c = col_of(t, R, seg);
     double s = w[t];
-    for (int i = 0; i < nv; ++i) s -= h[i * R + k] * V[i * stride + t];
+    for (int i = 0; i < nv; ++i) s -= h[i * P + c] * V[i * stride + t];
     w[t] = s;
 }
 
-// x[:,k] += sum_{i<nv} y[i][k] * Z_i[:,k]
+// x[:,c] += sum_{i<nv} y[i][c] * Z_i[:,c]
 __global__ void __launch_bounds__(256) k_basis_update(double *x, const double *Z, long stride, const double *y, int nv,
-                                                     long total, int R)
+                                                     long total, int R, int P, const int32_t *seg)
 {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total) return;
-    const int k = (int)(t % R);
+    const int c = col_of(t, R, seg);
     double s = 0.0;
-    for (int i = 0; i < nv; ++i) s += y[i * R + k] * Z[i * stride + t];
+    for (int i = 0; i < nv; ++i) s += y[i * P + c] * Z[i * stride + t];
     x[t] += s;
 }
 
@@ -188,29 +203,56 @@ void convert_vec(const void *src, hec_dtype_t sdt, void *dst, hec_dtype_t ddt, s
 
 namespace {
 
-// Scratch and helpers of one Krylov solve.
+// Scratch and helpers of one Krylov solve.  The vectors are [n][R]; the
+// solve runs P independent problems: the R right-hand sides, or for a batch
+// of nsys independent diagonal blocks (rows sys_ptr[s]..sys_ptr[s+1]-1) the
+// nsys x R pairs (system, rhs), numbered system-major.  Inner products are
+// taken per problem, in a fixed block order (deterministic).
 struct Ctx {
     hipStream_t st;
     long n;
-    int R;
-    DevMem partial, dots, coef;
-    double *hbuf = nullptr;  // pinned host scalars
+    int R, P;
+    DevMem partial, dots, coef, segm, browm, bptrm;
+    const int32_t *seg = nullptr;  // row -> system (batches only)
+    double *hbuf = nullptr;        // pinned host scalars
     int nblk, rows_per_iter;
-    Ctx(long n_, int R_, hipStream_t s) : st(s), n(n_), R(R_)
+    Ctx(long n_, int R_, hipStream_t s, int nsys = 1, const int32_t *sys_ptr = nullptr) : st(s), n(n_), R(R_)
     {
+        P = nsys * R;
         rows_per_iter = std::max(1, 256 / R);
-        nblk = (int)std::min<long>(1024, std::max<long>(1, (n + rows_per_iter - 1) / rows_per_iter));
+        // reduction blocks: each covers rows of one system only
+        const long chunk = std::max<long>((long)rows_per_iter * 4, (n + 1023) / 1024);
+        std::vector<int32_t> brow, bptr(1, 0);
+        for (int sy = 0; sy < nsys; ++sy) {
+            const long r0 = sys_ptr ? sys_ptr[sy] : 0, r1 = sys_ptr ? sys_ptr[sy + 1] : n;
+            for (long r = r0; r < r1; r += chunk) {
+                brow.push_back((int32_t)r);
+                brow.push_back((int32_t)std::min(r1, r + chunk));
+            }
+            bptr.push_back((int32_t)(brow.size() / 2));
+        }
+        if (brow.empty()) brow = {0, 0};
+        nblk = (int)(brow.size() / 2);
+        upload(browm, brow);
+        upload(bptrm, bptr);
+        if (nsys > 1) {
+            std::vector<int32_t> sg((size_t)n);
+            for (int sy = 0; sy < nsys; ++sy)
+                for (int32_t i = sys_ptr[sy]; i < sys_ptr[sy + 1]; ++i) sg[i] = sy;
+            upload(segm, sg);
+            seg = segm.as<int32_t>();
+        }
         partial.alloc(sizeof(double) * (size_t)nblk * kMaxPairs * R);
-        dots.alloc(sizeof(double) * kMaxPairs * R);
-        coef.alloc(sizeof(double) * (size_t)std::max(kMaxPairs, kMaxTerms) * R);
-        hip_check(hipHostMalloc((void **)&hbuf, sizeof(double) * (size_t)std::max(kMaxPairs, kMaxTerms) * R, 0),
+        dots.alloc(sizeof(double) * kMaxPairs * P);
+        coef.alloc(sizeof(double) * (size_t)std::max(kMaxPairs, kMaxTerms) * P);
+        hip_check(hipHostMalloc((void **)&hbuf, sizeof(double) * (size_t)std::max(kMaxPairs, kMaxTerms) * P, 0),
                   "hipHostMalloc");
     }
     ~Ctx()
     {
         if (hbuf) (void)hipHostFree(hbuf);
     }
-    // inner products of np pairs, per RHS, returned in hbuf[p*R + k]
+    // inner products of np pairs, per problem, returned in hbuf[p*P + c]
     void dots_to_host(const double *const *a, const double *const *b, int np)
     {
         DotArgs d{};
@@ -219,15 +261,15 @@ struct Ctx {
             d.b[p] = b[p];
         }
         d.np = np;
-        hipLaunchKernelGGL(k_dot_partial, dim3(nblk), dim3(256), 0, st, d, n, R, rows_per_iter,
+        hipLaunchKernelGGL(k_dot_partial, dim3(nblk), dim3(256), 0, st, d, R, rows_per_iter, browm.as<int32_t>(),
                            partial.as<double>());
-        hipLaunchKernelGGL(k_dot_final, dim3((np * R + 255) / 256), dim3(256), 0, st, partial.as<double>(), nblk, np,
-                           R, dots.as<double>());
+        hipLaunchKernelGGL(k_dot_final, dim3((np * P + 255) / 256), dim3(256), 0, st, partial.as<double>(),
+                           bptrm.as<int32_t>(), np, R, P, dots.as<double>());
         hip_check(hipGetLastError(), "dot launch");
-        hip_check(hipMemcpyAsync(hbuf, dots.p, sizeof(double) * np * R, hipMemcpyDeviceToHost, st), "D2H");
+        hip_check(hipMemcpyAsync(hbuf, dots.p, sizeof(double) * np * P, hipMemcpyDeviceToHost, st), "D2H");
         hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
     }
-    // out = sum_t c[t][k] in_t   (coefficients given on the host)
+    // out = sum_t c[t][col] in_t   (coefficients given on the host, [nt][P])
     void lincomb(double *out, const std::vector<const double *> &in, const std::vector<double> &c,
                  double *out2 = nullptr)
     {
@@ -240,7 +282,7 @@ struct Ctx {
         a.coef = coef.as<double>();
         const long total = n * R;
         if (total == 0) return;
-        hipLaunchKernelGGL(k_lincomb, dim3(blocks_for(total)), dim3(256), 0, st, a, total, R);
+        hipLaunchKernelGGL(k_lincomb, dim3(blocks_for(total)), dim3(256), 0, st, a, total, R, P, seg);
         hip_check(hipGetLastError(), "k_lincomb launch");
     }
     void upload_coef(const std::vector<double> &c)
@@ -281,11 +323,12 @@ void apply_M(const hec_precond_t &M, const double *r, double *z, int R, long n, 
 // rotations on the host.  Every RHS runs its own Arnoldi process in lockstep;
 // an RHS whose rotated residual reaches rtol stops extending its basis.
 hec_status_t gmres(const DevHec &A, const hec_precond_t &M, int m, const double *b, double *x, int R, double rtol,
-                   int maxit, hec_krylov_info_t *info, hipStream_t st)
+                   int maxit, hec_krylov_info_t *info, hipStream_t st, int nsys, const int32_t *sys_ptr)
 {
     const long n = A.n;
     const long nR = n * R;
-    Ctx c(n, R, st);
+    Ctx c(n, R, st, nsys, sys_ptr);
+    const int P = c.P;
     DevMem Vm, Zm, wm, rm;
     Vm.alloc(sizeof(double) * (size_t)(m + 1) * nR);
     Zm.alloc(sizeof(double) * (size_t)m * nR);
@@ -295,28 +338,28 @@ hec_status_t gmres(const DevHec &A, const hec_precond_t &M, int m, const double 
     auto Vi = [&](int i) { return V + (size_t)i * nR; };
     auto Zi = [&](int i) { return Z + (size_t)i * nR; };
 
-    std::vector<double> bnorm(R), relres(R, 0.0);
+    std::vector<double> bnorm(P), relres(P, 0.0);
     {
         const double *a[1] = {b};
         c.dots_to_host(a, a, 1);
-        for (int k = 0; k < R; ++k) bnorm[k] = std::sqrt(c.hbuf[k]);
+        for (int k = 0; k < P; ++k) bnorm[k] = std::sqrt(c.hbuf[k]);
     }
-    std::vector<char> done(R, 0);
+    std::vector<char> done(P, 0);
     bool zero_rhs = false;
-    for (int k = 0; k < R; ++k) {
+    for (int k = 0; k < P; ++k) {
         info[k] = hec_krylov_info_t{HEC_OK, 0, 0, 0, 0.0};
         if (bnorm[k] == 0.0) done[k] = 1, zero_rhs = true;
     }
     if (zero_rhs) {
         // a zero right-hand side has the solution x = 0
-        std::vector<double> keep(R);
-        for (int k = 0; k < R; ++k) keep[k] = bnorm[k] == 0.0 ? 0.0 : 1.0;
+        std::vector<double> keep(P);
+        for (int k = 0; k < P; ++k) keep[k] = bnorm[k] == 0.0 ? 0.0 : 1.0;
         c.lincomb(x, {x}, keep);
     }
-    std::vector<double> H((size_t)(m + 1) * m * R), cs((size_t)m * R), sn((size_t)m * R), g((size_t)(m + 1) * R);
-    auto h_at = [&](int i, int j, int k) -> double & { return H[((size_t)i * m + j) * R + k]; };
-    std::vector<int> kdim(R, 0);
-    std::vector<char> active(R, 0);
+    std::vector<double> H((size_t)(m + 1) * m * P), cs((size_t)m * P), sn((size_t)m * P), g((size_t)(m + 1) * P);
+    auto h_at = [&](int i, int j, int k) -> double & { return H[((size_t)i * m + j) * P + k]; };
+    std::vector<int> kdim(P, 0);
+    std::vector<char> active(P, 0);
     std::vector<const double *> pa(kMaxPairs), pb(kMaxPairs);
     int iters = 0;
     hec_status_t status = HEC_OK;
@@ -328,8 +371,8 @@ hec_status_t gmres(const DevHec &A, const hec_precond_t &M, int m, const double 
             c.dots_to_host(a, a, 1);
         }
         bool any = false;
-        std::vector<double> beta(R);
-        for (int k = 0; k < R; ++k) {
+        std::vector<double> beta(P);
+        for (int k = 0; k < P; ++k) {
             beta[k] = std::sqrt(c.hbuf[k]);
             relres[k] = bnorm[k] > 0 ? beta[k] / bnorm[k] : 0.0;
             if (bnorm[k] == 0.0 || relres[k] <= rtol) done[k] = 1;
@@ -342,11 +385,11 @@ hec_status_t gmres(const DevHec &A, const hec_precond_t &M, int m, const double 
             break;
         }
         // v_0 = r / beta
-        std::vector<double> cf(R);
-        for (int k = 0; k < R; ++k) cf[k] = active[k] ? 1.0 / beta[k] : 0.0;
+        std::vector<double> cf(P);
+        for (int k = 0; k < P; ++k) cf[k] = active[k] ? 1.0 / beta[k] : 0.0;
         c.lincomb(Vi(0), {r}, cf);
         std::fill(g.begin(), g.end(), 0.0);
-        for (int k = 0; k < R; ++k) {
+        for (int k = 0; k < P; ++k) {
             g[k] = active[k] ? beta[k] : 0.0;
             kdim[k] = 0;
         }
@@ -355,39 +398,39 @@ hec_status_t gmres(const DevHec &A, const hec_precond_t &M, int m, const double 
             apply_M(M, Vi(j), Zi(j), R, n, st);
             spmv(A, Zi(j), w, R, st);
             // two passes of classical Gram-Schmidt
-            std::vector<double> hcol((size_t)(j + 1) * R, 0.0);
+            std::vector<double> hcol((size_t)(j + 1) * P, 0.0);
             for (int pass = 0; pass < 2; ++pass) {
                 for (int i = 0; i <= j; ++i) {
                     pa[i] = Vi(i);
                     pb[i] = w;
                 }
                 c.dots_to_host(pa.data(), pb.data(), j + 1);
-                std::vector<double> hh(c.hbuf, c.hbuf + (size_t)(j + 1) * R);
+                std::vector<double> hh(c.hbuf, c.hbuf + (size_t)(j + 1) * P);
                 for (size_t q = 0; q < hh.size(); ++q) hcol[q] += hh[q];
                 c.upload_coef(hh);
                 hipLaunchKernelGGL(k_gs_update, dim3(blocks_for(nR)), dim3(256), 0, st, w, V, nR,
-                                   c.coef.as<double>(), j + 1, nR, R);
+                                   c.coef.as<double>(), j + 1, nR, R, P, c.seg);
                 hip_check(hipGetLastError(), "k_gs_update");
             }
             {
                 const double *a[1] = {w};
                 c.dots_to_host(a, a, 1);
             }
-            std::vector<double> hn(R);
-            for (int k = 0; k < R; ++k) hn[k] = std::sqrt(std::max(0.0, c.hbuf[k]));
-            for (int k = 0; k < R; ++k) cf[k] = (active[k] && hn[k] > 0.0) ? 1.0 / hn[k] : 0.0;
+            std::vector<double> hn(P);
+            for (int k = 0; k < P; ++k) hn[k] = std::sqrt(std::max(0.0, c.hbuf[k]));
+            for (int k = 0; k < P; ++k) cf[k] = (active[k] && hn[k] > 0.0) ? 1.0 / hn[k] : 0.0;
             c.lincomb(Vi(j + 1), {w}, cf);
             ++iters;
             bool still = false;
-            for (int k = 0; k < R; ++k) {
+            for (int k = 0; k < P; ++k) {
                 if (!active[k]) continue;
                 info[k].iters += 1;
                 info[k].precond_applies += 1;
-                for (int i = 0; i <= j; ++i) h_at(i, j, k) = hcol[(size_t)i * R + k];
+                for (int i = 0; i <= j; ++i) h_at(i, j, k) = hcol[(size_t)i * P + k];
                 h_at(j + 1, j, k) = hn[k];
                 for (int i = 0; i < j; ++i) {
-                    const double t = cs[i * R + k] * h_at(i, j, k) + sn[i * R + k] * h_at(i + 1, j, k);
-                    h_at(i + 1, j, k) = -sn[i * R + k] * h_at(i, j, k) + cs[i * R + k] * h_at(i + 1, j, k);
+                    const double t = cs[i * P + k] * h_at(i, j, k) + sn[i * P + k] * h_at(i + 1, j, k);
+                    h_at(i + 1, j, k) = -sn[i * P + k] * h_at(i, j, k) + cs[i * P + k] * h_at(i + 1, j, k);
                     h_at(i, j, k) = t;
                 }
                 const double den = std::hypot(h_at(j, j, k), h_at(j + 1, j, k));
@@ -398,14 +441,14 @@ hec_status_t gmres(const DevHec &A, const hec_precond_t &M, int m, const double 
                     done[k] = 1;
                     continue;
                 }
-                cs[j * R + k] = h_at(j, j, k) / den;
-                sn[j * R + k] = h_at(j + 1, j, k) / den;
+                cs[j * P + k] = h_at(j, j, k) / den;
+                sn[j * P + k] = h_at(j + 1, j, k) / den;
                 h_at(j, j, k) = den;
                 h_at(j + 1, j, k) = 0.0;
-                g[(j + 1) * R + k] = -sn[j * R + k] * g[j * R + k];
-                g[j * R + k] = cs[j * R + k] * g[j * R + k];
+                g[(j + 1) * P + k] = -sn[j * P + k] * g[j * P + k];
+                g[j * P + k] = cs[j * P + k] * g[j * P + k];
                 kdim[k] = j + 1;
-                if (std::fabs(g[(j + 1) * R + k]) / bnorm[k] <= rtol || hn[k] == 0.0 || iters >= maxit)
+                if (std::fabs(g[(j + 1) * P + k]) / bnorm[k] <= rtol || hn[k] == 0.0 || iters >= maxit)
                     active[k] = 0;
                 still = still || active[k];
             }
@@ -417,19 +460,19 @@ hec_status_t gmres(const DevHec &A, const hec_precond_t &M, int m, const double 
         // y = H^{-1} g per RHS, x += Z y
         const int nv = *std::max_element(kdim.begin(), kdim.end());
         if (nv > 0) {
-            std::vector<double> y((size_t)nv * R, 0.0);
-            for (int k = 0; k < R; ++k) {
+            std::vector<double> y((size_t)nv * P, 0.0);
+            for (int k = 0; k < P; ++k) {
                 const int kk = kdim[k];
                 for (int i = kk - 1; i >= 0; --i) {
-                    double s = g[i * R + k];
-                    for (int l = i + 1; l < kk; ++l) s -= h_at(i, l, k) * y[l * R + k];
-                    y[i * R + k] = s / h_at(i, i, k);
+                    double s = g[i * P + k];
+                    for (int l = i + 1; l < kk; ++l) s -= h_at(i, l, k) * y[l * P + k];
+                    y[i * P + k] = s / h_at(i, i, k);
                 }
                 if (kk > 0) info[k].restarts += 1;
             }
             c.upload_coef(y);
             hipLaunchKernelGGL(k_basis_update, dim3(blocks_for(nR)), dim3(256), 0, st, x, Z, nR, c.coef.as<double>(),
-                               nv, nR, R);
+                               nv, nR, R, P, c.seg);
             hip_check(hipGetLastError(), "k_basis_update");
         }
         if (status == HEC_ERR_BREAKDOWN) {
@@ -442,7 +485,7 @@ hec_status_t gmres(const DevHec &A, const hec_precond_t &M, int m, const double 
         c.dots_to_host(a, a, 1);
     }
     hec_status_t out = HEC_OK;
-    for (int k = 0; k < R; ++k) {
+    for (int k = 0; k < P; ++k) {
         info[k].relres = bnorm[k] > 0 ? std::sqrt(c.hbuf[k]) / bnorm[k] : 0.0;
         if (info[k].relres > rtol) {
             if (info[k].status == HEC_OK) info[k].status = HEC_ERR_NOT_CONVERGED;
@@ -456,26 +499,27 @@ hec_status_t gmres(const DevHec &A, const hec_precond_t &M, int m, const double 
 // r0; when rho or (r0, v) vanishes the recurrence restarts from the current
 // true residual.  Convergence is tested on the true residual.
 hec_status_t bicgstab(const DevHec &A, const hec_precond_t &M, const double *b, double *x, int R, double rtol,
-                      int maxit, hec_krylov_info_t *info, hipStream_t st)
+                      int maxit, hec_krylov_info_t *info, hipStream_t st, int nsys, const int32_t *sys_ptr)
 {
     const long n = A.n, nR = n * R;
-    Ctx c(n, R, st);
+    Ctx c(n, R, st, nsys, sys_ptr);
+    const int P = c.P;
     DevMem rm, rhm, pm, vm, phm, sm, shm, tm;
     for (DevMem *d : {&rm, &rhm, &pm, &vm, &phm, &sm, &shm, &tm}) d->alloc(sizeof(double) * (size_t)std::max<long>(1, nR));
     double *r = rm.as<double>(), *rh = rhm.as<double>(), *p = pm.as<double>(), *v = vm.as<double>(),
            *ph = phm.as<double>(), *s = sm.as<double>(), *sh = shm.as<double>(), *t = tm.as<double>();
-    std::vector<double> bnorm(R);
+    std::vector<double> bnorm(P);
     {
         const double *a[1] = {b};
         c.dots_to_host(a, a, 1);
-        for (int k = 0; k < R; ++k) bnorm[k] = std::sqrt(c.hbuf[k]);
+        for (int k = 0; k < P; ++k) bnorm[k] = std::sqrt(c.hbuf[k]);
     }
-    for (int k = 0; k < R; ++k) info[k] = hec_krylov_info_t{HEC_OK, 0, 0, 0, 0.0};
-    std::vector<char> done(R, 0);
+    for (int k = 0; k < P; ++k) info[k] = hec_krylov_info_t{HEC_OK, 0, 0, 0, 0.0};
+    std::vector<char> done(P, 0);
     {
-        std::vector<double> keep(R);
+        std::vector<double> keep(P);
         bool zero_rhs = false;
-        for (int k = 0; k < R; ++k) {
+        for (int k = 0; k < P; ++k) {
             keep[k] = bnorm[k] == 0.0 ? 0.0 : 1.0;
             zero_rhs = zero_rhs || bnorm[k] == 0.0;
         }
@@ -483,7 +527,7 @@ hec_status_t bicgstab(const DevHec &A, const hec_precond_t &M, const double *b, 
     }
     int iters = 0, breakdowns = 0;
     hec_status_t status = HEC_OK;
-    std::vector<double> rho(R), rho_old(R), alpha(R), omega(R), cf;
+    std::vector<double> rho(P), rho_old(P), alpha(P), omega(P), cf;
     for (;;) {
         residual(A, b, x, r, R, st);
         {
@@ -491,7 +535,7 @@ hec_status_t bicgstab(const DevHec &A, const hec_precond_t &M, const double *b, 
             c.dots_to_host(a, a, 1);
         }
         bool any = false;
-        for (int k = 0; k < R; ++k) {
+        for (int k = 0; k < P; ++k) {
             const double rr = bnorm[k] > 0 ? std::sqrt(c.hbuf[k]) / bnorm[k] : 0.0;
             if (bnorm[k] == 0.0 || rr <= rtol) done[k] = 1;
             any = any || !done[k];
@@ -511,15 +555,15 @@ hec_status_t bicgstab(const DevHec &A, const hec_precond_t &M, const double *b, 
         std::fill(rho_old.begin(), rho_old.end(), 1.0);
         std::fill(alpha.begin(), alpha.end(), 1.0);
         std::fill(omega.begin(), omega.end(), 1.0);
-        std::vector<char> act(R);
-        for (int k = 0; k < R; ++k) act[k] = !done[k];
+        std::vector<char> act(P);
+        for (int k = 0; k < P; ++k) act[k] = !done[k];
         bool restart = false;
         while (iters < maxit && !restart) {
             {
                 const double *a[1] = {rh}, *bb[1] = {r};
                 c.dots_to_host(a, bb, 1);
             }
-            for (int k = 0; k < R; ++k) {
+            for (int k = 0; k < P; ++k) {
                 rho[k] = c.hbuf[k];
                 if (act[k] && rho[k] == 0.0) restart = true;
             }
@@ -528,13 +572,13 @@ hec_status_t bicgstab(const DevHec &A, const hec_precond_t &M, const double *b, 
                 break;
             }
             // p = r + beta (p - omega v)
-            cf.assign(3 * (size_t)R, 0.0);
-            for (int k = 0; k < R; ++k) {
+            cf.assign(3 * (size_t)P, 0.0);
+            for (int k = 0; k < P; ++k) {
                 if (!act[k]) continue;
                 const double beta = (rho[k] / rho_old[k]) * (alpha[k] / omega[k]);
                 cf[k] = 1.0;
-                cf[R + k] = beta;
-                cf[2 * R + k] = -beta * omega[k];
+                cf[P + k] = beta;
+                cf[2 * P + k] = -beta * omega[k];
             }
             c.lincomb(p, {r, p, v}, cf);
             apply_M(M, p, ph, R, n, st);
@@ -543,7 +587,7 @@ hec_status_t bicgstab(const DevHec &A, const hec_precond_t &M, const double *b, 
                 const double *a[1] = {rh}, *bb[1] = {v};
                 c.dots_to_host(a, bb, 1);
             }
-            for (int k = 0; k < R; ++k) {
+            for (int k = 0; k < P; ++k) {
                 if (!act[k]) {
                     alpha[k] = 0.0;
                     continue;
@@ -556,14 +600,14 @@ hec_status_t bicgstab(const DevHec &A, const hec_precond_t &M, const double *b, 
                 break;
             }
             // s = r - alpha v
-            cf.assign(2 * (size_t)R, 0.0);
-            for (int k = 0; k < R; ++k) {
+            cf.assign(2 * (size_t)P, 0.0);
+            for (int k = 0; k < P; ++k) {
                 cf[k] = 1.0;
-                cf[R + k] = -alpha[k];
+                cf[P + k] = -alpha[k];
             }
             c.lincomb(s, {r, v}, cf);
             ++iters;
-            for (int k = 0; k < R; ++k)
+            for (int k = 0; k < P; ++k)
                 if (act[k]) {
                     info[k].iters += 1;
                     info[k].precond_applies += 1;
@@ -573,8 +617,8 @@ hec_status_t bicgstab(const DevHec &A, const hec_precond_t &M, const double *b, 
                 c.dots_to_host(a, a, 1);
             }
             bool early = false;
-            std::vector<char> sdone(R, 0);
-            for (int k = 0; k < R; ++k)
+            std::vector<char> sdone(P, 0);
+            for (int k = 0; k < P; ++k)
                 if (act[k] && std::sqrt(c.hbuf[k]) / bnorm[k] <= rtol) sdone[k] = 1, early = true;
             apply_M(M, s, sh, R, n, st);
             spmv(A, sh, t, R, st);
@@ -582,27 +626,27 @@ hec_status_t bicgstab(const DevHec &A, const hec_precond_t &M, const double *b, 
                 const double *a[2] = {t, t}, *bb[2] = {s, t};
                 c.dots_to_host(a, bb, 2);
             }
-            for (int k = 0; k < R; ++k) {
+            for (int k = 0; k < P; ++k) {
                 if (!act[k] || sdone[k]) {
                     omega[k] = 0.0;
                     continue;
                 }
-                const double ts = c.hbuf[k], tt = c.hbuf[R + k];
+                const double ts = c.hbuf[k], tt = c.hbuf[P + k];
                 omega[k] = tt != 0.0 ? ts / tt : 0.0;
                 info[k].precond_applies += 1;
             }
             // x += alpha ph + omega sh ; r = s - omega t
-            cf.assign(3 * (size_t)R, 0.0);
-            for (int k = 0; k < R; ++k) {
+            cf.assign(3 * (size_t)P, 0.0);
+            for (int k = 0; k < P; ++k) {
                 cf[k] = 1.0;
-                cf[R + k] = act[k] ? alpha[k] : 0.0;
-                cf[2 * R + k] = act[k] ? omega[k] : 0.0;
+                cf[P + k] = act[k] ? alpha[k] : 0.0;
+                cf[2 * P + k] = act[k] ? omega[k] : 0.0;
             }
             c.lincomb(x, {x, ph, sh}, cf);
-            cf.assign(2 * (size_t)R, 0.0);
-            for (int k = 0; k < R; ++k) {
+            cf.assign(2 * (size_t)P, 0.0);
+            for (int k = 0; k < P; ++k) {
                 cf[k] = 1.0;
-                cf[R + k] = -omega[k];
+                cf[P + k] = -omega[k];
             }
             c.lincomb(r, {s, t}, cf);
             {
@@ -610,7 +654,7 @@ hec_status_t bicgstab(const DevHec &A, const hec_precond_t &M, const double *b, 
                 c.dots_to_host(a, a, 1);
             }
             bool any_act = false;
-            for (int k = 0; k < R; ++k) {
+            for (int k = 0; k < P; ++k) {
                 if (!act[k]) continue;
                 const double rr = std::sqrt(c.hbuf[k]) / bnorm[k];
                 if (sdone[k] || rr <= rtol || omega[k] == 0.0) {
@@ -629,7 +673,7 @@ hec_status_t bicgstab(const DevHec &A, const hec_precond_t &M, const double *b, 
         c.dots_to_host(a, a, 1);
     }
     hec_status_t out = HEC_OK;
-    for (int k = 0; k < R; ++k) {
+    for (int k = 0; k < P; ++k) {
         info[k].relres = bnorm[k] > 0 ? std::sqrt(c.hbuf[k]) / bnorm[k] : 0.0;
         if (info[k].relres > rtol) {
             info[k].status = status == HEC_ERR_BREAKDOWN ? HEC_ERR_BREAKDOWN : HEC_ERR_NOT_CONVERGED;
@@ -740,9 +784,47 @@ hec_status_t krylov_solve(hec_matrix_t A, hec_precond_t M, hec_krylov_t method, 
             precond_check(M, A->d.n);
             if (method == HEC_GMRES || method == HEC_FGMRES) {
                 if (m < 1 || m > kMaxPairs - 1) fail(HEC_ERR_INVALID_ARG, "GMRES restart length must be 1..31");
-                return gmres(A->d, M, m, b, x, nrhs, rtol, maxit, info, st);
+                return gmres(A->d, M, m, b, x, nrhs, rtol, maxit, info, st, 1, nullptr);
             }
-            if (method == HEC_BICGSTAB) return bicgstab(A->d, M, b, x, nrhs, rtol, maxit, info, st);
+            if (method == HEC_BICGSTAB) return bicgstab(A->d, M, b, x, nrhs, rtol, maxit, info, st, 1, nullptr);
+            fail(HEC_ERR_INVALID_ARG, "unknown Krylov method");
+    });
+}
+
+hec_status_t krylov_solve_batch(hec_matrix_t A, hec_precond_t M, hec_krylov_t method, int32_t m, int32_t nsys,
+                                const int32_t *sys_ptr, const double *b, double *x, int32_t nrhs, double rtol,
+                                int32_t maxit, hec_krylov_info_t *info, hipStream_t st)
+{
+    return guard_status([&]() -> hec_status_t {
+            if (!A || !info || !sys_ptr || nsys < 1 || nrhs < 1 || maxit < 0 || !(rtol > 0.0))
+                fail(HEC_ERR_INVALID_ARG, "bad arguments");
+            if (nrhs > 256) fail(HEC_ERR_INVALID_ARG, "at most 256 right-hand sides per solve");
+            if ((int64_t)nsys * nrhs > 16384) fail(HEC_ERR_INVALID_ARG, "at most 16384 (system, rhs) problems");
+            const int32_t n = A->d.n;
+            if (sys_ptr[0] != 0 || sys_ptr[nsys] != n) fail(HEC_ERR_INVALID_ARG, "sys_ptr must run from 0 to n");
+            for (int32_t s = 0; s < nsys; ++s)
+                if (sys_ptr[s + 1] < sys_ptr[s]) fail(HEC_ERR_INVALID_ARG, "sys_ptr not monotone");
+            if (n > 0 && (!b || !x)) fail(HEC_ERR_INVALID_ARG, "vector pointer is NULL");
+            // the systems must not couple through A (the preconditioner's own
+            // setup checks its blocks)
+            for (int32_t s = 0; s < nsys; ++s)
+                for (int32_t i = sys_ptr[s]; i < sys_ptr[s + 1]; ++i) {
+                    const HecHost &h = A->d.host;
+                    for (int32_t e = 0; e < h.w; ++e) {
+                        const int32_t c = h.ell_col[(size_t)e * h.ld + i];
+                        if (c < n && (c < sys_ptr[s] || c >= sys_ptr[s + 1]))
+                            fail(HEC_ERR_INVALID_ARG, "A couples two systems (row " + std::to_string(i) + ")");
+                    }
+                    for (int32_t q = h.csr_ptr[i]; q < h.csr_ptr[i + 1]; ++q)
+                        if (h.csr_col[q] < sys_ptr[s] || h.csr_col[q] >= sys_ptr[s + 1])
+                            fail(HEC_ERR_INVALID_ARG, "A couples two systems (row " + std::to_string(i) + ")");
+                }
+            precond_check(M, n);
+            if (method == HEC_GMRES || method == HEC_FGMRES) {
+                if (m < 1 || m > kMaxPairs - 1) fail(HEC_ERR_INVALID_ARG, "GMRES restart length must be 1..31");
+                return gmres(A->d, M, m, b, x, nrhs, rtol, maxit, info, st, nsys, sys_ptr);
+            }
+            if (method == HEC_BICGSTAB) return bicgstab(A->d, M, b, x, nrhs, rtol, maxit, info, st, nsys, sys_ptr);
             fail(HEC_ERR_INVALID_ARG, "unknown Krylov method");
     });
 }

@@ -222,3 +222,53 @@ def test_graph_replay_matches_eager(kind):
         (H.ras_apply if kind == "ras" else H.ilu_apply)(M, r, ze)
         torch.cuda.synchronize()
         assert torch.equal(got, ze)
+
+
+@pytest.mark.parametrize("method", ["fgmres", "bicgstab"])
+@pytest.mark.parametrize("fdt", ["f64", "f32"])
+def test_batch_krylov_solves_each_system_alone(method, fdt):
+    # every (system, rhs) pair is its own Krylov problem: the result and the
+    # iteration count match the oracle solving that system by itself
+    mats = [synth.diffusion2d(30, 20, 1.0, seed=1), synth.diffusion3d(9, 8, 7, 1.0, seed=2),
+            synth.poisson2d(5, 3), synth.diffusion3d(13, 13, 13, 1.0, seed=4), synth.poisson2d(41, 1)]
+    A, sys_ptr = _block_diag(mats)
+    R = 2
+    f = H.batch_setup(A, sys_ptr, "iluk", k=1, factor_dtype=fdt, tune=H.tune_default(max_nrhs=R))
+    M = H.hec_from_csr(A)
+    b = synth.rhs(A.n, R, 11)
+    b[int(sys_ptr[2]):int(sys_ptr[3]), 1] = 0.0  # a zero right-hand side: x = 0 for that pair
+    xt = torch.zeros(A.n, R, dtype=torch.float64, device="cuda")
+    st, info = H.krylov_solve_batch(M, f, sys_ptr, dev(b), xt, method=method, m=30, rtol=1e-10)
+    assert st == 0 and len(info) == len(mats) * R
+    x = xt.cpu().numpy()
+    for s, Ms in enumerate(mats):
+        seg = slice(int(sys_ptr[s]), int(sys_ptr[s + 1]))
+        L, U = oracle.iluk(Ms, 1)
+        if fdt == "f32":
+            L32, U32 = oracle.to_f32(L), oracle.to_f32(U)
+            prec = lambda v: oracle.ilu_apply_f32(L32, U32, v)  # noqa: E731
+        else:
+            prec = lambda v: oracle.ilu_apply(L, U, v)  # noqa: E731
+        for k in range(R):
+            q = info[s * R + k]
+            bs = b[seg, k]
+            if not np.any(bs):
+                assert np.all(x[seg, k] == 0.0) and q.iters == 0
+                continue
+            true = np.linalg.norm(bs - oracle.spmv(Ms, x[seg, k])) / np.linalg.norm(bs)
+            assert true <= 1e-10 and abs(true - q.relres) <= 1e-12
+            solver = oracle.fgmres if method == "fgmres" else oracle.bicgstab
+            kw = {"m": 30} if method == "fgmres" else {}
+            xo, io = solver(Ms, bs, prec, rtol=1e-10, **kw)
+            assert relerr(x[seg, k], xo) <= 1e-7
+            assert abs(q.iters - io.iters) <= (2 if method == "fgmres" else 5)
+
+
+def test_batch_krylov_rejects_coupling():
+    A = synth.poisson2d(6)
+    M = H.hec_from_csr(A)
+    b = dev(synth.rhs(A.n, 1, 1))
+    x = torch.zeros_like(b)
+    with pytest.raises(H.HecError) as e:
+        H.krylov_solve_batch(M, None, np.array([0, 18, 36], np.int32), b, x)
+    assert e.value.name == "INVALID_ARG"
