@@ -792,8 +792,6 @@ template <typename T> __device__ __forceinline__ void lds_put(T *p, T v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-constexpr int kDfDepth = 3;  // steps per compute wave with loads in flight
-
 template <typename T, int W> struct DfRegs {
     int rb, re;
     int c[W];
@@ -910,10 +908,12 @@ __global__ void __launch_bounds__(W > 8 ? 512 : 768) k_dataflow(TriArgs a)
         bool aborted = false;
         // solve step j from registers u; `nj` is the step whose bounds are
         // read (returned in nb, ne) while this one waits for LDS
-        auto process = [&](const DfRegs<T, W> &u, int j, int nj, int &nb, int &ne) {
+        // Solve step j from registers u.  The matrix loads of step j+3 (bounds
+        // fb, fe, read one step earlier) go into `fill` right after this
+        // step's input reads are issued, and the bounds of step j+4 are read
+        // behind them, so neither waits on the other.
+        auto process = [&](const DfRegs<T, W> &u, DfRegs<T, W> &fill, int j, int &fb, int &fe, int nq) {
             if (j < ntr && lane == 0) ltr[2 * j] = __builtin_amdgcn_s_memrealtime();
-            nb = stl[2 * nj];
-            ne = stl[2 * nj + 1];
             const int items = (u.re - u.rb) * R;
             const int it = min(lane, items - 1);
             const int q = R1 ? it : it / R, k = it - q * R;
@@ -927,6 +927,9 @@ __global__ void __launch_bounds__(W > 8 ? 512 : 768) k_dataflow(TriArgs a)
                 off[e] = u.c[e] * R + k;
                 dep[e] = lds_get(xl + off[e]);
             }
+            load(fill, fb, fe);
+            fb = stl[2 * nq];
+            fe = stl[2 * nq + 1];
             bool pend = false;
 #pragma unroll
             for (int e = 0; e < W; ++e) pend |= is_sentinel(dep[e]);
@@ -982,56 +985,83 @@ __global__ void __launch_bounds__(W > 8 ? 512 : 768) k_dataflow(TriArgs a)
             lds_put(xl + r * R + k, sv);
             if (j < ntr && lane == 0) ltr[2 * j + 1] = __builtin_amdgcn_s_memrealtime();
         };
-        // The wave walks its own steps [j, jend) in order.  kDfDepth steps
-        // have their loads in flight; loads past the last step repeat it, so
-        // every path issues the same loads and the compiler's waits stay
-        // exact.  The loop is written out per register set (no register
-        // moves, no merged paths with skipped loads) and its exit test is
-        // wave-uniform.
+        // The wave walks its own steps [j, jend) in order.  Four register
+        // sets rotate: while step j is solved from one, steps j+1 and j+2 have
+        // their loads in flight and step j+3's loads are issued into the
+        // fourth.  Loads past the last step repeat it, so every path issues
+        // the same loads; the loop runs whole rotations with a single exit at
+        // the bottom and no register moves, so the compiler's load waits are
+        // exact.
         int j = a.wave_ptr[g * nwc + wv] - s0;
         const int jend = a.wave_ptr[g * nwc + wv + 1] - s0;
         const int last = jend - 1;
-        DfRegs<T, W> A, B, C;
+        DfRegs<T, W> A, B, C, D;
         auto first = [&](DfRegs<T, W> &u, int q) {
             q = min(q, last);
             load(u, stl[2 * q], stl[2 * q + 1]);
         };
-        auto run = [&](DfRegs<T, W> &u) {
-            int nb, ne;
-            process(u, j, min(j + kDfDepth, last), nb, ne);
-            load(u, nb, ne);
+        int fb = 0, fe = 0;
+        auto run = [&](const DfRegs<T, W> &u, DfRegs<T, W> &fill) {
+            process(u, fill, j, fb, fe, min(j + 4, last));
             j += 1;
         };
         if (j < jend) {
             first(A, j);
             first(B, j + 1);
             first(C, j + 2);
-            // whole triples in a loop with one exit at the bottom, so the
-            // loop is entered and repeated with the same loads in flight
-            const int triples = (jend - j) / 3, rest = (jend - j) - 3 * triples;
-            for (int t3 = 0; t3 < triples; ++t3) {
-                run(A);
-                run(B);
-                run(C);
+            fb = stl[2 * min(j + 3, last)];
+            fe = stl[2 * min(j + 3, last) + 1];
+            const int quads = (jend - j) / 4, rest = (jend - j) - 4 * quads;
+            for (int q4 = 0; q4 < quads; ++q4) {
+                run(A, D);
+                run(B, A);
+                run(C, B);
+                run(D, C);
                 if (__ballot(aborted) != 0) break;
             }
-            if (rest > 0 && __ballot(aborted) == 0) run(A);
-            if (rest > 1 && __ballot(aborted) == 0) run(B);
+            if (rest > 0 && __ballot(aborted) == 0) run(A, D);
+            if (rest > 1 && __ballot(aborted) == 0) run(B, A);
+            if (rest > 2 && __ballot(aborted) == 0) run(C, B);
         }
     } else if (wv == nwc) {
-        // import wave
+        // import wave: lane l owns items l, l+64, l+128, ... (level order).
+        // Each poll round reads the lane's next kLook items at once and
+        // copies every one that has arrived (copying a value again is
+        // harmless: a delivered slot never changes during the launch); the
+        // lane then moves past the delivered prefix.  One round trip thus
+        // delivers several levels' worth of a lane's items.
+        constexpr int kLook = 4;
         const int items = nimp * R;
         const int xoff = 2 * win * R;
         int it = lane;
         unsigned idle = 0;
         while (__ballot(it < items) != 0) {
             if (it < items) {
-                const int q = it / R, k = it - q * R;
-                const T v = __hip_atomic_load(mrd + (size_t)isl[q] * a.mbox_stride + k, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
-                if (!is_sentinel(v)) {
-                    lds_put(xl + xoff + it, v);
-                    it += 64;
+                T v[kLook];
+#pragma unroll
+                for (int u = 0; u < kLook; ++u) {
+                    const int i2 = it + 64 * u;
+                    v[u] = sentinel<T>();
+                    if (i2 < items) {
+                        const int q = i2 / R, k = i2 - q * R;
+                        v[u] = __hip_atomic_load(mrd + (size_t)isl[q] * a.mbox_stride + k, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
+                int adv = 0;
+                bool lead = true;
+#pragma unroll
+                for (int u = 0; u < kLook; ++u) {
+                    const int i2 = it + 64 * u;
+                    if (i2 < items && !is_sentinel(v[u])) {
+                        lds_put(xl + xoff + i2, v[u]);
+                        adv += lead ? 1 : 0;
+                    } else {
+                        lead = false;
+                    }
+                }
+                if (adv > 0) {
+                    it += 64 * adv;
                     idle = 0;
                 } else if (++idle > kSpinLimit) {
                     lds_put(&s_abort, 2);
