@@ -183,7 +183,8 @@ def run_config(cfg, args):
                         "nnz_offdiag_U": stu["nnz_offdiag"], "setup_s": round(setup, 3), "fgmres": kr,
                         "dataflow": stl["dataflow"], "ell_width_L": stl["ell_width"],
                         "nnz_tail_L": stl["nnz_tail"], "x": x}
-        d = (res["f32"]["x"] - res["f64"]["x"]).norm().item() / res["f64"]["x"].norm().item()
+        d = None if args.no_krylov else \
+            (res["f32"]["x"] - res["f64"]["x"]).norm().item() / res["f64"]["x"].norm().item()
         for k in res:
             res[k].pop("x")
         out.update({"value": res["f32"]["apply_GBps"], "dtype": "f32 factors, f64 refinement",

@@ -988,13 +988,16 @@ __global__ void __launch_bounds__(W > 8 ? 512 : 768) k_dataflow(TriArgs a)
         // The wave walks its own steps [j, jend) in order.  Four register
         // sets rotate: while step j is solved from one, steps j+1 and j+2 have
         // their loads in flight and step j+3's loads are issued into the
-        // fourth.  Loads past the last step repeat it, so every path issues
+        // fourth (three sets and two steps ahead for rows wider than 8).  Loads past the last step repeat it, so every path issues
         // the same loads; the loop runs whole rotations with a single exit at
         // the bottom and no register moves, so the compiler's load waits are
         // exact.
         int j = a.wave_ptr[g * nwc + wv] - s0;
         const int jend = a.wave_ptr[g * nwc + wv + 1] - s0;
         const int last = jend - 1;
+        // Rows wider than 8 slots keep one step fewer in flight (three sets):
+        // the vector-memory counter holds at most 63 outstanding loads.
+        constexpr int kAhead = W > 8 ? 2 : 3;
         DfRegs<T, W> A, B, C, D;
         auto first = [&](DfRegs<T, W> &u, int q) {
             q = min(q, last);
@@ -1002,38 +1005,50 @@ __global__ void __launch_bounds__(W > 8 ? 512 : 768) k_dataflow(TriArgs a)
         };
         int fb = 0, fe = 0;
         auto run = [&](const DfRegs<T, W> &u, DfRegs<T, W> &fill) {
-            process(u, fill, j, fb, fe, min(j + 4, last));
+            process(u, fill, j, fb, fe, min(j + kAhead + 1, last));
             j += 1;
         };
         if (j < jend) {
             first(A, j);
             first(B, j + 1);
-            first(C, j + 2);
-            fb = stl[2 * min(j + 3, last)];
-            fe = stl[2 * min(j + 3, last) + 1];
-            const int quads = (jend - j) / 4, rest = (jend - j) - 4 * quads;
-            for (int q4 = 0; q4 < quads; ++q4) {
-                run(A, D);
-                run(B, A);
-                run(C, B);
-                run(D, C);
-                if (__ballot(aborted) != 0) break;
+            if (kAhead == 3) first(C, j + 2);
+            fb = stl[2 * min(j + kAhead, last)];
+            fe = stl[2 * min(j + kAhead, last) + 1];
+            if (kAhead == 3) {
+                const int quads = (jend - j) / 4, rest = (jend - j) - 4 * quads;
+                for (int q4 = 0; q4 < quads; ++q4) {
+                    run(A, D);
+                    run(B, A);
+                    run(C, B);
+                    run(D, C);
+                    if (__ballot(aborted) != 0) break;
+                }
+                if (rest > 0 && __ballot(aborted) == 0) run(A, D);
+                if (rest > 1 && __ballot(aborted) == 0) run(B, A);
+                if (rest > 2 && __ballot(aborted) == 0) run(C, B);
+            } else {
+                const int triples = (jend - j) / 3, rest = (jend - j) - 3 * triples;
+                for (int q3 = 0; q3 < triples; ++q3) {
+                    run(A, C);
+                    run(B, A);
+                    run(C, B);
+                    if (__ballot(aborted) != 0) break;
+                }
+                if (rest > 0 && __ballot(aborted) == 0) run(A, C);
+                if (rest > 1 && __ballot(aborted) == 0) run(B, A);
             }
-            if (rest > 0 && __ballot(aborted) == 0) run(A, D);
-            if (rest > 1 && __ballot(aborted) == 0) run(B, A);
-            if (rest > 2 && __ballot(aborted) == 0) run(C, B);
         }
     } else if (wv == nwc) {
         // import wave: lane l owns items l, l+64, l+128, ... (level order).
-        // Each poll round reads the lane's next kLook items at once and
-        // copies every one that has arrived (copying a value again is
-        // harmless: a delivered slot never changes during the launch); the
-        // lane then moves past the delivered prefix.  One round trip thus
-        // delivers several levels' worth of a lane's items.
-        constexpr int kLook = 4;
+        // Each poll round reads those of the lane's next kLook items that have
+        // not arrived yet, copies every new arrival into LDS, and moves the
+        // lane past the delivered prefix.  One round trip thus delivers
+        // several levels' worth of a lane's items without re-reading any.
+        constexpr int kLook = 2;
         const int items = nimp * R;
         const int xoff = 2 * win * R;
         int it = lane;
+        unsigned got = 0;  // bit u: item it + 64 u already delivered
         unsigned idle = 0;
         while (__ballot(it < items) != 0) {
             if (it < items) {
@@ -1042,26 +1057,26 @@ __global__ void __launch_bounds__(W > 8 ? 512 : 768) k_dataflow(TriArgs a)
                 for (int u = 0; u < kLook; ++u) {
                     const int i2 = it + 64 * u;
                     v[u] = sentinel<T>();
-                    if (i2 < items) {
+                    if (i2 < items && !((got >> u) & 1u)) {
                         const int q = i2 / R, k = i2 - q * R;
                         v[u] = __hip_atomic_load(mrd + (size_t)isl[q] * a.mbox_stride + k, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT);
                     }
                 }
-                int adv = 0;
-                bool lead = true;
+                bool fresh = false;
 #pragma unroll
                 for (int u = 0; u < kLook; ++u) {
-                    const int i2 = it + 64 * u;
-                    if (i2 < items && !is_sentinel(v[u])) {
-                        lds_put(xl + xoff + i2, v[u]);
-                        adv += lead ? 1 : 0;
-                    } else {
-                        lead = false;
+                    if (!is_sentinel(v[u])) {
+                        lds_put(xl + xoff + it + 64 * u, v[u]);
+                        got |= 1u << u;
+                        fresh = true;
                     }
                 }
-                if (adv > 0) {
-                    it += 64 * adv;
+                while (got & 1u) {
+                    got >>= 1;
+                    it += 64;
+                }
+                if (fresh) {
                     idle = 0;
                 } else if (++idle > kSpinLimit) {
                     lds_put(&s_abort, 2);
