@@ -857,6 +857,16 @@ void build_exec(TriHost &t, const Csr &a, const Tune &tune, const DeviceShape &d
         if (!t.unit) ex.dinv[x] = 1.0 / h.csr_val[pe];
     }
     t.nnz_tail = (int64_t)ex.tail_col.size();
+    // Fold the reciprocal diagonal into the row: x = d b - sum (d a_j) x_j, so
+    // the kernels scale b once when they read it and the dependency chain of
+    // a row ends with its last multiply-add (no trailing multiply).
+    if (!t.unit) {
+        for (int32_t x = 0; x < n; ++x) {
+            for (int32_t e = 0; e < w; ++e) ex.ell_val[(size_t)e * ld + x] *= ex.dinv[x];
+            if (has_tail)
+                for (int32_t p = ex.tail_ptr[x]; p < ex.tail_ptr[x + 1]; ++p) ex.tail_val[p] *= ex.dinv[x];
+        }
+    }
 
     // 3. schedule
     ex.sched = Schedule();

@@ -44,6 +44,11 @@ template <> __device__ __forceinline__ float sentinel<float>() { return __uint_a
 __device__ __forceinline__ bool is_sentinel(double v) { return __double_as_longlong(v) == (long long)kSentinel64; }
 __device__ __forceinline__ bool is_sentinel(float v) { return __float_as_uint(v) == kSentinel32; }
 
+// Right-hand side times the reciprocal diagonal, rounded on its own (never
+// contracted into the first multiply-add), identically in every kernel.
+__device__ __forceinline__ double scale_rhs(double b, double d) { return __dmul_rn(b, d); }
+__device__ __forceinline__ float scale_rhs(float b, float d) { return __fmul_rn(b, d); }
+
 // Per-launch state of the persistent kernel shared by the row routine.
 template <typename T> struct Ctx {
     T *xl;          // LDS window (device rows lo..hi-1), holds b then x
@@ -96,8 +101,9 @@ __device__ __forceinline__ T dep_value(const TriArgs &a, const Ctx<T> &cx, int c
 template <typename T, typename TIn, bool LDS>
 __device__ __forceinline__ T rhs_value(const TriArgs &a, const Ctx<T> &cx, int x, int k)
 {
-    if (LDS) return cx.xl[(x - cx.lo) * a.R + k];  // gathered at kernel start
-    return static_cast<T>(static_cast<const TIn *>(a.bin)[(size_t)a.gather[x] * a.R + k]);
+    if (LDS) return cx.xl[(x - cx.lo) * a.R + k];  // gathered (and scaled) at kernel start
+    const T b = static_cast<T>(static_cast<const TIn *>(a.bin)[(size_t)a.gather[x] * a.R + k]);
+    return a.dinv ? scale_rhs(b, static_cast<const T *>(a.dinv)[x]) : b;
 }
 
 // Partial sum of one row's off-diagonal terms (lane `lane` of `lanes`).
@@ -122,7 +128,6 @@ __device__ __forceinline__ T row_terms(const TriArgs &a, const Ctx<T> &cx, int x
 template <typename T, typename TOut, bool PERS, bool LDS>
 __device__ __forceinline__ void finish_row(const TriArgs &a, const Ctx<T> &cx, int x, int k, T s)
 {
-    if (a.dinv) s *= static_cast<const T *>(a.dinv)[x];
     if (LDS) cx.xl[(x - cx.lo) * a.R + k] = s;
     if (!PERS) {
         static_cast<T *>(a.xw)[(size_t)x * a.R + k] = s;
@@ -237,7 +242,8 @@ __global__ void __launch_bounds__(1024) k_persistent(TriArgs a)
         const int items = (cx.hi - cx.lo) * a.R;
         for (int t = threadIdx.x; t < items; t += blockDim.x) {
             const int q = t / a.R, k = t - q * a.R;
-            cx.xl[t] = static_cast<T>(bin[(size_t)a.gather[cx.lo + q] * a.R + k]);
+            const T b = static_cast<T>(bin[(size_t)a.gather[cx.lo + q] * a.R + k]);
+            cx.xl[t] = a.dinv ? scale_rhs(b, static_cast<const T *>(a.dinv)[cx.lo + q]) : b;
         }
         __syncthreads();
     }
@@ -302,15 +308,12 @@ __global__ void __launch_bounds__(1024) k_owner(TriArgs a)
     T *mrd = mbox + (par ? half : 0);
     const int lo = a.window[2 * g], hi = a.window[2 * g + 1];
     const int CH = RPT * nt;
-    // LDS: window [win*R] T, then two buffers of { vals[W][CH] T, dinv[CH] T, cols[W][CH], slot[CH], dst[CH] }
+    // LDS: window [win*R] T, then two buffers of { vals[W][CH] T, cols[W][CH], slot[CH], dst[CH] }
     T *xl = reinterpret_cast<T *>(smem);
     const size_t win_bytes = (((size_t)(hi - lo) * R * sizeof(T)) + 15) & ~(size_t)15;
-    const size_t buf_bytes = (size_t)CH * ((W + (UNIT ? 0 : 1)) * sizeof(T) + (W + 2) * sizeof(int));
+    const size_t buf_bytes = (size_t)CH * (W * sizeof(T) + (W + 2) * sizeof(int));
     auto bvals = [&](int b) { return reinterpret_cast<T *>(smem + win_bytes + b * buf_bytes); };
-    auto bdinv = [&](int b) { return bvals(b) + (size_t)W * CH; };
-    auto bcols = [&](int b) {
-        return reinterpret_cast<int *>(smem + win_bytes + b * buf_bytes + (size_t)CH * (W + (UNIT ? 0 : 1)) * sizeof(T));
-    };
+    auto bcols = [&](int b) { return reinterpret_cast<int *>(smem + win_bytes + b * buf_bytes + (size_t)CH * W * sizeof(T)); };
     auto bslot = [&](int b) { return bcols(b) + (size_t)W * CH; };
     auto bdst = [&](int b) { return bslot(b) + CH; };
 
@@ -324,16 +327,15 @@ __global__ void __launch_bounds__(1024) k_owner(TriArgs a)
         for (int t = tid; t < items; t += nt) {
             const int q = t / R, k = t - q * R;
             const size_t src = (size_t)a.gather[lo + q] * R + k;
-            xl[t] = a.in_f64 ? static_cast<T>(static_cast<const double *>(a.bin)[src])
-                             : static_cast<T>(static_cast<const float *>(a.bin)[src]);
+            const T b = a.in_f64 ? static_cast<T>(static_cast<const double *>(a.bin)[src])
+                                 : static_cast<T>(static_cast<const float *>(a.bin)[src]);
+            xl[t] = UNIT ? b : scale_rhs(b, static_cast<const T *>(a.dinv)[lo + q]);
         }
     }
     const T *ev = static_cast<const T *>(a.ell_val);
-    const T *dv = static_cast<const T *>(a.dinv);
     // registers of one chunk prefetch
     int rc[RPT][W];
     T rv[RPT][W];
-    T rd[RPT];
     int rs[RPT], rt[RPT];
     auto chunk_rows = [&](int q, int &r0, int &r1) {
         const int f = a.chunk_step[2 * q], e = a.chunk_step[2 * q + 1];
@@ -352,7 +354,6 @@ __global__ void __launch_bounds__(1024) k_owner(TriArgs a)
                     rc[i][e] = a.ell_col[(size_t)e * a.ld + row];
                     rv[i][e] = ev[(size_t)e * a.ld + row];
                 }
-                if (!UNIT) rd[i] = dv[row];
                 rs[i] = a.exp_slot[row];
                 rt[i] = a.xout ? a.scatter[row] : -1;
             }
@@ -362,7 +363,6 @@ __global__ void __launch_bounds__(1024) k_owner(TriArgs a)
         int r0, r1;
         chunk_rows(q, r0, r1);
         T *vb = bvals(b);
-        T *db = bdinv(b);
         int *cb = bcols(b);
         int *sb = bslot(b);
         int *tb = bdst(b);
@@ -375,7 +375,6 @@ __global__ void __launch_bounds__(1024) k_owner(TriArgs a)
                     cb[e * CH + rr] = rc[i][e];
                     vb[e * CH + rr] = rv[i][e];
                 }
-                if (!UNIT) db[rr] = rd[i];
                 sb[rr] = rs[i];
                 tb[rr] = rt[i];
             }
@@ -394,7 +393,6 @@ __global__ void __launch_bounds__(1024) k_owner(TriArgs a)
         int cr0, cr1;
         chunk_rows(q, cr0, cr1);
         const T *vb = bvals(b);
-        const T *db = bdinv(b);
         const int *cb = bcols(b);
         const int *sb = bslot(b);
         const int *tb = bdst(b);
@@ -422,7 +420,6 @@ __global__ void __launch_bounds__(1024) k_owner(TriArgs a)
                         sv -= vb[e * CH + i] * dep;
                     }
                 }
-                if (!UNIT) sv *= db[i];
                 xl[(x - lo) * R + k] = sv;
                 if (a.write_xw) static_cast<T *>(a.xw)[(size_t)x * R + k] = sv;
                 const int slot = sb[i];
@@ -461,7 +458,8 @@ __global__ void __launch_bounds__(1024) k_owner(TriArgs a)
 size_t owner_lds_bytes(int win, int R, int W, int rows_per_chunk, bool unit, size_t tsize)
 {
     const size_t win_bytes = (((size_t)win * R * tsize) + 15) & ~(size_t)15;
-    const size_t buf = (size_t)rows_per_chunk * ((W + (unit ? 0 : 1)) * tsize + (W + 2) * sizeof(int));
+    (void)unit;
+    const size_t buf = (size_t)rows_per_chunk * (W * tsize + (W + 2) * sizeof(int));
     return win_bytes + 2 * buf;
 }
 
@@ -517,13 +515,13 @@ constexpr int kWsHead = 8;  // ints: first step, end step, first row, first entr
 template <typename T, int W>
 struct WsLayout {
     size_t win, buf;
-    size_t o_vals, o_dinv, o_stage, o_cols, o_slot, o_dst, o_ent, o_head, o_step;
+    size_t o_vals, o_stage, o_cols, o_slot, o_dst, o_ent, o_head, o_step;
     __host__ __device__ WsLayout(int rows, int CH, bool unit)
     {
         win = (((size_t)rows * sizeof(T)) + 15) & ~(size_t)15;
         o_vals = 0;
-        o_dinv = o_vals + (size_t)W * CH * sizeof(T);
-        o_stage = o_dinv + (unit ? 0 : (size_t)CH * sizeof(T));
+        (void)unit;
+        o_stage = o_vals + (size_t)W * CH * sizeof(T);
         o_cols = o_stage + (size_t)W * CH * sizeof(T);
         o_slot = o_cols + (size_t)W * CH * sizeof(int);
         o_dst = o_slot + (size_t)CH * sizeof(int);
@@ -570,8 +568,9 @@ __global__ void __launch_bounds__(128) k_owner_split(TriArgs a)
     }
     for (int t = tid; t < hi - lo; t += blockDim.x) {
         const size_t src = (size_t)a.gather[lo + t];
-        xl[t] = a.in_f64 ? static_cast<T>(static_cast<const double *>(a.bin)[src])
-                         : static_cast<T>(static_cast<const float *>(a.bin)[src]);
+        const T b = a.in_f64 ? static_cast<T>(static_cast<const double *>(a.bin)[src])
+                             : static_cast<T>(static_cast<const float *>(a.bin)[src]);
+        xl[t] = UNIT ? b : scale_rhs(b, static_cast<const T *>(a.dinv)[lo + t]);
     }
     __syncthreads();
     volatile int *v_fetched = &s_fetched;
@@ -585,7 +584,6 @@ __global__ void __launch_bounds__(128) k_owner_split(TriArgs a)
     if (wave == 1) {
         // ---------------- fetch wave ----------------
         const T *ev = static_cast<const T *>(a.ell_val);
-        const T *dv = static_cast<const T *>(a.dinv);
         int q_next = c0;          // next chunk to load
         int loaded_end = s0;      // steps below this lie in loaded chunks
         int pub = s0 - 1;         // last published step
@@ -606,7 +604,6 @@ __global__ void __launch_bounds__(128) k_owner_split(TriArgs a)
                 }
                 unsigned char *B = buf(q_next);
                 T *vb = reinterpret_cast<T *>(B + L.o_vals);
-                T *db = reinterpret_cast<T *>(B + L.o_dinv);
                 int *cb = reinterpret_cast<int *>(B + L.o_cols);
                 int *sb = reinterpret_cast<int *>(B + L.o_slot);
                 int *tb = reinterpret_cast<int *>(B + L.o_dst);
@@ -623,7 +620,6 @@ __global__ void __launch_bounds__(128) k_owner_split(TriArgs a)
                         cb[k * CH + i] = a.ell_col[(size_t)k * a.ld + row];
                         vb[k * CH + i] = ev[(size_t)k * a.ld + row];
                     }
-                    if (!UNIT) db[i] = dv[row];
                     sb[i] = a.exp_slot[row];
                     tb[i] = a.xout ? a.scatter[row] : -1;
                 }
@@ -719,7 +715,6 @@ __global__ void __launch_bounds__(128) k_owner_split(TriArgs a)
                 hb = reinterpret_cast<const int *>(B + L.o_head);
             }
             const T *vb = reinterpret_cast<const T *>(B + L.o_vals);
-            const T *db = reinterpret_cast<const T *>(B + L.o_dinv);
             const T *st = reinterpret_cast<const T *>(B + L.o_stage);
             const int *cb = reinterpret_cast<const int *>(B + L.o_cols);
             const int *sb = reinterpret_cast<const int *>(B + L.o_slot);
@@ -736,7 +731,6 @@ __global__ void __launch_bounds__(128) k_owner_split(TriArgs a)
                     const int c = cb[k * CH + i];
                     if (c != n) sv -= vb[k * CH + i] * (c > n ? st[i * W + k] : xl[c - lo]);
                 }
-                if (!UNIT) sv *= db[i];
                 xl[x - lo] = sv;
                 if (a.write_xw) static_cast<T *>(a.xw)[x] = sv;
                 const int slot = sb[i];
@@ -796,7 +790,6 @@ template <typename T, int W> struct DfRegs {
     int rb, re;
     int c[W];
     T v[W];
-    T d;
 };
 
 template <typename T, int W, bool UNIT, bool TAIL, bool R1>
@@ -856,11 +849,16 @@ __global__ void __launch_bounds__(W > 8 ? 512 : 768) k_dataflow(TriArgs a)
                 const int t = min(t0 + u * nt, win * R - 1);
                 gi[u] = a.gather[lo + (R1 ? t : t / R)];
             }
-            T bv[kFill];
+            T bv[kFill], dd[kFill];
 #pragma unroll
             for (int u = 0; u < kFill; ++u) {
                 const int t = min(t0 + u * nt, win * R - 1);
                 bv[u] = static_cast<T>(bin[(size_t)gi[u] * R + (R1 ? 0 : t % R)]);
+                if (!UNIT) dd[u] = static_cast<const T *>(a.dinv)[lo + (R1 ? t : t / R)];
+            }
+            if (!UNIT) {
+#pragma unroll
+                for (int u = 0; u < kFill; ++u) bv[u] = scale_rhs(bv[u], dd[u]);
             }
 #pragma unroll
             for (int u = 0; u < kFill; ++u)
@@ -887,7 +885,6 @@ __global__ void __launch_bounds__(W > 8 ? 512 : 768) k_dataflow(TriArgs a)
 
     if (wv < nwc) {
         const T *ev = static_cast<const T *>(a.ell_val);
-        const T *dv = static_cast<const T *>(a.dinv);
         const T *tv = static_cast<const T *>(a.tail_val);
         // Lanes past the step's items repeat its last item, so loads and
         // their uses are unconditional and the compiler's load waits stay
@@ -902,7 +899,6 @@ __global__ void __launch_bounds__(W > 8 ? 512 : 768) k_dataflow(TriArgs a)
                 u.c[e] = a.ell_col[(size_t)e * a.ld + x];
                 u.v[e] = ev[(size_t)e * a.ld + x];
             }
-            if (!UNIT) u.d = dv[x];
         };
         const int ntr = a.trace ? min(ns, a.trace_stride - 1) : 0;
         bool aborted = false;
@@ -980,7 +976,6 @@ __global__ void __launch_bounds__(W > 8 ? 512 : 768) k_dataflow(TriArgs a)
                     sv -= tv[p] * dd;
                 }
             }
-            if (!UNIT) sv *= u.d;
             // lanes past the items store the same value as the last item's lane
             lds_put(xl + r * R + k, sv);
             if (j < ntr && lane == 0) ltr[2 * j + 1] = __builtin_amdgcn_s_memrealtime();
