@@ -69,7 +69,8 @@ __device__ __forceinline__ int col_of(long t, int R, const int32_t *seg)
 
 // partial[blk][pair][k] = sum over the block's rows [brow[2 blk], brow[2 blk + 1])
 // of a_pair * b_pair (a block never spans two systems).  Threads of a block
-// are arranged as (rows x R): thread t owns rhs t % R.
+// are arranged as (rows x R): thread t owns rhs t % R.  When every pair shares
+// its second vector (Gram-Schmidt: V_i . w) that vector is read once per row.
 __global__ void __launch_bounds__(256) k_dot_partial(DotArgs d, int R, int rows_per_iter, const int32_t *brow,
                                                      double *partial)
 {
@@ -78,33 +79,64 @@ __global__ void __launch_bounds__(256) k_dot_partial(DotArgs d, int R, int rows_
     const int used = rows_per_iter * R;
     const int k = tid % R, r0 = tid / R;
     const long row0 = brow[2 * blockIdx.x], row1 = brow[2 * blockIdx.x + 1];
-    for (int p = 0; p < d.np; ++p) {
-        double acc = 0.0;
-        if (tid < used)
-            for (long row = row0 + r0; row < row1; row += rows_per_iter) acc += d.a[p][row * R + k] * d.b[p][row * R + k];
-        red[tid] = acc;
-        __syncthreads();
-        // fold the rows dimension: threads with the same k
-        for (int span = rows_per_iter; span > 1;) {
-            const int half = (span + 1) / 2;
-            if (tid < used && r0 < span - half) red[tid] += red[tid + half * R];
-            __syncthreads();
-            span = half;
+    bool same_b = true;
+    for (int p = 1; p < d.np; ++p) same_b = same_b && d.b[p] == d.b[0];
+    double acc[kMaxPairs];
+#pragma unroll
+    for (int p = 0; p < kMaxPairs; ++p) acc[p] = 0.0;
+    if (tid < used) {
+        if (same_b) {
+            for (long row = row0 + r0; row < row1; row += rows_per_iter) {
+                const double bv = d.b[0][row * R + k];
+#pragma unroll
+                for (int p = 0; p < kMaxPairs; ++p)
+                    if (p < d.np) acc[p] += d.a[p][row * R + k] * bv;
+            }
+        } else {
+#pragma unroll
+            for (int p = 0; p < kMaxPairs; ++p)
+                if (p < d.np)
+                    for (long row = row0 + r0; row < row1; row += rows_per_iter)
+                        acc[p] += d.a[p][row * R + k] * d.b[p][row * R + k];
         }
-        if (tid < R) partial[((size_t)blockIdx.x * d.np + p) * R + tid] = red[tid];
-        __syncthreads();
+    }
+#pragma unroll
+    for (int p = 0; p < kMaxPairs; ++p) {
+        if (p < d.np) {  // uniform across the block
+            red[tid] = acc[p];
+            __syncthreads();
+            // fold the rows dimension: threads with the same k
+            for (int span = rows_per_iter; span > 1;) {
+                const int half = (span + 1) / 2;
+                if (tid < used && r0 < span - half) red[tid] += red[tid + half * R];
+                __syncthreads();
+                span = half;
+            }
+            if (tid < R) partial[((size_t)blockIdx.x * d.np + p) * R + tid] = red[tid];
+            __syncthreads();
+        }
     }
 }
 
-// out[p][col] = sum of the partials of the blocks of col's system, in block order
-__global__ void k_dot_final(const double *partial, const int32_t *bptr, int np, int R, int P, double *out)
+// out[p][col] = sum of the partials of the blocks of col's system: one
+// workgroup per (pair, column); thread i adds blocks i, i+256, ... in order,
+// then a fixed tree folds the 256 sums (deterministic).
+__global__ void __launch_bounds__(256) k_dot_final(const double *partial, const int32_t *bptr, int np, int R, int P,
+                                                   double *out)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= np * P) return;
+    __shared__ double red[256];
+    const int t = blockIdx.x;  // p * P + col
     const int p = t / P, col = t - p * P, sys = col / R, k = col - sys * R;
     double s = 0.0;
-    for (int b = bptr[sys]; b < bptr[sys + 1]; ++b) s += partial[((size_t)b * np + p) * R + k];
-    out[t] = s;
+    for (int b = bptr[sys] + (int)threadIdx.x; b < bptr[sys + 1]; b += 256)
+        s += partial[((size_t)b * np + p) * R + k];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int half = 128; half > 0; half >>= 1) {
+        if ((int)threadIdx.x < half) red[threadIdx.x] += red[threadIdx.x + half];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[t] = red[0];
 }
 
 struct LinArgs {
@@ -149,6 +181,18 @@ __global__ void __launch_bounds__(256) k_basis_update(double *x, const double *Z
     double s = 0.0;
     for (int i = 0; i < nv; ++i) s += y[i * P + c] * Z[i * stride + t];
     x[t] += s;
+}
+
+// v[:,c] = w[:,c] / ||w[:,c]|| for active problems (norm^2 in d[c]), else 0
+__global__ void __launch_bounds__(256) k_normalize(double *v, const double *w, const double *d, const int8_t *act,
+                                                  long total, int R, const int32_t *seg)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const int c = col_of(t, R, seg);
+    const double hn = sqrt(fmax(0.0, d[c]));
+    const double cf = (act[c] && hn > 0.0) ? 1.0 / hn : 0.0;
+    v[t] = cf * w[t];
 }
 
 template <typename TS, typename TD>
@@ -213,6 +257,9 @@ struct Ctx {
     long n;
     int R, P;
     DevMem partial, dots, coef, segm, browm, bptrm;
+    DevMem d1m, d2m, dnm, actm;     // device-resident Gram-Schmidt coefficients and active mask
+    double *hb2 = nullptr;          // pinned: [2*kMaxPairs + 1][P] copies of d1, d2, dn
+    int8_t *hact = nullptr;         // pinned staging of the active mask
     const int32_t *seg = nullptr;  // row -> system (batches only)
     double *hbuf = nullptr;        // pinned host scalars
     int nblk, rows_per_iter;
@@ -247,10 +294,40 @@ struct Ctx {
         coef.alloc(sizeof(double) * (size_t)std::max(kMaxPairs, kMaxTerms) * P);
         hip_check(hipHostMalloc((void **)&hbuf, sizeof(double) * (size_t)std::max(kMaxPairs, kMaxTerms) * P, 0),
                   "hipHostMalloc");
+        d1m.alloc(sizeof(double) * kMaxPairs * P);
+        d2m.alloc(sizeof(double) * kMaxPairs * P);
+        dnm.alloc(sizeof(double) * P);
+        actm.alloc((size_t)P);
+        hip_check(hipHostMalloc((void **)&hb2, sizeof(double) * (2 * (size_t)kMaxPairs + 1) * P, 0), "hipHostMalloc");
+        hip_check(hipHostMalloc((void **)&hact, (size_t)P, 0), "hipHostMalloc");
     }
     ~Ctx()
     {
         if (hbuf) (void)hipHostFree(hbuf);
+        if (hb2) (void)hipHostFree(hb2);
+        if (hact) (void)hipHostFree(hact);
+    }
+    // inner products of np pairs, per problem, into out[p*P + c] on the device
+    void dots_dev(const double *const *a, const double *const *b, int np, double *out)
+    {
+        DotArgs d{};
+        for (int p = 0; p < np; ++p) {
+            d.a[p] = a[p];
+            d.b[p] = b[p];
+        }
+        d.np = np;
+        hipLaunchKernelGGL(k_dot_partial, dim3(nblk), dim3(256), 0, st, d, R, rows_per_iter, browm.as<int32_t>(),
+                           partial.as<double>());
+        hipLaunchKernelGGL(k_dot_final, dim3(np * P), dim3(256), 0, st, partial.as<double>(), bptrm.as<int32_t>(),
+                           np, R, P, out);
+        hip_check(hipGetLastError(), "dot launch");
+    }
+    // stream-ordered upload of the active mask; the host rewrites the staging
+    // area only after the next synchronization, when the copy has landed
+    void upload_active(const std::vector<char> &active)
+    {
+        for (int q = 0; q < P; ++q) hact[q] = active[q] ? 1 : 0;
+        hip_check(hipMemcpyAsync(actm.p, hact, (size_t)P, hipMemcpyHostToDevice, st), "H2D");
     }
     // inner products of np pairs, per problem, returned in hbuf[p*P + c]
     void dots_to_host(const double *const *a, const double *const *b, int np)
@@ -263,8 +340,8 @@ struct Ctx {
         d.np = np;
         hipLaunchKernelGGL(k_dot_partial, dim3(nblk), dim3(256), 0, st, d, R, rows_per_iter, browm.as<int32_t>(),
                            partial.as<double>());
-        hipLaunchKernelGGL(k_dot_final, dim3((np * P + 255) / 256), dim3(256), 0, st, partial.as<double>(),
-                           bptrm.as<int32_t>(), np, R, P, dots.as<double>());
+        hipLaunchKernelGGL(k_dot_final, dim3(np * P), dim3(256), 0, st, partial.as<double>(), bptrm.as<int32_t>(),
+                           np, R, P, dots.as<double>());
         hip_check(hipGetLastError(), "dot launch");
         hip_check(hipMemcpyAsync(hbuf, dots.p, sizeof(double) * np * P, hipMemcpyDeviceToHost, st), "D2H");
         hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
@@ -388,6 +465,7 @@ hec_status_t gmres(const DevHec &A, const hec_precond_t &M, int m, const double 
         std::vector<double> cf(P);
         for (int k = 0; k < P; ++k) cf[k] = active[k] ? 1.0 / beta[k] : 0.0;
         c.lincomb(Vi(0), {r}, cf);
+        c.upload_active(active);
         std::fill(g.begin(), g.end(), 0.0);
         for (int k = 0; k < P; ++k) {
             g[k] = active[k] ? beta[k] : 0.0;
@@ -397,29 +475,37 @@ hec_status_t gmres(const DevHec &A, const hec_precond_t &M, int m, const double 
         for (; j < m; ++j) {
             apply_M(M, Vi(j), Zi(j), R, n, st);
             spmv(A, Zi(j), w, R, st);
-            // two passes of classical Gram-Schmidt
-            std::vector<double> hcol((size_t)(j + 1) * P, 0.0);
+            // two passes of classical Gram-Schmidt, coefficients kept on the
+            // device; the Hessenberg column reaches the host once per step
+            for (int i = 0; i <= j; ++i) {
+                pa[i] = Vi(i);
+                pb[i] = w;
+            }
             for (int pass = 0; pass < 2; ++pass) {
-                for (int i = 0; i <= j; ++i) {
-                    pa[i] = Vi(i);
-                    pb[i] = w;
-                }
-                c.dots_to_host(pa.data(), pb.data(), j + 1);
-                std::vector<double> hh(c.hbuf, c.hbuf + (size_t)(j + 1) * P);
-                for (size_t q = 0; q < hh.size(); ++q) hcol[q] += hh[q];
-                c.upload_coef(hh);
-                hipLaunchKernelGGL(k_gs_update, dim3(blocks_for(nR)), dim3(256), 0, st, w, V, nR,
-                                   c.coef.as<double>(), j + 1, nR, R, P, c.seg);
+                double *dp = pass == 0 ? c.d1m.as<double>() : c.d2m.as<double>();
+                c.dots_dev(pa.data(), pb.data(), j + 1, dp);
+                hipLaunchKernelGGL(k_gs_update, dim3(blocks_for(nR)), dim3(256), 0, st, w, V, nR, dp, j + 1, nR, R,
+                                   P, c.seg);
                 hip_check(hipGetLastError(), "k_gs_update");
             }
             {
                 const double *a[1] = {w};
-                c.dots_to_host(a, a, 1);
+                c.dots_dev(a, a, 1, c.dnm.as<double>());
             }
+            hipLaunchKernelGGL(k_normalize, dim3(blocks_for(nR)), dim3(256), 0, st, Vi(j + 1), w, c.dnm.as<double>(),
+                               c.actm.as<int8_t>(), nR, R, c.seg);
+            hip_check(hipGetLastError(), "k_normalize");
+            const size_t hb = (size_t)(j + 1) * P;
+            hip_check(hipMemcpyAsync(c.hb2, c.d1m.p, sizeof(double) * hb, hipMemcpyDeviceToHost, st), "D2H");
+            hip_check(hipMemcpyAsync(c.hb2 + (size_t)kMaxPairs * P, c.d2m.p, sizeof(double) * hb,
+                                     hipMemcpyDeviceToHost, st), "D2H");
+            hip_check(hipMemcpyAsync(c.hb2 + 2 * (size_t)kMaxPairs * P, c.dnm.p, sizeof(double) * P,
+                                     hipMemcpyDeviceToHost, st), "D2H");
+            hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+            std::vector<double> hcol(hb);
+            for (size_t q = 0; q < hb; ++q) hcol[q] = c.hb2[q] + c.hb2[(size_t)kMaxPairs * P + q];
             std::vector<double> hn(P);
-            for (int k = 0; k < P; ++k) hn[k] = std::sqrt(std::max(0.0, c.hbuf[k]));
-            for (int k = 0; k < P; ++k) cf[k] = (active[k] && hn[k] > 0.0) ? 1.0 / hn[k] : 0.0;
-            c.lincomb(Vi(j + 1), {w}, cf);
+            for (int k = 0; k < P; ++k) hn[k] = std::sqrt(std::max(0.0, c.hb2[2 * (size_t)kMaxPairs * P + k]));
             ++iters;
             bool still = false;
             for (int k = 0; k < P; ++k) {
@@ -452,6 +538,7 @@ hec_status_t gmres(const DevHec &A, const hec_precond_t &M, int m, const double 
                     active[k] = 0;
                 still = still || active[k];
             }
+            c.upload_active(active);
             if (!still) {
                 ++j;
                 break;
