@@ -72,13 +72,24 @@ __device__ __forceinline__ int col_of(long t, int R, const int32_t *seg)
 // are arranged as (rows x R): thread t owns rhs t % R.  When every pair shares
 // its second vector (Gram-Schmidt: V_i . w) that vector is read once per row.
 __global__ void __launch_bounds__(256) k_dot_partial(DotArgs d, int R, int rows_per_iter, const int32_t *brow,
-                                                     double *partial)
+                                                     const int32_t *bsys, const int8_t *act, double *partial)
 {
     __shared__ double red[256];
+    __shared__ int s_live;
     const int tid = threadIdx.x;
     const int used = rows_per_iter * R;
     const int k = tid % R, r0 = tid / R;
-    const long row0 = brow[2 * blockIdx.x], row1 = brow[2 * blockIdx.x + 1];
+    long row0 = brow[2 * blockIdx.x], row1 = brow[2 * blockIdx.x + 1];
+    if (act) {
+        // a block whose system has no active problem contributes zeros
+        if (tid == 0) {
+            int live = 0;
+            for (int q = 0; q < R; ++q) live |= act[bsys[blockIdx.x] * R + q];
+            s_live = live;
+        }
+        __syncthreads();
+        if (!s_live) row1 = row0;
+    }
     bool same_b = true;
     for (int p = 1; p < d.np; ++p) same_b = same_b && d.b[p] == d.b[0];
     double acc[kMaxPairs];
@@ -159,13 +170,15 @@ __global__ void __launch_bounds__(256) k_lincomb(LinArgs a, long total, int R, i
     if (a.out2) a.out2[t] = s;
 }
 
-// w[:,c] -= sum_{i<nv} h[i][c] * V_i[:,c]   (V_i = V + i*stride)
+// w[:,c] -= sum_{i<nv} h[i][c] * V_i[:,c]   (V_i = V + i*stride); problems
+// that are no longer active (act[c] == 0) are left untouched
 __global__ void __launch_bounds__(256) k_gs_update(double *w, const double *V, long stride, const double *h, int nv,
-                                                  long total, int R, int P, const int32_t *seg)
+                                                  long total, int R, int P, const int32_t *seg, const int8_t *act)
 {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total) return;
     const int c = col_of(t, R, seg);
+    if (act && !act[c]) return;
     double s = w[t];
     for (int i = 0; i < nv; ++i) s -= h[i * P + c] * V[i * stride + t];
     w[t] = s;
@@ -256,7 +269,7 @@ struct Ctx {
     hipStream_t st;
     long n;
     int R, P;
-    DevMem partial, dots, coef, segm, browm, bptrm;
+    DevMem partial, dots, coef, segm, browm, bptrm, bsysm;
     DevMem d1m, d2m, dnm, actm;     // device-resident Gram-Schmidt coefficients and active mask
     double *hb2 = nullptr;          // pinned: [2*kMaxPairs + 1][P] copies of d1, d2, dn
     int8_t *hact = nullptr;         // pinned staging of the active mask
@@ -269,19 +282,24 @@ struct Ctx {
         rows_per_iter = std::max(1, 256 / R);
         // reduction blocks: each covers rows of one system only
         const long chunk = std::max<long>((long)rows_per_iter * 4, (n + 1023) / 1024);
-        std::vector<int32_t> brow, bptr(1, 0);
+        std::vector<int32_t> brow, bptr(1, 0), bsys;
         for (int sy = 0; sy < nsys; ++sy) {
             const long r0 = sys_ptr ? sys_ptr[sy] : 0, r1 = sys_ptr ? sys_ptr[sy + 1] : n;
             for (long r = r0; r < r1; r += chunk) {
                 brow.push_back((int32_t)r);
                 brow.push_back((int32_t)std::min(r1, r + chunk));
+                bsys.push_back(sy);
             }
             bptr.push_back((int32_t)(brow.size() / 2));
         }
-        if (brow.empty()) brow = {0, 0};
+        if (brow.empty()) {
+            brow = {0, 0};
+            bsys = {0};
+        }
         nblk = (int)(brow.size() / 2);
         upload(browm, brow);
         upload(bptrm, bptr);
+        upload(bsysm, bsys);
         if (nsys > 1) {
             std::vector<int32_t> sg((size_t)n);
             for (int sy = 0; sy < nsys; ++sy)
@@ -308,7 +326,7 @@ struct Ctx {
         if (hact) (void)hipHostFree(hact);
     }
     // inner products of np pairs, per problem, into out[p*P + c] on the device
-    void dots_dev(const double *const *a, const double *const *b, int np, double *out)
+    void dots_dev(const double *const *a, const double *const *b, int np, double *out, const int8_t *act = nullptr)
     {
         DotArgs d{};
         for (int p = 0; p < np; ++p) {
@@ -317,7 +335,7 @@ struct Ctx {
         }
         d.np = np;
         hipLaunchKernelGGL(k_dot_partial, dim3(nblk), dim3(256), 0, st, d, R, rows_per_iter, browm.as<int32_t>(),
-                           partial.as<double>());
+                           bsysm.as<int32_t>(), act, partial.as<double>());
         hipLaunchKernelGGL(k_dot_final, dim3(np * P), dim3(256), 0, st, partial.as<double>(), bptrm.as<int32_t>(),
                            np, R, P, out);
         hip_check(hipGetLastError(), "dot launch");
@@ -339,7 +357,7 @@ struct Ctx {
         }
         d.np = np;
         hipLaunchKernelGGL(k_dot_partial, dim3(nblk), dim3(256), 0, st, d, R, rows_per_iter, browm.as<int32_t>(),
-                           partial.as<double>());
+                           bsysm.as<int32_t>(), (const int8_t *)nullptr, partial.as<double>());
         hipLaunchKernelGGL(k_dot_final, dim3(np * P), dim3(256), 0, st, partial.as<double>(), bptrm.as<int32_t>(),
                            np, R, P, dots.as<double>());
         hip_check(hipGetLastError(), "dot launch");
@@ -483,14 +501,14 @@ hec_status_t gmres(const DevHec &A, const hec_precond_t &M, int m, const double 
             }
             for (int pass = 0; pass < 2; ++pass) {
                 double *dp = pass == 0 ? c.d1m.as<double>() : c.d2m.as<double>();
-                c.dots_dev(pa.data(), pb.data(), j + 1, dp);
+                c.dots_dev(pa.data(), pb.data(), j + 1, dp, c.actm.as<int8_t>());
                 hipLaunchKernelGGL(k_gs_update, dim3(blocks_for(nR)), dim3(256), 0, st, w, V, nR, dp, j + 1, nR, R,
-                                   P, c.seg);
+                                   P, c.seg, c.actm.as<int8_t>());
                 hip_check(hipGetLastError(), "k_gs_update");
             }
             {
                 const double *a[1] = {w};
-                c.dots_dev(a, a, 1, c.dnm.as<double>());
+                c.dots_dev(a, a, 1, c.dnm.as<double>(), c.actm.as<int8_t>());
             }
             hipLaunchKernelGGL(k_normalize, dim3(blocks_for(nR)), dim3(256), 0, st, Vi(j + 1), w, c.dnm.as<double>(),
                                c.actm.as<int8_t>(), nR, R, c.seg);
