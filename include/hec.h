@@ -267,6 +267,19 @@ void ilu_destroy(ilu_t ilu);
 hec_status_t ras_setup(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val,
                        int32_t nsub, const int32_t *owner, int32_t overlap, hec_dtype_t factor_dt,
                        const hec_tune_t *tune, ras_t *out);
+/* Block ILU(k) and block ILUT (Section 3), and RAS with those subdomain
+ * factorizations: as ras_setup, but every A_s is factored by `kind` (k: fill
+ * level for HEC_ILUK; tol, p: drop tolerance relative to the row's 2-norm and
+ * entries kept per row in each of L and U for HEC_ILUT) instead of ILU(0).
+ * overlap = 0 gives the block-Jacobi forms (BILU(k), BILUT): every row is in
+ * exactly one block and the couplings between blocks are dropped.  The
+ * returned handle is a ras_t (ras_apply, ras_info, ras_plans, krylov_solve).
+ * Errors: as ras_setup, plus INVALID_ARG for an unknown kind, k < 0, p < 0 or
+ * tol < 0. */
+hec_status_t ras_setup_ilu(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val,
+                           int32_t nsub, const int32_t *owner, int32_t overlap, hec_ilu_kind_t kind,
+                           int32_t k, double tol, int32_t p, hec_dtype_t factor_dt,
+                           const hec_tune_t *tune, ras_t *out);
 hec_status_t ras_apply(ras_t ras, const double *r, double *z, int32_t nrhs, hipStream_t stream);
 /* Extended-subdomain sizes (ext[nsub], may be NULL) and total extended rows. */
 hec_status_t ras_info(ras_t ras, int32_t *nsub, int64_t *total_ext, int32_t *ext_sizes);

@@ -354,6 +354,59 @@ def ilu_apply_f32(L32: CSR, U32: CSR, r, unit_l: bool = True) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------
+# Multithreaded level-scheduled CPU baseline (Algorithm 2 on the host cores).
+# --------------------------------------------------------------------------
+
+_omp_lib = None
+
+
+def _Lomp():
+    global _omp_lib
+    if _omp_lib is None:
+        lib = ctypes.CDLL(_build.build_omp())
+        i32, vp = ctypes.c_int32, ctypes.c_void_p
+        lib.orc_level_solve_omp.restype = ctypes.c_int
+        lib.orc_level_solve_omp.argtypes = [i32, vp, vp, vp, ctypes.c_int, ctypes.c_int, i32, vp, vp,
+                                            i32, vp, vp, i32]
+        lib.orc_omp_threads.restype = ctypes.c_int
+        lib.orc_omp_threads.argtypes = []
+        _omp_lib = lib
+    return _omp_lib
+
+
+def omp_threads() -> int:
+    """Threads the OpenMP baseline uses by default on this host."""
+    return int(_Lomp().orc_omp_threads())
+
+
+class LevelSolveCPU:
+    """One triangle prepared for the multithreaded level-scheduled CPU solve:
+    levels by eq. (2) and level sets by eq. (3) (this module's own analysis),
+    then every level's rows in parallel with the serial substitution's
+    per-row arithmetic, so the result equals :func:`lower_solve` /
+    :func:`upper_solve` bit for bit.  A host comparison baseline, not an
+    oracle of its own."""
+
+    def __init__(self, T: CSR, upper: bool = False, unit: bool = False):
+        lev, nlev = levels(T, upper=upper)
+        levelptr, perm, _ = level_schedule(lev, nlev, upper=upper)
+        self.n, self.upper, self.unit, self.nlev = T.n, bool(upper), bool(unit), nlev
+        self.rp, self.ci = _csr_args(T)
+        self.v = np.ascontiguousarray(T.val, dtype=np.float64)
+        self.levelptr = np.ascontiguousarray(levelptr, dtype=np.int32)
+        self.perm = np.ascontiguousarray(perm, dtype=np.int32)
+
+    def solve(self, b, threads: int = 0) -> np.ndarray:
+        b2, flat = _as2d(b)
+        b2 = np.ascontiguousarray(b2, dtype=np.float64)
+        x = np.empty_like(b2)
+        _check(_Lomp().orc_level_solve_omp(self.n, _p(self.rp), _p(self.ci), _p(self.v), int(self.unit),
+                                           int(self.upper), self.nlev, _p(self.levelptr), _p(self.perm),
+                                           b2.shape[1], _p(b2), _p(x), int(threads)))
+        return x[:, 0] if flat else x
+
+
+# --------------------------------------------------------------------------
 # Restricted Additive Schwarz, Section 3 and eq. (4).
 # --------------------------------------------------------------------------
 
@@ -372,10 +425,16 @@ def _submatrix(A: CSR, rows: np.ndarray) -> CSR:
     return CSR(len(rows), S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data.copy())
 
 
-def ras_setup(A: CSR, owner: np.ndarray, nsub: int, overlap: int = 1):
+def ras_setup(A: CSR, owner: np.ndarray, nsub: int, overlap: int = 1, kind: str = "ilu0",
+              k: int = 0, tau: float = 0.0, p: int = 0):
     """RAS setup: subdomain i owns the rows with owner == i; its extended set
     adds ``overlap`` rings of graph neighbours in A; A_i = A[ext_i, ext_i]
-    (couplings to rows outside are dropped) is factored by ILU(0)."""
+    (couplings to rows outside are dropped) is factored by ILU(0), or by
+    ILU(k) / ILUT(p, tau) for the block forms of Section 3 (with overlap 0
+    these are block ILU(k) and block ILUT: one block per subdomain, the
+    couplings between blocks dropped)."""
+    if kind not in ("ilu0", "iluk", "ilut"):
+        raise ValueError("unknown ILU kind %r" % kind)
     S = A.to_scipy()
     out = []
     for s in range(nsub):
@@ -385,15 +444,20 @@ def ras_setup(A: CSR, owner: np.ndarray, nsub: int, overlap: int = 1):
             nb = np.unique(S[ext].indices)
             ext = np.union1d(ext, nb)
         Ai = _submatrix(A, ext)
-        L, U = ilu0(Ai)
+        if kind == "ilu0":
+            L, U = ilu0(Ai)
+        elif kind == "iluk":
+            L, U = iluk(Ai, k)
+        else:
+            L, U = ilut(Ai, p, tau)
         out.append(RASDomain(ext, np.searchsorted(ext, owned), owned, L, U))
     return out
 
 
 def ras_apply(doms, r) -> np.ndarray:
     """z = sum_i R_i^0' (L_i U_i)^{-1} R_i r (eq. (4) applied block by block):
-    restrict r to each extended subdomain, solve with its ILU(0) factors and
-    write back only the owned rows."""
+    restrict r to each extended subdomain, solve with its factors and write
+    back only the owned rows."""
     r2, flat = _as2d(r)
     z = np.zeros_like(r2, dtype=np.float64)
     for d in doms:

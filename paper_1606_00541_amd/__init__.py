@@ -93,6 +93,8 @@ SIGNATURES = {
     "ilu_apply": (_i32, [_vp, _vp, _vp, _i32, _i32, _vp]),
     "ilu_destroy": (None, [_vp]),
     "ras_setup": (_i32, [_i32, _vp, _vp, _vp, _i32, _vp, _i32, _i32, _P(Tune), _P(_vp)]),
+    "ras_setup_ilu": (_i32, [_i32, _vp, _vp, _vp, _i32, _vp, _i32, _i32, _i32, ctypes.c_double, _i32, _i32,
+                             _P(Tune), _P(_vp)]),
     "ras_apply": (_i32, [_vp, _vp, _vp, _i32, _vp]),
     "ras_info": (_i32, [_vp, _P(_i32), _P(_i64), _vp]),
     "ras_plans": (_i32, [_vp, _P(_vp), _P(_vp)]),
@@ -398,6 +400,22 @@ def ras_setup(A, nsub, owner, overlap=1, factor_dtype="f64", tune: Tune | None =
     out = ctypes.c_void_p()
     _check(lib().ras_setup(n, _ptr(rp), _ptr(ci), _ptr(v), int(nsub), _ptr(ow), int(overlap), _dt(factor_dtype),
                            ctypes.byref(tune) if tune is not None else None, ctypes.byref(out)))
+    s = Ras(out.value)
+    s.n = n
+    s.nsub = int(nsub)
+    return s
+
+
+def ras_setup_ilu(A, nsub, owner, overlap=0, kind="ilut", k=0, tol=0.0, p=0, factor_dtype="f64",
+                  tune: Tune | None = None) -> Ras:
+    """Block ILU(k) / block ILUT (overlap 0) or RAS with that subdomain
+    factorization (overlap > 0)."""
+    n, rp, ci, v = _csr(A)
+    ow = _np(owner, np.int32)
+    out = ctypes.c_void_p()
+    _check(lib().ras_setup_ilu(n, _ptr(rp), _ptr(ci), _ptr(v), int(nsub), _ptr(ow), int(overlap), ILU_KIND[kind],
+                               int(k), float(tol), int(p), _dt(factor_dtype),
+                               ctypes.byref(tune) if tune is not None else None, ctypes.byref(out)))
     s = Ras(out.value)
     s.n = n
     s.nsub = int(nsub)

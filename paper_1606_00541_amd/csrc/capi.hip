@@ -541,9 +541,17 @@ void ilu_destroy(ilu_t f) { delete f; }
 hec_status_t ras_setup(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val, int32_t nsub,
                        const int32_t *owner, int32_t overlap, hec_dtype_t fdt, const hec_tune_t *tune, ras_t *out)
 {
+    return ras_setup_ilu(n, rowptr, col, val, nsub, owner, overlap, HEC_ILU0, 0, 0.0, 0, fdt, tune, out);
+}
+
+hec_status_t ras_setup_ilu(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val, int32_t nsub,
+                           const int32_t *owner, int32_t overlap, hec_ilu_kind_t kind, int32_t k, double tol,
+                           int32_t p, hec_dtype_t fdt, const hec_tune_t *tune, ras_t *out)
+{
     return guard([&] {
         if (!out) fail(HEC_ERR_INVALID_ARG, "out is NULL");
         if (fdt != HEC_F64 && fdt != HEC_F32) fail(HEC_ERR_INVALID_ARG, "bad factor dtype");
+        if (kind != HEC_ILU0 && kind != HEC_ILUK && kind != HEC_ILUT) fail(HEC_ERR_INVALID_ARG, "unknown ILU kind");
         Tune tu = tune_from(tune);
         Csr a = csr_copy(n, rowptr, col, val, HEC_F64);
         auto s = std::make_unique<ras_s>();
@@ -551,7 +559,7 @@ hec_status_t ras_setup(int32_t n, const int32_t *rowptr, const int32_t *col, con
         s->nsub = nsub;
         s->lay = ras_layout(a, nsub, owner, overlap);
         ilu_s &f = s->f;
-        factor(s->lay.blockdiag, HEC_ILU0, 0, 0.0, 0, f.Lf, f.Uf, &s->lay.ext_ptr);
+        factor(s->lay.blockdiag, kind, k, tol, p, f.Lf, f.Uf, &s->lay.ext_ptr);
         build_ilu(f, f.Lf, f.Uf, fdt, tu);
         if (!tu.host_only) {
             const int32_t m = s->lay.blockdiag.n;

@@ -30,6 +30,7 @@ __all__ = [
     "diffusion3d",
     "rhs",
     "subdomain_cuts",
+    "grid_bisection",
     "batch_systems",
     "random_lower",
 ]
@@ -177,6 +178,38 @@ def subdomain_cuts(n: int, nsub: int, lo: int, hi: int, seed: int, max_draws: in
             owner = np.repeat(np.arange(nsub, dtype=np.int32), sizes)
             return owner, sizes
     raise RuntimeError("no admissible subdomain cut found")
+
+
+def grid_bisection(nx: int, ny: int, nz: int, nparts: int) -> np.ndarray:
+    """Geometric partition of an nx x ny x nz grid (natural order
+    idx = x + nx*(y + ny*z)) into ``nparts`` boxes by recursive coordinate
+    bisection: the longest side of the current box (z, then y, then x on
+    ties) is cut so that the two halves get cell counts in the ratio of the
+    parts they receive (floor(parts/2) : the rest).  A stand-in for a graph
+    partitioner's subdomains.  Returns the owner array (int32 [n])."""
+    if nparts < 1 or nparts > nx * ny * nz:
+        raise ValueError("bad number of parts")
+    owner = np.empty((nz, ny, nx), dtype=np.int32)
+
+    def rec(box, first, parts):
+        if parts == 1:
+            (z0, z1), (y0, y1), (x0, x1) = box
+            owner[z0:z1, y0:y1, x0:x1] = first
+            return
+        ext = [hi - lo for lo, hi in box]
+        ax = int(np.argmax(ext))
+        if ext[ax] < 2:
+            raise ValueError("more parts than the grid can be cut into")
+        left = parts // 2
+        lo, hi = box[ax]
+        cut = lo + min(max(1, int(round(ext[ax] * left / parts))), ext[ax] - 1)
+        a, b = list(box), list(box)
+        a[ax], b[ax] = (lo, cut), (cut, hi)
+        rec(a, first, left)
+        rec(b, first + left, parts - left)
+
+    rec([(0, nz), (0, ny), (0, nx)], 0, nparts)
+    return owner.ravel()
 
 
 def batch_systems(nsys: int, seed: int, nmin: float = 1e3, nmax: float = 2e5):

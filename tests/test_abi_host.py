@@ -2,6 +2,7 @@
 header declares, and the host-side analysis (Algorithm 1), factorizations
 and RAS setup agree bit for bit with the oracle.  No GPU is touched: plans
 are built with the host-only tuning flag."""
+import ctypes
 import os
 import re
 
@@ -187,6 +188,27 @@ def test_ras_layout_matches_oracle():
     nsub, tot, sizes = H.ras_info(s)
     assert nsub == 5 and tot == sum(len(d.ext) for d in doms)
     assert list(sizes) == [len(d.ext) for d in doms]
+
+
+
+def test_block_ilu_layout_and_errors():
+    A = synth.diffusion3d(8, 8, 6, 1.0, seed=3)
+    owner = synth.grid_bisection(8, 8, 6, 6)
+    s = H.ras_setup_ilu(A, 6, owner, overlap=0, kind="ilut", p=7, tol=0.1, tune=HOST)
+    nsub, tot, sizes = H.ras_info(s)
+    assert nsub == 6 and tot == A.n and list(sizes) == list(np.bincount(owner))
+    s1 = H.ras_setup_ilu(A, 6, owner, overlap=1, kind="iluk", k=1, tune=HOST)
+    doms = oracle.ras_setup(A, owner, 6, overlap=1, kind="iluk", k=1)
+    assert list(H.ras_info(s1)[2]) == [len(d.ext) for d in doms]
+    for kw in ({"kind": "iluk", "k": -1}, {"kind": "ilut", "p": -1}, {"kind": "ilut", "tol": -1.0}):
+        with pytest.raises(H.HecError) as e:
+            H.ras_setup_ilu(A, 6, owner, tune=HOST, **kw)
+        assert e.value.name == "INVALID_ARG"
+    n, rp, ci, v = H._csr(A)
+    out = ctypes.c_void_p()
+    rc = H.lib().ras_setup_ilu(n, H._ptr(rp), H._ptr(ci), H._ptr(v), 6, H._ptr(owner.astype(np.int32)), 0, 7, 0,
+                               0.0, 0, 0, ctypes.byref(HOST), ctypes.byref(out))
+    assert H.STATUS_NAMES[rc] == "INVALID_ARG"
 
 
 def test_auto_tuning_picks_the_dataflow_kernel_when_it_fits():

@@ -95,6 +95,45 @@ def test_ras_matches_oracle(fdt):
         assert relerr(z, oracle.ras_apply_f32(oracle.ras_to_f32(doms), r)) <= 1e-5
 
 
+
+@pytest.mark.parametrize("fdt", ["f64", "f32"])
+@pytest.mark.parametrize("overlap", [0, 1])
+@pytest.mark.parametrize("kind,args", [("iluk", {"k": 1}), ("ilut", {"p": 7, "tol": 0.1}),
+                                       ("ilut", {"p": 10, "tol": 1e-3})])
+def test_block_ilu_and_ras_ilu_match_oracle(kind, args, overlap, fdt):
+    # BILU(k) / BILUT (overlap 0) and RAS with ILU(k) / ILUT subdomains
+    A = synth.diffusion3d(16, 14, 12, 1.0, seed=9)
+    owner = synth.grid_bisection(16, 14, 12, 8)
+    s = H.ras_setup_ilu(A, 8, owner, overlap=overlap, kind=kind, factor_dtype=fdt,
+                        tune=H.tune_default(max_nrhs=2), **args)
+    oargs = {"k": args["k"]} if kind == "iluk" else {"p": args["p"], "tau": args["tol"]}
+    doms = oracle.ras_setup(A, owner, 8, overlap=overlap, kind=kind, **oargs)
+    assert list(H.ras_info(s)[2]) == [len(d.ext) for d in doms]
+    r = synth.rhs(A.n, 2, 6)
+    z = apply(s, r)
+    if fdt == "f64":
+        assert relerr(z, oracle.ras_apply(doms, r)) <= FP64_TOL
+    else:
+        assert relerr(z, oracle.ras_apply_f32(oracle.ras_to_f32(doms), r)) <= 1e-5
+
+
+def test_gmres20_with_block_ilut():
+    # the paper's solver and block preconditioner pairing (Section 4, GMRES(20))
+    A = synth.poisson3d(24)
+    owner = synth.grid_bisection(24, 24, 24, 16)
+    s = H.ras_setup_ilu(A, 16, owner, overlap=0, kind="ilut", p=7, tol=0.1)
+    M = H.hec_from_csr(A)
+    b = synth.rhs(A.n, 1, 1)
+    xt = torch.zeros(A.n, 1, dtype=torch.float64, device="cuda")
+    st, info = H.krylov_solve(M, s, dev(b), xt, method="gmres", m=20, rtol=1e-10)
+    assert st == 0 and info[0].relres <= 1e-10
+    x = xt.cpu().numpy()[:, 0]
+    assert np.linalg.norm(b[:, 0] - oracle.spmv(A, x)) / np.linalg.norm(b[:, 0]) <= 1e-10
+    doms = oracle.ras_setup(A, owner, 16, overlap=0, kind="ilut", p=7, tau=0.1)
+    xo, oinfo = oracle.fgmres(A, b[:, 0], lambda v: oracle.ras_apply(doms, v), m=20, rtol=1e-10)
+    assert oinfo.converged and abs(info[0].iters - oinfo.iters) <= 2
+
+
 def _block_diag(mats):
     rps, cis, vs, sys_ptr, off, nnz = [np.zeros(1, np.int64)], [], [], [0], 0, 0
     for M in mats:

@@ -108,3 +108,42 @@ def test_ras_preconditioned_bicgstab():
     b = synth.rhs(A.n, 1, 4)[:, 0]
     x, info = oracle.bicgstab(A, b, lambda v: oracle.ras_apply_f32(d32, v), rtol=1e-10)
     assert info.converged and info.relres <= 1e-10
+
+
+@pytest.mark.parametrize("kind,args", [("iluk", {"k": 1}), ("iluk", {"k": 2}),
+                                       ("ilut", {"p": 7, "tau": 0.1}), ("ilut", {"p": 10, "tau": 1e-3})])
+def test_block_ilu_is_the_factorization_of_the_decoupled_matrix(kind, args):
+    # block ILU(k) / block ILUT (Section 3, overlap 0): the same factorization
+    # applied to A with every coupling between blocks removed
+    A = synth.diffusion3d(8, 7, 6, 1.0, seed=12)
+    owner = synth.grid_bisection(8, 7, 6, 5)
+    doms = oracle.ras_setup(A, owner, 5, overlap=0, kind=kind, **args)
+    Ad = A.to_dense()
+    Ab = _dense_csr(np.where(owner[:, None] == owner[None, :], Ad, 0.0))
+    L, U = oracle.iluk(Ab, args["k"]) if kind == "iluk" else oracle.ilut(Ab, args["p"], args["tau"])
+    r = synth.rhs(A.n, 2, 13)
+    assert np.array_equal(oracle.ras_apply(doms, r), oracle.ilu_apply(L, U, r))
+
+
+def test_block_ilut_without_dropping_is_the_exact_block_solve():
+    # tau = 0 and p >= block size keeps every entry: each block is solved exactly
+    A = synth.diffusion2d(9, 8, 1.5, seed=14)
+    owner = synth.grid_bisection(9, 8, 1, 4)
+    doms = oracle.ras_setup(A, owner, 4, overlap=0, kind="ilut", tau=0.0, p=A.n)
+    Ab = np.where(owner[:, None] == owner[None, :], A.to_dense(), 0.0)
+    r = synth.rhs(A.n, 1, 15)
+    ref = np.linalg.solve(Ab, r)
+    assert np.linalg.norm(oracle.ras_apply(doms, r) - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_grid_bisection_boxes():
+    owner = synth.grid_bisection(10, 9, 7, 12)
+    sizes = np.bincount(owner)
+    assert len(sizes) == 12 and sizes.sum() == 630
+    o = owner.reshape(7, 9, 10)
+    for s in range(12):
+        z, y, x = np.nonzero(o == s)
+        box = (z.max() - z.min() + 1) * (y.max() - y.min() + 1) * (x.max() - x.min() + 1)
+        assert box == sizes[s]  # every part is one axis-aligned box
+    with pytest.raises(ValueError):
+        oracle.ras_setup(synth.poisson2d(4), np.zeros(16, np.int32), 1, kind="ilu2")

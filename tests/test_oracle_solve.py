@@ -159,3 +159,27 @@ def test_errors_are_reported():
         oracle.lower_solve(nodiag, np.ones(2))
     # with a unit diagonal the missing entry is fine
     assert np.array_equal(oracle.lower_solve(nodiag, np.ones(2), unit=True), np.array([1.0, 0.0]))
+
+
+@pytest.mark.parametrize("threads", [1, 3, 8])
+@pytest.mark.parametrize("upper,unit", [(False, False), (False, True), (True, False)])
+def test_omp_level_solve_equals_serial_substitution(threads, upper, unit):
+    # the multithreaded CPU baseline does the serial per-row arithmetic in
+    # level order (Algorithm 2 on the host), so it must agree bit for bit
+    T = synth.random_lower(700, 0.01, 21, unit=unit, dense_row=350)
+    if upper:
+        T = CSR(T.n, *_transpose(T))
+    b = synth.rhs(T.n, 3, 22)
+    ref = oracle.upper_solve(T, b, unit=unit) if upper else oracle.lower_solve(T, b, unit=unit)
+    got = oracle.LevelSolveCPU(T, upper=upper, unit=unit).solve(b, threads=threads)
+    assert np.array_equal(got, ref)
+
+
+def test_omp_level_solve_on_ilu0_factors():
+    A = synth.poisson3d(12, 10, 9)
+    L, U = oracle.ilu0(A)
+    r = synth.rhs(A.n, 1, 2)
+    sl, su = oracle.LevelSolveCPU(L, unit=True), oracle.LevelSolveCPU(U, upper=True)
+    assert sl.nlev == 12 + 10 + 9 - 2 and su.nlev == sl.nlev
+    assert np.array_equal(su.solve(sl.solve(r)), oracle.ilu_apply(L, U, r))
+    assert oracle.omp_threads() >= 1
