@@ -170,7 +170,8 @@ def _tune(H, args, **kw):
 def run_config(cfg, args):
     """Secondary workloads (one JSON line each): 3 = mixed precision on
     heterogeneous ILUT, 4 = RAS with 16 RHS, 5 = 256 batched systems,
-    6 = the block-preconditioner table of the paper's Example 1."""
+    6 = the block-preconditioner table of the paper's Example 1, 7 = SOR /
+    Gauss-Seidel smoother sweeps."""
     import numpy as np
     import torch
 
@@ -289,10 +290,64 @@ def run_config(cfg, args):
                     round(res["f64"]["fgmres"]["seconds"] / res["f32"]["fgmres"]["seconds"], 4)})
     elif cfg == 6:
         out.update(_table1(H, torch, np, synth, args))
+    elif cfg == 7:
+        out.update(_smoother(H, torch, np, synth, args))
     else:
         raise SystemExit("unknown --config %d" % cfg)
     print(json.dumps(out))
     return 0
+
+
+def _smoother(H, torch, np, synth, args):
+    """SOR / Gauss-Seidel sweeps on the 128^3 Poisson matrix: a forward
+    sweep is one SpMV with U + (1 - 1/omega) D and one level-scheduled lower
+    solve with D/omega + L; a symmetric sweep adds the mirrored pair."""
+    s = args.grid
+    A = synth.poisson3d(s)
+    n = A.n
+    res = {}
+    b = torch.from_numpy(synth.rhs(n, 1, 7)).cuda()
+    for omega in (1.0, 1.5):
+        _log("config 7: SOR setup, omega %.1f" % omega)
+        t0 = time.time()
+        S = H.sor_setup(A, omega, tune=_tune(H, args))
+        setup = time.time() - t0
+        nnz_off = (A.nnz - n) // 2
+        nnz_n = nnz_off + (0 if omega == 1.0 else n)
+        # SpMV: values + indices, read x and b, write t; solve: as one triangular launch
+        B_fwd = nnz_n * 12 + 3 * n * 8 + per_launch_bytes(n, nnz_off, 1, diag=True)
+        row = {"setup_s": round(setup, 3)}
+        for sym in (False, True):
+            x = torch.zeros_like(b)
+            for _ in range(args.warmup):
+                H.sor_apply(S, b, x, sweeps=1, symmetric=sym)
+            torch.cuda.synchronize()
+            stream = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            H.sor_apply(S, b, x, sweeps=args.steps, symmetric=sym)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            Bs = B_fwd * (2 if sym else 1)
+            row["ssor" if sym else "sor"] = {"ms_per_sweep": round(ms, 4), "GBps": round(Bs / (ms * 1e-3) / 1e9, 2)}
+        if not args.no_cpu_baseline:
+            import oracle
+
+            x0 = synth.rhs(n, 1, 8)
+            xt = torch.from_numpy(x0.copy()).cuda()
+            H.sor_apply(S, b, xt, sweeps=1, symmetric=True)
+            t2 = time.time()
+            ref = oracle.sor(A, b.cpu().numpy(), x0, omega=omega, sweeps=1, symmetric=True)
+            row["cpu_oracle_ms_per_ssor_sweep"] = round(1e3 * (time.time() - t2), 3)
+            row["parity_relerr_vs_oracle"] = float(np.linalg.norm(xt.cpu().numpy() - ref) / np.linalg.norm(ref))
+        res["omega_%.1f" % omega] = row
+    gs = res["omega_1.0"]["sor"]
+    return {"value": gs["GBps"], "dtype": "f64", "ms_per_step": gs["ms_per_sweep"],
+            "config": {"workload": "SOR / Gauss-Seidel smoother on 3D 7-point Poisson %d^3 (n=%d), FP64, 1 RHS; "
+                                   "step = one forward Gauss-Seidel sweep (SpMV + level-scheduled lower solve)"
+                                   % (s, n)},
+            "sweeps": res}
 
 
 # Block counts and one-application times ("Pre GPU (s)") of the paper's

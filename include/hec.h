@@ -302,6 +302,31 @@ hec_status_t batch_setup(int32_t n, const int32_t *rowptr, const int32_t *col, c
                          ilu_t *out);
 
 /* ---------------------------------------------------------------------------
+ * SOR / Gauss-Seidel smoother (Section 1: Gauss-Seidel smoothers of algebraic
+ * multigrid are among the users of triangular solves).  With A = D + L + U
+ * (diagonal, strict lower and strict upper parts) a forward sweep is
+ *     x <- (D/omega + L)^{-1} (b - (U + (1 - 1/omega) D) x),
+ * one HEC SpMV followed by one level-scheduled lower solve (Algorithm 2); a
+ * backward sweep exchanges L and U.  omega = 1 is Gauss-Seidel.
+ * sor_setup: host CSR A (rows sorted, every diagonal stored and nonzero),
+ * 0 < omega < 2; builds the plans of D/omega + L and D/omega + U (tune as
+ * tri_analyze; NULL = defaults) and the two SpMV operators, all FP64.  The host
+ * arrays are copied.
+ * sor_apply: `sweeps` >= 0 sweeps on x in place (x holds the initial guess);
+ * symmetric = 0: forward sweeps; 1: forward then backward per sweep (SSOR).
+ * b, x: device FP64 [n][nrhs]; must not alias.  Asynchronous on `stream`.
+ * Errors: INVALID_ARG (omega outside (0, 2), nrhs < 1, sweeps < 0, aliasing),
+ * MISSING_DIAG, ZERO_PIVOT, UNSORTED, NOT_TRIANGULAR as tri_analyze,
+ * NO_DEVICE for a host-only setup.
+ * ------------------------------------------------------------------------- */
+typedef struct sor_s *sor_t;
+hec_status_t sor_setup(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val, double omega,
+                       const hec_tune_t *tune, sor_t *out);
+hec_status_t sor_apply(sor_t sor, const double *b, double *x, int32_t nrhs, int32_t sweeps, int32_t symmetric,
+                       hipStream_t stream);
+void sor_destroy(sor_t sor);
+
+/* ---------------------------------------------------------------------------
  * Restarted Krylov solvers (Section 4 uses restarted GMRES) for A x = b with
  * right preconditioning by M; every RHS is an independent system sharing the
  * operator.  Residual, inner products, norms and updates are FP64 on the

@@ -51,6 +51,8 @@ def _L():
         lib.orc_ilut.argtypes = [i32, vp, vp, vp, i32, ctypes.c_double,
                                  ctypes.POINTER(_I32P), ctypes.POINTER(_I32P), ctypes.POINTER(_F64P),
                                  ctypes.POINTER(_I32P), ctypes.POINTER(_I32P), ctypes.POINTER(_F64P)]
+        lib.orc_sor.restype = ctypes.c_int
+        lib.orc_sor.argtypes = [i32, vp, vp, vp, ctypes.c_double, i32, vp, vp, i32, ctypes.c_int]
         lib.orc_free.restype = None
         lib.orc_free.argtypes = [vp]
         _lib = lib
@@ -130,6 +132,21 @@ def upper_solve_f32(U: CSR, b, unit: bool = False) -> np.ndarray:
     rp, ci = _csr_args(U)
     v = np.ascontiguousarray(U.val, dtype=np.float32)
     _check(_L().orc_upper_solve_f32(U.n, _p(rp), _p(ci), _p(v), int(unit), b2.shape[1], _p(b2), _p(x)))
+    return x[:, 0] if flat else x
+
+
+def sor(A: CSR, b, x0, omega: float = 1.0, sweeps: int = 1, symmetric: bool = False) -> np.ndarray:
+    """SOR sweeps in the elementwise textbook form (Gauss-Seidel for
+    omega = 1; the smoothers Section 1 names): row by row, in place,
+    x_i <- (1 - omega) x_i + omega (b_i - sum_{j != i} a_ij x_j) / a_ii;
+    forward rows 0..n-1, then (symmetric) rows n-1..0.  Returns the new x."""
+    b2, flat = _as2d(b)
+    b2 = np.ascontiguousarray(b2, dtype=np.float64)
+    x = np.ascontiguousarray(np.array(_as2d(x0)[0], dtype=np.float64))
+    rp, ci = _csr_args(A)
+    v = np.ascontiguousarray(A.val, dtype=np.float64)
+    _check(_L().orc_sor(A.n, _p(rp), _p(ci), _p(v), float(omega), b2.shape[1], _p(b2), _p(x), int(sweeps),
+                        int(bool(symmetric))))
     return x[:, 0] if flat else x
 
 

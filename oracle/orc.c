@@ -204,6 +204,51 @@ void orc_spmv(int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
 }
 
 /* ------------------------------------------------------------------------ */
+/* SOR sweeps (the Gauss-Seidel smoothers Section 1 lists among the users of  */
+/* triangular solves), elementwise textbook form: row by row,                 */
+/*   x_i <- (1 - omega) x_i + omega (b_i - sum_{j != i} a_ij x_j) / a_ii,     */
+/* in place, so rows before i already hold their new values.  A forward sweep */
+/* runs i = 0..n-1; a symmetric sweep follows it with i = n-1..0.             */
+/* ------------------------------------------------------------------------ */
+
+static int sor_row(int32_t i, const int32_t *rp, const int32_t *ci, const double *v, double omega,
+                   int32_t nrhs, const double *b, double *x)
+{
+    double d = 0.0;
+    int have_d = 0;
+    for (int32_t p = rp[i]; p < rp[i + 1]; ++p)
+        if (ci[p] == i) { d = v[p]; have_d = 1; }
+    if (!have_d) return -2;
+    if (d == 0.0) return -3;
+    for (int32_t r = 0; r < nrhs; ++r) {
+        double sigma = 0.0;
+        for (int32_t p = rp[i]; p < rp[i + 1]; ++p)
+            if (ci[p] != i) sigma = sigma + v[p] * x[(int64_t)ci[p] * nrhs + r];
+        const double xi = x[(int64_t)i * nrhs + r];
+        x[(int64_t)i * nrhs + r] = (1.0 - omega) * xi + omega * (b[(int64_t)i * nrhs + r] - sigma) / d;
+    }
+    return 0;
+}
+
+int orc_sor(int32_t n, const int32_t *rp, const int32_t *ci, const double *v, double omega, int32_t nrhs,
+            const double *b, double *x, int32_t sweeps, int symmetric)
+{
+    if (nrhs < 1 || sweeps < 0) return -5;
+    for (int32_t k = 0; k < sweeps; ++k) {
+        for (int32_t i = 0; i < n; ++i) {
+            int rc = sor_row(i, rp, ci, v, omega, nrhs, b, x);
+            if (rc) return rc;
+        }
+        if (symmetric)
+            for (int32_t i = n - 1; i >= 0; --i) {
+                int rc = sor_row(i, rp, ci, v, omega, nrhs, b, x);
+                if (rc) return rc;
+            }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Incomplete factorizations of Section 3 (Saad's textbook forms).           */
 /* ------------------------------------------------------------------------ */
 

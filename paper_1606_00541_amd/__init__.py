@@ -99,6 +99,9 @@ SIGNATURES = {
     "ras_info": (_i32, [_vp, _P(_i32), _P(_i64), _vp]),
     "ras_plans": (_i32, [_vp, _P(_vp), _P(_vp)]),
     "ras_destroy": (None, [_vp]),
+    "sor_setup": (_i32, [_i32, _vp, _vp, _vp, ctypes.c_double, _P(Tune), _P(_vp)]),
+    "sor_apply": (_i32, [_vp, _vp, _vp, _i32, _i32, _i32, _vp]),
+    "sor_destroy": (None, [_vp]),
     "batch_setup": (_i32, [_i32, _vp, _vp, _vp, _i32, _vp, _i32, _i32, _f64, _i32, _i32, _P(Tune), _P(_vp)]),
     "krylov_solve": (_i32, [_vp, Precond, _i32, _i32, _vp, _vp, _i32, _f64, _i32, _vp, _vp]),
     "krylov_solve_batch": (_i32, [_vp, Precond, _i32, _i32, _i32, _vp, _vp, _vp, _i32, _f64, _i32, _vp, _vp]),
@@ -215,6 +218,10 @@ class Ilu(_Handle):
 
 class Ras(_Handle):
     _destroy = "ras_destroy"
+
+
+class Sor(_Handle):
+    _destroy = "sor_destroy"
 
 
 class Graph(_Handle):
@@ -420,6 +427,27 @@ def ras_setup_ilu(A, nsub, owner, overlap=0, kind="ilut", k=0, tol=0.0, p=0, fac
     s.n = n
     s.nsub = int(nsub)
     return s
+
+
+def sor_setup(A, omega=1.0, tune: Tune | None = None) -> Sor:
+    """SOR / Gauss-Seidel smoother of A (FP64 plans of D/omega + L and
+    D/omega + U, and the two SpMV operators)."""
+    n, rp, ci, v = _csr(A)
+    out = ctypes.c_void_p()
+    _check(lib().sor_setup(n, _ptr(rp), _ptr(ci), _ptr(v), float(omega),
+                           ctypes.byref(tune) if tune is not None else None, ctypes.byref(out)))
+    s = Sor(out.value)
+    s.n = n
+    return s
+
+
+def sor_apply(s: Sor, b, x, sweeps=1, symmetric=False, stream=None):
+    """`sweeps` SOR sweeps on x in place (forward, or SSOR when symmetric)."""
+    pb, R, db = _vec(b, s.n)
+    px, R2, dx = _vec(x, s.n)
+    if R != R2 or db != HEC_F64 or dx != HEC_F64:
+        raise ValueError("sor_apply takes FP64 b and x of equal shape")
+    _check(lib().sor_apply(s.ptr, pb, px, R, int(sweeps), int(bool(symmetric)), _stream(stream)))
 
 
 def ras_apply(s: Ras, r, z, stream=None):

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <functional>
 #include <memory>
@@ -177,6 +178,15 @@ struct ilu_s {
     tri_plan_s L, U;
     DevMem qmap;                 // U device row -> L device row of the same original row
     std::vector<int32_t> sys_ptr;
+};
+
+struct sor_s {
+    int32_t n = 0;
+    double omega = 1.0;
+    tri_plan_s fwd, bwd;         // D/omega + L (lower), D/omega + U (upper)
+    DevHec nf, nb;               // U + (1 - 1/omega) D, L + (1 - 1/omega) D
+    DevMem t;                    // right-hand side of the current sweep, [n][R]
+    int32_t t_R = 0;
 };
 
 struct ras_s {
@@ -602,6 +612,94 @@ hec_status_t ras_plans(ras_t s, tri_plan_t *L, tri_plan_t *U)
 }
 
 void ras_destroy(ras_t s) { delete s; }
+
+hec_status_t sor_setup(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val, double omega,
+                       const hec_tune_t *tune, sor_t *out)
+{
+    return guard([&] {
+        if (!out) fail(HEC_ERR_INVALID_ARG, "out is NULL");
+        if (!(omega > 0.0 && omega < 2.0)) fail(HEC_ERR_INVALID_ARG, "omega must lie in (0, 2)");
+        Tune tu = tune_from(tune);
+        Csr a = csr_copy(n, rowptr, col, val, HEC_F64);
+        check_csr_structure(a);
+        // split A = D + L + U row by row; entry order inside a row is kept
+        Csr ml, mu, nl, nu;
+        for (Csr *c : {&ml, &mu, &nl, &nu}) {
+            c->n = n;
+            c->rp.assign((size_t)n + 1, 0);
+        }
+        const double shift = 1.0 - 1.0 / omega;
+        for (int32_t i = 0; i < n; ++i) {
+            double d = 0.0;
+            bool have = false;
+            for (int32_t p = a.rp[i]; p < a.rp[i + 1]; ++p)
+                if (a.ci[p] == i) { d = a.v[p]; have = true; }
+            if (!have) fail(HEC_ERR_MISSING_DIAG, "row " + std::to_string(i) + " has no diagonal entry");
+            if (d == 0.0 || !std::isfinite(d)) fail(HEC_ERR_ZERO_PIVOT, "zero or non-finite diagonal in row " + std::to_string(i));
+            for (int32_t p = a.rp[i]; p < a.rp[i + 1]; ++p) {
+                const int32_t j = a.ci[p];
+                const double v = a.v[p];
+                if (j < i) {
+                    ml.ci.push_back(j), ml.v.push_back(v);
+                    nl.ci.push_back(j), nl.v.push_back(v);
+                } else if (j > i) {
+                    mu.ci.push_back(j), mu.v.push_back(v);
+                    nu.ci.push_back(j), nu.v.push_back(v);
+                } else {
+                    ml.ci.push_back(i), ml.v.push_back(d / omega);
+                    mu.ci.push_back(i), mu.v.push_back(d / omega);
+                    if (shift != 0.0) {
+                        nl.ci.push_back(i), nl.v.push_back(shift * d);
+                        nu.ci.push_back(i), nu.v.push_back(shift * d);
+                    }
+                }
+            }
+            for (Csr *c : {&ml, &mu, &nl, &nu}) c->rp[i + 1] = (int32_t)c->ci.size();
+        }
+        auto s = std::make_unique<sor_s>();
+        s->n = n;
+        s->omega = omega;
+        build_plan(s->fwd, ml, false, false, HEC_F64, tu);
+        build_plan(s->bwd, mu, true, false, HEC_F64, tu);
+        if (!tu.host_only) {
+            build_devhec(s->nf, nu, HEC_F64, -1);
+            build_devhec(s->nb, nl, HEC_F64, -1);
+        }
+        *out = s.release();
+    });
+}
+
+hec_status_t sor_apply(sor_t s, const double *b, double *x, int32_t nrhs, int32_t sweeps, int32_t symmetric,
+                       hipStream_t st)
+{
+    return guard([&] {
+        if (!s) fail(HEC_ERR_INVALID_ARG, "sor is NULL");
+        if (nrhs < 1 || sweeps < 0) fail(HEC_ERR_INVALID_ARG, "nrhs must be >= 1 and sweeps >= 0");
+        require_device(s->fwd);
+        if (s->n > 0 && (!b || !x)) fail(HEC_ERR_INVALID_ARG, "vector pointer is NULL");
+        if (b == x && s->n > 0) fail(HEC_ERR_INVALID_ARG, "sor_apply needs distinct b and x");
+        check_device_error(s->fwd.d);
+        check_device_error(s->bwd.d);
+        ensure_workspace(s->fwd.d, nrhs);
+        ensure_workspace(s->bwd.d, nrhs);
+        if (nrhs > s->t_R) {
+            s->t.alloc(((size_t)s->n + 1) * nrhs * sizeof(double));
+            s->t_R = nrhs;
+        }
+        double *t = s->t.as<double>();
+        const int32_t *of = s->fwd.d.orig.as<int32_t>(), *ob = s->bwd.d.orig.as<int32_t>();
+        for (int32_t k = 0; k < sweeps; ++k) {
+            residual(s->nf, b, x, t, nrhs, st);  // t = b - (U + (1 - 1/omega) D) x
+            launch_tri(s->fwd.d, t, HEC_F64, of, s->fwd.d.xw.p, x, HEC_F64, of, nrhs, st);
+            if (symmetric) {
+                residual(s->nb, b, x, t, nrhs, st);  // t = b - (L + (1 - 1/omega) D) x
+                launch_tri(s->bwd.d, t, HEC_F64, ob, s->bwd.d.xw.p, x, HEC_F64, ob, nrhs, st);
+            }
+        }
+    });
+}
+
+void sor_destroy(sor_t s) { delete s; }
 
 hec_status_t hec_graph_capture(hec_precond_t M, const void *r, void *z, int32_t nrhs, hec_dtype_t vdt,
                                hipStream_t st, hec_graph_t *out)

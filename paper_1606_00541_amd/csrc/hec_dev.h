@@ -166,6 +166,8 @@ struct DevHec {   // general HEC matrix for y = A x
     HecHost host;   // host copy (export)
     int64_t tail_nnz = 0;
 };
+// Upload a general matrix as HEC (ELL width -1 = median row length).
+void build_devhec(DevHec &d, const Csr &a, hec_dtype_t dt, int32_t ell_width);
 void spmv(const DevHec &A, const double *x, double *y, int32_t R, hipStream_t st);
 // r = b - A x
 void residual(const DevHec &A, const double *b, const double *x, double *r, int32_t R, hipStream_t st);

@@ -790,6 +790,58 @@ hec_status_t bicgstab(const DevHec &A, const hec_precond_t &M, const double *b, 
 
 }  // namespace
 
+namespace hec {
+
+void build_devhec(DevHec &d, const Csr &a, hec_dtype_t dt, int32_t ell_width)
+{
+    const int32_t n = a.n;
+    d.n = n;
+    d.dt = dt;
+    int32_t w = ell_width;
+    if (w < 0) {
+        std::vector<int32_t> len(n);
+        for (int32_t i = 0; i < n; ++i) len[i] = a.rp[i + 1] - a.rp[i];
+        std::vector<int32_t> srt = len;
+        std::sort(srt.begin(), srt.end());
+        w = n ? srt[(n - 1) / 2] : 0;
+        w = std::min(w, 64);
+    }
+    HecHost &h = d.host;
+    h.n = n;
+    h.w = w;
+    h.ld = (n + 63) / 64 * 64;
+    h.ell_col.assign((size_t)w * h.ld, n);
+    h.ell_val.assign((size_t)w * h.ld, 0.0);
+    h.csr_ptr.assign((size_t)n + 1, 0);
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t e = 0;
+        for (int32_t p = a.rp[i]; p < a.rp[i + 1]; ++p) {
+            if (e < w) {
+                h.ell_col[(size_t)e * h.ld + i] = a.ci[p];
+                h.ell_val[(size_t)e * h.ld + i] = a.v[p];
+                ++e;
+            } else {
+                h.csr_col.push_back(a.ci[p]);
+                h.csr_val.push_back(a.v[p]);
+            }
+        }
+        h.csr_ptr[i + 1] = (int32_t)h.csr_col.size();
+    }
+    d.w = w;
+    d.ld = h.ld;
+    d.tail_nnz = (int64_t)h.csr_col.size();
+    hip_check(hipGetDevice(&d.device), "hipGetDevice");
+    upload(d.ell_col, h.ell_col);
+    upload_values(d.ell_val, h.ell_val, dt);
+    if (d.tail_nnz > 0) {
+        upload(d.tail_ptr, h.csr_ptr);
+        upload(d.tail_col, h.csr_col);
+        upload_values(d.tail_val, h.csr_val, dt);
+    }
+}
+
+}  // namespace hec
+
 extern "C" {
 
 hec_status_t hec_from_csr(int32_t n, const int32_t *rowptr, const int32_t *col, const void *val, hec_dtype_t dt,
@@ -800,50 +852,7 @@ hec_status_t hec_from_csr(int32_t n, const int32_t *rowptr, const int32_t *col, 
             if (ell_width < -1 || ell_width > 64) fail(HEC_ERR_INVALID_ARG, "ell_width out of range");
             Csr a = csr_copy(n, rowptr, col, val, dt);
             auto m = std::make_unique<hec_matrix_s>();
-            DevHec &d = m->d;
-            d.n = n;
-            d.dt = dt;
-            int32_t w = ell_width;
-            if (w < 0) {
-                std::vector<int32_t> len(n);
-                for (int32_t i = 0; i < n; ++i) len[i] = a.rp[i + 1] - a.rp[i];
-                std::vector<int32_t> srt = len;
-                std::sort(srt.begin(), srt.end());
-                w = n ? srt[(n - 1) / 2] : 0;
-                w = std::min(w, 64);
-            }
-            HecHost &h = d.host;
-            h.n = n;
-            h.w = w;
-            h.ld = (n + 63) / 64 * 64;
-            h.ell_col.assign((size_t)w * h.ld, n);
-            h.ell_val.assign((size_t)w * h.ld, 0.0);
-            h.csr_ptr.assign((size_t)n + 1, 0);
-            for (int32_t i = 0; i < n; ++i) {
-                int32_t e = 0;
-                for (int32_t p = a.rp[i]; p < a.rp[i + 1]; ++p) {
-                    if (e < w) {
-                        h.ell_col[(size_t)e * h.ld + i] = a.ci[p];
-                        h.ell_val[(size_t)e * h.ld + i] = a.v[p];
-                        ++e;
-                    } else {
-                        h.csr_col.push_back(a.ci[p]);
-                        h.csr_val.push_back(a.v[p]);
-                    }
-                }
-                h.csr_ptr[i + 1] = (int32_t)h.csr_col.size();
-            }
-            d.w = w;
-            d.ld = h.ld;
-            d.tail_nnz = (int64_t)h.csr_col.size();
-            hip_check(hipGetDevice(&d.device), "hipGetDevice");
-            upload(d.ell_col, h.ell_col);
-            upload_values(d.ell_val, h.ell_val, dt);
-            if (d.tail_nnz > 0) {
-                upload(d.tail_ptr, h.csr_ptr);
-                upload(d.tail_col, h.csr_col);
-                upload_values(d.tail_val, h.csr_val, dt);
-            }
+            build_devhec(m->d, a, dt, ell_width);
             *out = m.release();
             return HEC_OK;
     });

@@ -211,6 +211,32 @@ def test_block_ilu_layout_and_errors():
     assert H.STATUS_NAMES[rc] == "INVALID_ARG"
 
 
+
+def test_sor_setup_validation():
+    A = synth.diffusion2d(6, 5, 1.0, seed=2)
+    s = H.sor_setup(A, 1.2, tune=HOST)
+    with pytest.raises(H.HecError) as e:  # host-only setup has no device plans
+        H._check(H.lib().sor_apply(s.ptr, None, None, 1, 1, 0, None))
+    assert e.value.name == "NO_DEVICE"
+    for om in (0.0, 2.0, -1.0):
+        with pytest.raises(H.HecError) as e:
+            H.sor_setup(A, om, tune=HOST)
+        assert e.value.name == "INVALID_ARG"
+    v = A.val.copy()
+    diag = A.col == np.repeat(np.arange(A.n), np.diff(A.rowptr))
+    v[np.flatnonzero(diag)[3]] = 0.0
+    with pytest.raises(H.HecError) as e:
+        H.sor_setup(CSR(A.n, A.rowptr, A.col, v), 1.0, tune=HOST)
+    assert e.value.name == "ZERO_PIVOT"
+    keep = ~(diag & (np.repeat(np.arange(A.n), np.diff(A.rowptr)) == 4))
+    rows = np.repeat(np.arange(A.n), np.diff(A.rowptr))[keep]
+    rp = np.zeros(A.n + 1, np.int32)
+    np.cumsum(np.bincount(rows, minlength=A.n), out=rp[1:])
+    with pytest.raises(H.HecError) as e:
+        H.sor_setup(CSR(A.n, rp, A.col[keep], A.val[keep]), 1.0, tune=HOST)
+    assert e.value.name == "MISSING_DIAG"
+
+
 def test_auto_tuning_picks_the_dataflow_kernel_when_it_fits():
     A = synth.poisson3d(12)
     L, _ = oracle.ilu0(A)
