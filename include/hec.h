@@ -254,6 +254,24 @@ hec_status_t ilu_plans(ilu_t ilu, tri_plan_t *L, tri_plan_t *U);
 hec_status_t ilu_apply(ilu_t ilu, const void *r, void *z, int32_t nrhs, hec_dtype_t vec_dt,
                        hipStream_t stream);
 void ilu_destroy(ilu_t ilu);
+/* Numeric refactorization on the device (Section 3's ILU(0) / ILU(k), computed
+ * over the level sets of eq. (2): the rows of one level of L are independent).
+ * For a handle from ilu_setup or batch_setup with kind HEC_ILU0 or HEC_ILUK:
+ * new values `val` (device FP64 [nnz], in the order of rowptr/col) of a matrix
+ * whose pattern (host rowptr[n+1], col[nnz], sorted rows) lies inside the
+ * factor pattern built at setup (A's own pattern qualifies) are factored on
+ * the device and written into both plans in place; the factors equal those a
+ * new setup would compute, bit for bit.  The first call for a pattern builds
+ * its device maps (host work); later calls with the same pattern reuse them,
+ * and rowptr = col = NULL names the previous call's pattern without comparing.
+ * Runs on `stream` and synchronizes it (to report a zero pivot; the plans are
+ * then left unchanged).  Solves on other streams must be ordered by the caller.
+ * ilu_factor returns the refactored values afterwards.
+ * Errors: INVALID_ARG (ILUT handle, NULL arrays, no earlier pattern, an entry
+ * outside the factor pattern), ZERO_PIVOT, CAPACITY (a factor row longer than 1024 entries),
+ * NO_DEVICE for a host-only setup. */
+hec_status_t ilu_refactor(ilu_t ilu, const int32_t *rowptr, const int32_t *col, const double *val,
+                          hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Restricted Additive Schwarz (Section 3, eq. (4)): subdomain s owns the rows

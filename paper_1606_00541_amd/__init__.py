@@ -92,6 +92,7 @@ SIGNATURES = {
     "ilu_plans": (_i32, [_vp, _P(_vp), _P(_vp)]),
     "ilu_apply": (_i32, [_vp, _vp, _vp, _i32, _i32, _vp]),
     "ilu_destroy": (None, [_vp]),
+    "ilu_refactor": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "ras_setup": (_i32, [_i32, _vp, _vp, _vp, _i32, _vp, _i32, _i32, _P(Tune), _P(_vp)]),
     "ras_setup_ilu": (_i32, [_i32, _vp, _vp, _vp, _i32, _vp, _i32, _i32, _i32, ctypes.c_double, _i32, _i32,
                              _P(Tune), _P(_vp)]),
@@ -391,6 +392,30 @@ def ilu_plans(f: Ilu):
     pl, pu = _BorrowedPlan(L.value, keep=f), _BorrowedPlan(U.value, keep=f)
     pl.n = pu.n = f.n
     return pl, pu
+
+
+def ilu_refactor(f: Ilu, A=None, val=None, stream=None):
+    """Refactor on the device with new values of A (pattern inside the
+    setup's factor pattern).  ``val``: device FP64 tensor of A's values in CSR
+    order (default: A's host values, copied to the device).  With A None the
+    previous call's pattern is reused and ``val`` is required."""
+    import torch
+
+    if A is None:
+        if val is None:
+            raise ValueError("val is required when A is None")
+        rp = ci = None
+    else:
+        n, rp, ci, v = _csr(A)
+        if val is None:
+            val = torch.from_numpy(np.ascontiguousarray(v, dtype=np.float64)).cuda()
+        if val.numel() != ci.shape[0]:
+            raise ValueError("val must hold nnz(A) values")
+    if val.dtype != torch.float64 or not val.is_cuda:
+        raise ValueError("val must be a device FP64 tensor")
+    val = val.contiguous()
+    _check(lib().ilu_refactor(f.ptr, _ptr(rp) if rp is not None else None, _ptr(ci) if ci is not None else None,
+                              ctypes.c_void_p(val.data_ptr()), _stream(stream)))
 
 
 def ilu_apply(f: Ilu, r, z, stream=None):

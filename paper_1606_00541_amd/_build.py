@@ -20,7 +20,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
 HOST_SRCS = ["analysis.cpp", "factor.cpp"]
-HIP_SRCS = ["tri_kernels.hip", "krylov.hip", "capi.hip"]
+HIP_SRCS = ["tri_kernels.hip", "krylov.hip", "refactor.hip", "capi.hip"]
 HEADERS = ["hec_host.h", "hec_dev.h"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]

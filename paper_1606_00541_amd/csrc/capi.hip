@@ -178,6 +178,9 @@ struct ilu_s {
     tri_plan_s L, U;
     DevMem qmap;                 // U device row -> L device row of the same original row
     std::vector<int32_t> sys_ptr;
+    hec_ilu_kind_t kind = HEC_ILU0;
+    std::unique_ptr<DevRefactor> rf;  // device refactorization data (built on first use)
+    bool dev_newer = false;      // the device factors are newer than Lf, Uf
 };
 
 struct sor_s {
@@ -321,6 +324,108 @@ void ilu_apply_impl(ilu_s *f, const void *r, void *z, int32_t nrhs, hec_dtype_t 
     launch_tri(f->L.d, r, vdt, f->L.d.orig.as<int32_t>(), f->L.d.xw.p, nullptr, vdt, nullptr, nrhs, st);
     launch_tri(f->U.d, f->L.d.xw.p, f->fdt, f->qmap.as<int32_t>(), f->U.d.xw.p, z, vdt,
                f->U.d.orig.as<int32_t>(), nrhs, st);
+}
+
+// Device refactorization data of an ILU(0)/ILU(k) handle for A's pattern
+// (rowptr, col): the combined factor pattern F, A's entries in F, rows in
+// L's level order, and where each factor entry lives in the two plans.
+void build_refactor(ilu_s &f, const int32_t *rowptr, const int32_t *col)
+{
+    const int32_t n = f.n;
+    auto r = std::make_unique<DevRefactor>();
+    r->n = n;
+    std::vector<int32_t> frp((size_t)n + 1, 0), fci, fdpos(n);
+    fci.reserve((size_t)(f.Lf.nnz() + f.Uf.nnz()));
+    int32_t maxrow = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        for (int32_t p = f.Lf.rp[i]; p < f.Lf.rp[i + 1]; ++p)
+            if (f.Lf.ci[p] < i) fci.push_back(f.Lf.ci[p]);
+        fdpos[i] = (int32_t)fci.size();
+        for (int32_t p = f.Uf.rp[i]; p < f.Uf.rp[i + 1]; ++p) fci.push_back(f.Uf.ci[p]);
+        frp[i + 1] = (int32_t)fci.size();
+        maxrow = std::max(maxrow, frp[i + 1] - frp[i]);
+    }
+    if (maxrow > kRefactorMaxRow)
+        fail(HEC_ERR_CAPACITY, "a factor row has " + std::to_string(maxrow) + " entries; the device refactorization "
+             "stages at most " + std::to_string(kRefactorMaxRow));
+    // A's entries inside F's pattern
+    if (rowptr[0] != 0) fail(HEC_ERR_INVALID_ARG, "rowptr[0] must be 0");
+    const int64_t nnz_a = rowptr[n];
+    std::vector<int32_t> a2f((size_t)nnz_a);
+    for (int32_t i = 0; i < n; ++i) {
+        if (rowptr[i + 1] < rowptr[i]) fail(HEC_ERR_INVALID_ARG, "rowptr is not monotone");
+        auto b = fci.begin() + frp[i], e = fci.begin() + frp[i + 1];
+        for (int32_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            auto it = std::lower_bound(b, e, col[p]);
+            if (it == e || *it != col[p])
+                fail(HEC_ERR_INVALID_ARG, "entry (" + std::to_string(i) + ", " + std::to_string(col[p]) +
+                     ") of A is not in the factor pattern built at setup");
+            a2f[p] = (int32_t)(it - fci.begin());
+        }
+    }
+    // plan positions: the off-diagonals of a row keep their order in both layouts
+    auto place = [](const ExecHost &ex, int32_t x, int32_t e) {
+        return e < ex.w ? e * ex.ld + x : -1 - (ex.tail_ptr[x] + (e - ex.w));
+    };
+    std::vector<int32_t> l_src, l_dst, u_src, u_dst, u_diag, d_src(n);
+    const ExecHost &el = f.L.h.ex, &eu = f.U.h.ex;
+    for (int32_t x = 0; x < n; ++x) {
+        const int32_t i = el.orig[x];
+        int32_t e = 0;
+        for (int32_t p = frp[i]; p < fdpos[i]; ++p, ++e) {
+            l_src.push_back(p);
+            l_dst.push_back(place(el, x, e));
+        }
+    }
+    for (int32_t x = 0; x < n; ++x) {
+        const int32_t i = eu.orig[x];
+        int32_t e = 0;
+        d_src[x] = fdpos[i];
+        for (int32_t p = fdpos[i] + 1; p < frp[i + 1]; ++p, ++e) {
+            u_src.push_back(p);
+            u_dst.push_back(place(eu, x, e));
+            u_diag.push_back(fdpos[i]);
+        }
+    }
+    const Levels &lv = f.L.h.lev;
+    r->levelptr = lv.levelptr;
+    r->nnz_a = nnz_a;
+    r->nnz_f = (int64_t)fci.size();
+    r->nl = (int64_t)l_src.size();
+    r->nu = (int64_t)u_src.size();
+    r->a_rp.assign(rowptr, rowptr + n + 1);
+    r->a_ci.assign(col, col + nnz_a);
+    upload(r->a2f, a2f);
+    upload(r->frp, frp);
+    upload(r->fci, fci);
+    upload(r->fdpos, fdpos);
+    upload(r->rows, lv.perm);
+    upload(r->l_src, l_src);
+    upload(r->l_dst, l_dst);
+    upload(r->u_src, u_src);
+    upload(r->u_dst, u_dst);
+    upload(r->u_diag, u_diag);
+    upload(r->d_src, d_src);
+    r->fval.alloc(std::max<size_t>(1, fci.size()) * sizeof(double));
+    r->err.alloc(sizeof(int));
+    f.rf = std::move(r);
+}
+
+// Copy the device factors back into Lf and Uf after a device refactorization.
+void sync_host_factors(ilu_s &f)
+{
+    if (!f.dev_newer || !f.rf) return;
+    const DevRefactor &r = *f.rf;
+    std::vector<double> fv((size_t)r.nnz_f);
+    if (r.nnz_f > 0)
+        hip_check(hipMemcpy(fv.data(), r.fval.p, fv.size() * sizeof(double), hipMemcpyDeviceToHost), "factor download");
+    int64_t q = 0;
+    for (int32_t i = 0; i < f.n; ++i) {
+        for (int32_t p = f.Lf.rp[i]; p < f.Lf.rp[i + 1]; ++p)
+            if (f.Lf.ci[p] < i) f.Lf.v[p] = fv[q++];
+        for (int32_t p = f.Uf.rp[i]; p < f.Uf.rp[i + 1]; ++p) f.Uf.v[p] = fv[q++];
+    }
+    f.dev_newer = false;
 }
 
 void ras_apply_impl(ras_s *s, const double *r, double *z, int32_t nrhs, hipStream_t st)
@@ -489,6 +594,7 @@ hec_status_t ilu_setup(int32_t n, const int32_t *rowptr, const int32_t *col, con
         Csr a = csr_copy(n, rowptr, col, val, HEC_F64);
         auto f = std::make_unique<ilu_s>();
         factor(a, kind, k, tol, p, f->Lf, f->Uf);
+        f->kind = kind;
         build_ilu(*f, f->Lf, f->Uf, fdt, tu);
         *out = f.release();
     });
@@ -515,6 +621,7 @@ hec_status_t batch_setup(int32_t n, const int32_t *rowptr, const int32_t *col, c
         auto f = std::make_unique<ilu_s>();
         f->sys_ptr.assign(sys_ptr, sys_ptr + nsys + 1);
         factor(a, kind, k, tol, p, f->Lf, f->Uf, &f->sys_ptr);
+        f->kind = kind;
         build_ilu(*f, f->Lf, f->Uf, fdt, tu);
         *out = f.release();
     });
@@ -524,6 +631,7 @@ hec_status_t ilu_factor(ilu_t f, int32_t which, int64_t *nnz, int32_t *rowptr, i
 {
     return guard([&] {
         if (!f || (which != 0 && which != 1)) fail(HEC_ERR_INVALID_ARG, "bad arguments");
+        sync_host_factors(*f);
         const Csr &c = which == 0 ? f->Lf : f->Uf;
         if (nnz) *nnz = c.nnz();
         if (rowptr) std::copy(c.rp.begin(), c.rp.end(), rowptr);
@@ -547,6 +655,32 @@ hec_status_t ilu_apply(ilu_t f, const void *r, void *z, int32_t nrhs, hec_dtype_
 }
 
 void ilu_destroy(ilu_t f) { delete f; }
+
+hec_status_t ilu_refactor(ilu_t f, const int32_t *rowptr, const int32_t *col, const double *val, hipStream_t st)
+{
+    return guard([&] {
+        if (!f) fail(HEC_ERR_INVALID_ARG, "ilu is NULL");
+        if (f->kind == HEC_ILUT) fail(HEC_ERR_INVALID_ARG, "ILUT's pattern depends on the values; refactor needs ILU(0) or ILU(k)");
+        require_device(f->L);
+        const int32_t n = f->n;
+        if (!rowptr && !col) {
+            if (!f->rf) fail(HEC_ERR_INVALID_ARG, "no pattern given and none from an earlier call");
+        } else {
+            if (!rowptr || (!col && rowptr[n] > 0)) fail(HEC_ERR_INVALID_ARG, "rowptr or col is NULL");
+            const bool same = f->rf && f->rf->a_rp.size() == (size_t)n + 1 &&
+                              std::equal(f->rf->a_rp.begin(), f->rf->a_rp.end(), rowptr) &&
+                              (int64_t)f->rf->a_ci.size() == (int64_t)rowptr[n] &&
+                              std::equal(f->rf->a_ci.begin(), f->rf->a_ci.end(), col);
+            if (!same) build_refactor(*f, rowptr, col);
+        }
+        if (f->rf->nnz_a > 0 && !val) fail(HEC_ERR_INVALID_ARG, "val is NULL");
+        check_device_error(f->L.d);
+        check_device_error(f->U.d);
+        refactor_numeric(*f->rf, val, st);
+        refactor_refill(*f->rf, f->L.d, f->U.d, st);
+        f->dev_newer = true;
+    });
+}
 
 hec_status_t ras_setup(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val, int32_t nsub,
                        const int32_t *owner, int32_t overlap, hec_dtype_t fdt, const hec_tune_t *tune, ras_t *out)

@@ -140,6 +140,27 @@ struct DevTri {
     ~DevTri();
 };
 
+// Device numeric refactorization of an ILU(0)/ILU(k) factor over its fixed
+// pattern: F = L\U in CSR (sorted rows, diagonal present), A's entries mapped
+// into it, rows in level order of L, and the positions of every factor
+// entry in the two plans' execution layouts (ELL index e*ld + row, or
+// -1 - tail index).
+constexpr int kRefactorMaxRow = 1024;   // longest factor row (LDS staging)
+struct DevRefactor {
+    int32_t n = 0;
+    int64_t nnz_a = 0, nnz_f = 0, nl = 0, nu = 0;
+    std::vector<int32_t> a_rp, a_ci;      // pattern of A the map was built for
+    std::vector<int32_t> levelptr;        // levels of L (host bounds into rows)
+    DevMem a2f, frp, fci, fdpos, fval, rows, err;
+    DevMem l_src, l_dst, u_src, u_dst, u_diag, d_src;
+};
+// Scatter A's device values into F and eliminate level by level; synchronizes
+// `st` and throws ZERO_PIVOT on a zero or non-finite pivot.
+void refactor_numeric(DevRefactor &r, const double *aval, hipStream_t st);
+// Write F's values into the plans (L as is, U scaled by its reciprocal
+// diagonal, U's reciprocal diagonal array).
+void refactor_refill(const DevRefactor &r, DevTri &L, DevTri &U, hipStream_t st);
+
 // Fill `count` values of type dt with the mailbox sentinel (synchronous).
 void fill_sentinel(void *p, size_t count, hec_dtype_t dt);
 void upload_tri(DevTri &d, const TriHost &t, int32_t max_nrhs);

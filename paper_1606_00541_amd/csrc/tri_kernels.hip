@@ -46,8 +46,16 @@ __device__ __forceinline__ bool is_sentinel(float v) { return __float_as_uint(v)
 
 // Right-hand side times the reciprocal diagonal, rounded on its own (never
 // contracted into the first multiply-add), identically in every kernel.
-__device__ __forceinline__ double scale_rhs(double b, double d) { return __dmul_rn(b, d); }
-__device__ __forceinline__ float scale_rhs(float b, float d) { return __fmul_rn(b, d); }
+__device__ __forceinline__ double scale_rhs(double b, double d)
+{
+#pragma clang fp contract(off)
+    return b * d;
+}
+__device__ __forceinline__ float scale_rhs(float b, float d)
+{
+#pragma clang fp contract(off)
+    return b * d;
+}
 
 // Per-launch state of the persistent kernel shared by the row routine.
 template <typename T> struct Ctx {

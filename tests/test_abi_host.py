@@ -212,6 +212,16 @@ def test_block_ilu_layout_and_errors():
 
 
 
+
+def test_refactor_needs_a_device_and_a_fixed_pattern_kind():
+    A = synth.poisson2d(6)
+    n, rp, ci, v = H._csr(A)
+    for kind, code in (("ilu0", "NO_DEVICE"), ("ilut", "INVALID_ARG")):
+        f = H.ilu_setup(A, kind, p=4, tol=1e-2, tune=HOST)
+        rc = H.lib().ilu_refactor(f.ptr, H._ptr(rp), H._ptr(ci), None, None)
+        assert H.STATUS_NAMES[rc] == code
+
+
 def test_sor_setup_validation():
     A = synth.diffusion2d(6, 5, 1.0, seed=2)
     s = H.sor_setup(A, 1.2, tune=HOST)

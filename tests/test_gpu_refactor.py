@@ -1,0 +1,123 @@
+"""GPU numeric refactorization (Section 3's ILU(0) / ILU(k) over the level
+sets of eq. (2)): new values of a matrix with the setup's pattern, factored on
+the device and written into the plans in place, give the oracle's factors and
+the same solves as a new setup, bit for bit."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth import CSR
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1606_00541_amd as H  # noqa: E402
+
+
+def tune(sched, **kw):
+    if sched == "owner_dataflow":
+        return H.tune_default(schedule="owner_persistent", kernel_variant=4, **kw)
+    if sched == "owner_persistent":
+        return H.tune_default(schedule=sched, kernel_variant=2, **kw)
+    return H.tune_default(schedule=sched, **kw)
+
+
+def apply(f, r):
+    rt = torch.from_numpy(np.ascontiguousarray(r)).cuda()
+    zt = torch.empty_like(rt)
+    H.ilu_apply(f, rt, zt)
+    return zt.cpu().numpy()
+
+
+def factors(f):
+    return [H.ilu_factor(f, w) for w in (0, 1)]
+
+
+def same_factors(fa, ref):
+    for (rp, ci, v), T in zip(fa, ref):
+        assert np.array_equal(rp, T.rowptr) and np.array_equal(ci, T.col) and np.array_equal(v, T.val)
+
+
+@pytest.mark.parametrize("sched", ["auto", "level_launch", "level_persistent", "owner_persistent", "owner_dataflow"])
+@pytest.mark.parametrize("fdt", ["f64", "f32"])
+def test_ilu0_refactor_equals_new_setup(sched, fdt):
+    A1 = synth.diffusion3d(14, 13, 11, 1.0, seed=41)
+    A2 = synth.diffusion3d(14, 13, 11, 2.0, seed=42)  # same pattern, other values
+    t = tune(sched, max_nrhs=2) if sched != "auto" else H.tune_default(max_nrhs=2)
+    f = H.ilu_setup(A1, "ilu0", factor_dtype=fdt, tune=t)
+    H.ilu_refactor(f, A2)
+    same_factors(factors(f), oracle.ilu0(A2))
+    g = H.ilu_setup(A2, "ilu0", factor_dtype=fdt, tune=t)
+    r = synth.rhs(A2.n, 2, 43)
+    assert np.array_equal(apply(f, r), apply(g, r))
+
+
+@pytest.mark.parametrize("k,width", [(1, -1), (2, -1), (1, 2)])
+def test_iluk_refactor_with_fill_and_tails(k, width):
+    # width 2 leaves most factor entries in the CSR tails of a level-launch plan
+    A1 = synth.diffusion3d(12, 11, 10, 1.0, seed=44)
+    A2 = synth.diffusion3d(12, 11, 10, 1.5, seed=45)
+    t = H.tune_default(schedule="level_launch", ell_width=width) if width > 0 else H.tune_default()
+    f = H.ilu_setup(A1, "iluk", k=k, tune=t)
+    H.ilu_refactor(f, A2)
+    same_factors(factors(f), oracle.iluk(A2, k))
+    g = H.ilu_setup(A2, "iluk", k=k, tune=t)
+    r = synth.rhs(A2.n, 1, 46)
+    assert np.array_equal(apply(f, r), apply(g, r))
+
+
+def test_batch_refactor_and_repeat():
+    mats1 = [synth.diffusion2d(20, 17, 1.0, seed=47), synth.diffusion3d(9, 8, 7, 1.0, seed=48)]
+    mats2 = [synth.diffusion2d(20, 17, 2.0, seed=49), synth.diffusion3d(9, 8, 7, 2.0, seed=50)]
+
+    def block_diag(mats):
+        import scipy.sparse as sp
+        m = sp.block_diag([M.to_scipy() for M in mats]).tocsr()
+        m.sort_indices()
+        ptr = np.cumsum([0] + [M.n for M in mats]).astype(np.int32)
+        return CSR(m.shape[0], m.indptr.astype(np.int32), m.indices.astype(np.int32), m.data.copy()), ptr
+
+    A1, sp1 = block_diag(mats1)
+    A2, _ = block_diag(mats2)
+    f = H.batch_setup(A1, sp1, "iluk", k=1, tune=H.tune_default(max_nrhs=3))
+    g = H.batch_setup(A2, sp1, "iluk", k=1, tune=H.tune_default(max_nrhs=3))
+    r = synth.rhs(A1.n, 3, 51)
+    before = apply(f, r)
+    H.ilu_refactor(f, A2)
+    assert np.array_equal(apply(f, r), apply(g, r))
+    # the previous pattern, named without arrays, with values already on the device
+    H.ilu_refactor(f, None, val=torch.from_numpy(A2.val.copy()).cuda())
+    assert np.array_equal(apply(f, r), apply(g, r))
+    H.ilu_refactor(f, A1)
+    assert np.array_equal(apply(f, r), before)
+
+
+def test_refactor_zero_pivot_leaves_the_plans():
+    A = synth.poisson2d(9)
+    f = H.ilu_setup(A, "ilu0")
+    r = synth.rhs(A.n, 1, 52)
+    before = apply(f, r)
+    v = A.val.copy()
+    v[0] = 0.0  # a_00 = 0: the first pivot vanishes
+    with pytest.raises(H.HecError) as e:
+        H.ilu_refactor(f, CSR(A.n, A.rowptr, A.col, v))
+    assert e.value.name == "ZERO_PIVOT"
+    assert np.array_equal(apply(f, r), before)
+
+
+def test_refactor_rejects_ilut_and_foreign_patterns():
+    A = synth.poisson2d(8)
+    f = H.ilu_setup(A, "ilut", p=5, tol=1e-2)
+    with pytest.raises(H.HecError) as e:
+        H.ilu_refactor(f, A)
+    assert e.value.name == "INVALID_ARG"
+    g = H.ilu_setup(A, "ilu0")
+    B = synth.poisson2d(8)
+    Bs = B.to_scipy().tolil()
+    Bs[0, 20] = -0.1  # an entry outside ILU(0)'s pattern
+    Bs = Bs.tocsr()
+    Bs.sort_indices()
+    with pytest.raises(H.HecError) as e:
+        H.ilu_refactor(g, CSR(64, Bs.indptr.astype(np.int32), Bs.indices.astype(np.int32), Bs.data.copy()))
+    assert e.value.name == "INVALID_ARG"
