@@ -244,7 +244,7 @@ def run_config(cfg, args):
                                            "rows), overlap 1, ILU(0) per subdomain, 16 RHS; BiCGSTAB to 1e-10",
                                "extended_rows": int(tot), "nlev_L": stl["nlev"], "nlev_U": stu["nlev"],
                                "setup_s": round(setup, 3), "dataflow": stl["dataflow"],
-                               "workgroups": stl["num_groups"]},
+                               "syncfree": stl["syncfree"], "workgroups": stl["num_groups"]},
                     "solves_per_s": round(1000.0 * R / ms, 2), "bicgstab": kr})
     elif cfg == 5:
         _log("config 5: generating systems")
@@ -277,7 +277,7 @@ def run_config(cfg, args):
             x, kr = (None, None) if args.no_krylov else _krylov_batch(H, torch, f, Aop, sys_ptr, b, "fgmres")
             res[fdt] = {"apply_ms": round(ms, 4), "apply_GBps": round(B / (ms * 1e-3) / 1e9, 3),
                         "nlev_L": stl["nlev"], "nlev_U": stu["nlev"], "setup_s": round(setup, 3), "fgmres": kr,
-                        "dataflow": stl["dataflow"], "workgroups": stl["num_groups"],
+                        "dataflow": stl["dataflow"], "syncfree": stl["syncfree"], "workgroups": stl["num_groups"],
                         "systems_per_s": None if kr is None else round(len(mats) * R / kr["seconds"], 3)}
         out.update({"value": res["f32"]["apply_GBps"], "dtype": "f32 factors, f64 refinement",
                     "ms_per_step": res["f32"]["apply_ms"],
@@ -497,7 +497,10 @@ def main(argv=None):
     # dominant kernel: the triangular-solve kernel; L and U launches share it
     bl = per_launch_bytes(n, stl["nnz_offdiag"], 1, diag=False)
     bu = per_launch_bytes(n, stu["nnz_offdiag"], 1, diag=True)
-    if args.schedule == "level_launch":
+    if stl["syncfree"] and stu["syncfree"]:
+        kname, tag = "k_syncfree", "syncfree"
+        launches = 2
+    elif stl["schedule"] == 1:
         kname, tag = "k_level", "launch"
         launches = stl["nlev"] + stu["nlev"]
     elif stl["dataflow"] and stu["dataflow"]:

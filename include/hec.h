@@ -107,7 +107,13 @@ typedef struct hec_tune {
                                inputs; block_threads sets its compute wavefronts (at most 640,
                                384 above ELL width 8); ELL width 1..8, 10, 12 or 16 (others round
                                up; the automatic width covers the longest row, up to 16);
-                               max_nrhs at most 64 */
+                               max_nrhs at most 64; 5 = barrier-free kernel over the
+                               level-ordered layout in global memory (schedule AUTO or
+                               LEVEL_LAUNCH): one launch, each (row, rhs) waits only for its
+                               own inputs, for solutions too large for LDS.  Schedule AUTO
+                               picks it when the dataflow kernel does not fit and the levels
+                               are narrow (fewer than 2^20 (row, rhs) items per level on
+                               average), else one launch per level */
 } hec_tune_t;
 
 /* Per-RHS outcome of krylov_solve. */
@@ -129,6 +135,7 @@ typedef struct tri_stats {
     int32_t unit_diag, dtype;
     int32_t crit_hops;       /* most workgroup-to-workgroup handoffs along one dependency chain */
     int32_t dataflow;        /* 1 when the plan runs on the dataflow owner kernel */
+    int32_t syncfree;        /* 1 when the plan runs on the barrier-free global-memory kernel */
 } tri_stats_t;
 
 typedef struct hec_matrix_s *hec_matrix_t;

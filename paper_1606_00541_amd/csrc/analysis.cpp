@@ -41,7 +41,9 @@ Tune tune_from(const hec_tune_t *t)
     u.chunk_rows = t->chunk_rows > 0 ? t->chunk_rows : std::max(256, u.block_threads);
     u.partition = t->partition;
     u.variant = t->kernel_variant;
-    if (u.variant < 0 || u.variant > 4) fail(HEC_ERR_INVALID_ARG, "tune.kernel_variant out of range");
+    if (u.variant < 0 || u.variant > 5) fail(HEC_ERR_INVALID_ARG, "tune.kernel_variant out of range");
+    if (u.variant == 5 && u.schedule != HEC_SCHED_AUTO && u.schedule != HEC_SCHED_LEVEL_LAUNCH)
+        fail(HEC_ERR_INVALID_ARG, "kernel_variant 5 runs the level-ordered layout (schedule AUTO or LEVEL_LAUNCH)");
     if (u.partition < 0 || u.partition > 3) fail(HEC_ERR_INVALID_ARG, "tune.partition out of range");
     if (u.schedule < HEC_SCHED_AUTO || u.schedule > HEC_SCHED_OWNER_PERSISTENT)
         fail(HEC_ERR_INVALID_ARG, "tune.schedule out of range");
@@ -953,6 +955,12 @@ TriHost analyze(const Csr &a, bool upper, bool unit, hec_dtype_t dt, const Tune 
     // GPU busy without any cross-workgroup waits.  An explicit owner
     // schedule without a kernel choice falls back to the LDS-chunked kernel.
     Tune tu = tune;
+    t.variant = tu.variant;
+    if (tu.variant == 5) {  // the barrier-free kernel over the level-ordered layout
+        tu.schedule = HEC_SCHED_LEVEL_LAUNCH;
+        attempt(tu);
+        return t;
+    }
     const bool auto_sched = tu.schedule == HEC_SCHED_AUTO;
     if (auto_sched) tu.schedule = HEC_SCHED_OWNER_PERSISTENT;
     if (tu.schedule == HEC_SCHED_OWNER_PERSISTENT && tu.variant == 0) {
@@ -966,8 +974,16 @@ TriHost analyze(const Csr &a, bool upper, bool unit, hec_dtype_t dt, const Tune 
                 if (e.code != HEC_ERR_CAPACITY) throw;
             }
         }
-        if (auto_sched) tu.schedule = HEC_SCHED_LEVEL_LAUNCH;
-        else tu.variant = 2;
+        if (auto_sched) {
+            // too large for LDS: the barrier-free kernel when levels are
+            // narrow (its per-level cost is one memory round trip), one
+            // launch per level when they are wide (cached gathers)
+            tu.schedule = HEC_SCHED_LEVEL_LAUNCH;
+            const double items = (double)a.n * std::max(1, tu.max_nrhs);
+            if (items < (double)(1 << 20) * std::max(1, t.lev.nlev)) t.variant = tu.variant = 5;
+        } else {
+            tu.variant = 2;
+        }
     }
     attempt(tu);
     return t;

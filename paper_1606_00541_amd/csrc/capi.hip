@@ -228,7 +228,7 @@ void build_plan(tri_plan_s &p, const Csr &a, bool upper, bool unit, hec_dtype_t 
     p.upper = upper;
     p.h = analyze(a, upper, unit, dt, tu, device_shape(tu, dt));
     p.d.block = tu.block_threads;
-    p.d.variant = tu.variant;
+    p.d.variant = p.h.variant;
     if (!tu.host_only) {
         upload_tri(p.d, p.h, tu.max_nrhs);
         p.on_device = true;
@@ -548,6 +548,7 @@ hec_status_t tri_plan_stats(tri_plan_t p, tri_stats_t *s)
         s->lds_rows = h.ex.sched.max_window;
         s->crit_hops = h.ex.sched.crit_hops;
         s->dataflow = h.ex.sched.dataflow ? 1 : 0;
+        s->syncfree = (h.ex.sched.kind == HEC_SCHED_LEVEL_LAUNCH && h.variant == 5) ? 1 : 0;
         s->unit_diag = h.unit ? 1 : 0;
         s->dtype = h.dt;
     });

@@ -118,6 +118,7 @@ struct ExecHost {
 struct TriHost {
     int32_t n = 0;
     bool upper = false, unit = false;
+    int32_t variant = 0;  // kernel the plan runs (hec_tune_t.kernel_variant, automatic choices resolved)
     hec_dtype_t dt = HEC_F64;
     Levels lev;
     HecHost hec;

@@ -1205,6 +1205,82 @@ OwnerKernel split_kernel(int w, bool unit, size_t &lds, int rows, int CH)
     }
 }
 
+// Barrier-free solve of a level-ordered plan through global memory, for
+// solutions too large for LDS (the alternative to one launch per level).  The
+// (row, rhs) items in level order are cut into chunks of 64, dealt
+// round-robin to the resident wavefronts.  A chunk depends only on earlier
+// chunks, and the earliest unfinished chunk belongs to a wavefront that has
+// finished all its earlier ones, so the solve progresses as long as every
+// wavefront is resident (the grid never exceeds co-residency).  xw starts as
+// the sentinel; an item reads its inputs with agent-scope loads and, once
+// none holds the sentinel, computes exactly as solve_item does and publishes
+// its value with an agent-scope store.  Lanes whose inputs are ready finish
+// inside the wait loop, so a wavefront never waits on one of its own lanes.
+template <typename T, typename TIn, typename TOut>
+__global__ void __launch_bounds__(256) k_syncfree(TriArgs a, int waves)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const long items = (long)a.n * a.R;
+    const long nch = (items + 63) >> 6;
+    const T *ev = static_cast<const T *>(a.ell_val);
+    T *xw = static_cast<T *>(a.xw);
+    for (long ch = wave; ch < nch; ch += waves) {
+        const long t = (ch << 6) + lane;
+        bool todo = t < items;
+        const int x = todo ? (int)(t / a.R) : 0;
+        const int k = todo ? (int)(t - (long)x * a.R) : 0;
+        T b = T(0);
+        if (todo) {
+            b = static_cast<T>(static_cast<const TIn *>(a.bin)[(size_t)a.gather[x] * a.R + k]);
+            if (a.dinv) b = scale_rhs(b, static_cast<const T *>(a.dinv)[x]);
+        }
+        unsigned spins = 0;
+        while (__ballot(todo)) {
+            if (todo) {
+                T s = b;
+                bool ready = true;
+                for (int e = 0; e < a.w && ready; ++e) {
+                    const int c = a.ell_col[(size_t)e * a.ld + x];
+                    if (c != a.n) {
+                        const T v = __hip_atomic_load(xw + (size_t)c * a.R + k, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                        if (is_sentinel(v)) ready = false;
+                        else s -= ev[(size_t)e * a.ld + x] * v;
+                    }
+                }
+                if (ready && a.tail_ptr) {
+                    const T *tv = static_cast<const T *>(a.tail_val);
+                    for (int p = a.tail_ptr[x]; p < a.tail_ptr[x + 1] && ready; ++p) {
+                        const T v = __hip_atomic_load(xw + (size_t)a.tail_col[p] * a.R + k, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                        if (is_sentinel(v)) ready = false;
+                        else s -= tv[p] * v;
+                    }
+                }
+                if (ready) {
+                    __hip_atomic_store(xw + (size_t)x * a.R + k, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (a.xout) {
+                        const int d = a.scatter[x];
+                        if (d >= 0) static_cast<TOut *>(a.xout)[(size_t)d * a.R + k] = static_cast<TOut>(s);
+                    }
+                    todo = false;
+                }
+            }
+            if (__ballot(todo)) {
+                __builtin_amdgcn_s_sleep(1);
+                if ((++spins & 255u) == 0 &&
+                    (spins > kSpinLimit ||
+                     __hip_atomic_load(a.err_dev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+                    __hip_atomic_store(a.err_dev, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(a.err_host, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    return;
+                }
+            }
+        }
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_fill_sentinel(T *p, size_t count)
 {
@@ -1216,6 +1292,17 @@ template <typename T, typename TIn, typename TOut>
 void launch_typed(DevTri &d, TriArgs a, hipStream_t st)
 {
     if (d.n == 0) return;
+    if (d.kind == HEC_SCHED_LEVEL_LAUNCH && d.variant == 5) {
+        const size_t cnt = ((size_t)d.n + 1) * a.R;
+        hipLaunchKernelGGL(k_fill_sentinel<T>, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st,
+                           static_cast<T *>(a.xw), cnt);
+        const long chunks = ((long)d.n * a.R + 63) / 64;
+        const int cap = capacity_of((const void *)k_syncfree<T, TIn, TOut>, 256, 0);
+        const int grid = (int)std::max<long>(1, std::min<long>(cap, (chunks + 3) / 4));
+        hipLaunchKernelGGL((k_syncfree<T, TIn, TOut>), dim3(grid), dim3(256), 0, st, a, grid * 4);
+        hip_check(hipGetLastError(), "k_syncfree launch");
+        return;
+    }
     if (d.kind == HEC_SCHED_LEVEL_LAUNCH) {
         for (int32_t k = 0; k < d.nlev; ++k) {
             a.row_begin = d.levelptr[k];

@@ -45,7 +45,11 @@ def test_tune_defaults_and_validation():
     with pytest.raises(H.HecError):
         H.tri_analyze(L, tune=H.tune_default(host_only=1, group_lanes=3))
     with pytest.raises(H.HecError):
-        H.tri_analyze(L, tune=H.tune_default(host_only=1, kernel_variant=5))
+        H.tri_analyze(L, tune=H.tune_default(host_only=1, kernel_variant=6))
+    with pytest.raises(H.HecError):  # the barrier-free kernel runs the level-ordered layout only
+        H.tri_analyze(L, tune=H.tune_default(host_only=1, kernel_variant=5, schedule="owner_persistent"))
+    p = H.tri_analyze(L, tune=H.tune_default(host_only=1, kernel_variant=5))
+    assert H.tri_plan_stats(p)["schedule"] == 1
     with pytest.raises(H.HecError):
         H.tri_analyze(L, tune=H.tune_default(host_only=1, block_threads=256, chunk_rows=768))
     # an owner plan with the default chunk size builds (steps are cut to chunks)
@@ -252,11 +256,17 @@ def test_auto_tuning_picks_the_dataflow_kernel_when_it_fits():
     L, _ = oracle.ilu0(A)
     st = H.tri_plan_stats(H.tri_analyze(L, unit_diag=True, tune=HOST))
     assert st["schedule"] == 3 and st["dataflow"] == 1
-    # one group cannot hold every row in LDS: one launch per level
+    # one group cannot hold every row in LDS: the level-ordered layout, run by
+    # the barrier-free kernel when levels are narrow ...
     A = synth.poisson2d(160)
     L, _ = oracle.ilu0(A)
     st = H.tri_plan_stats(H.tri_analyze(L, unit_diag=True, tune=H.tune_default(host_only=1, num_groups=1)))
-    assert st["schedule"] == 1 and st["dataflow"] == 0
+    assert st["schedule"] == 1 and st["dataflow"] == 0 and st["syncfree"] == 1
+    # ... and by one launch per level when they are wide (2^20 items and more)
+    n = (1 << 20) + 64
+    D = CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.full(n, 2.0))
+    st = H.tri_plan_stats(H.tri_analyze(D, tune=H.tune_default(host_only=1, num_groups=1)))
+    assert st["schedule"] == 1 and st["nlev"] == 1 and st["syncfree"] == 0
     # an explicit owner schedule falls back to the LDS-chunked owner kernel
     st = H.tri_plan_stats(H.tri_analyze(L, unit_diag=True, tune=H.tune_default(
         host_only=1, schedule="owner_persistent", num_groups=1)))

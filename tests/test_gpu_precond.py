@@ -160,6 +160,24 @@ def test_batch_matches_per_system_oracle():
         assert relerr(z[seg], oracle.ilu_apply(L, U, r[seg])) <= FP64_TOL
 
 
+def test_batch_and_ras_on_the_barrier_free_kernel():
+    # many independent systems / subdomains solved in one barrier-free launch
+    mats = [synth.diffusion2d(15 + 3 * i, 11, 1.0, seed=60 + i) for i in range(5)]
+    A, sys_ptr = _block_diag(mats)
+    t = H.tune_default(schedule="level_launch", kernel_variant=5, max_nrhs=3)
+    f = H.batch_setup(A, sys_ptr, "iluk", k=1, tune=t)
+    g = H.batch_setup(A, sys_ptr, "iluk", k=1, tune=H.tune_default(schedule="level_launch", max_nrhs=3))
+    r = synth.rhs(A.n, 3, 61)
+    assert np.array_equal(apply(f, r), apply(g, r))
+    B = synth.poisson3d(16)
+    owner, _ = synth.subdomain_cuts(B.n, 6, 400, 1000, seed=62)
+    s1 = H.ras_setup(B, 6, owner, overlap=1, factor_dtype="f32", tune=t)
+    s2 = H.ras_setup(B, 6, owner, overlap=1, factor_dtype="f32",
+                     tune=H.tune_default(schedule="level_launch", max_nrhs=3))
+    r = synth.rhs(B.n, 3, 63)
+    assert np.array_equal(apply(s1, r), apply(s2, r))
+
+
 def test_batch_rejects_coupled_systems():
     A = synth.poisson2d(6)
     with pytest.raises(H.HecError) as e:

@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 
 import paper_1606_00541_amd as H  # noqa: E402
 
-SCHEDS = ["level_launch", "level_persistent", "owner_persistent", "owner_dataflow"]
+SCHEDS = ["level_launch", "level_persistent", "owner_persistent", "owner_dataflow", "syncfree"]
 FP64_TOL = 1e-12
 
 
@@ -21,6 +21,8 @@ def tune(sched, **kw):
     by the dataflow kernel (no per-level barrier)."""
     if sched == "owner_dataflow":
         return H.tune_default(schedule="owner_persistent", kernel_variant=4, **kw)
+    if sched == "syncfree":  # the barrier-free kernel over the level-ordered layout
+        return H.tune_default(schedule="level_launch", kernel_variant=5, **kw)
     if sched == "owner_persistent":  # the LDS-chunked owner kernel (or its generic fallback)
         return H.tune_default(schedule=sched, kernel_variant=2, **kw)
     return H.tune_default(schedule=sched, **kw)
@@ -154,7 +156,7 @@ def test_diagonal_and_bidiagonal_closed_forms():
         assert np.array_equal(solve(p, np.ones(n)), np.arange(1, n + 1, dtype=float))
 
 
-@pytest.mark.parametrize("sched", ["owner_persistent", "owner_dataflow"])
+@pytest.mark.parametrize("sched", ["owner_persistent", "owner_dataflow", "syncfree"])
 def test_in_place_solve(sched):
     L = synth.random_lower(1500, 0.003, seed=8)
     b = synth.rhs(L.n, 1, 9)[:, 0]
@@ -259,3 +261,22 @@ def test_dataflow_wide_rows_bit_identical(dt, nrhs):
         assert st["ell_width"] in (10, 12, 16) and st["nnz_tail"] == 0 and st["dataflow"] == 1
         for rep in range(2):
             assert np.array_equal(solve(p, b, up), solve(ref, b, up))
+
+
+@pytest.mark.parametrize("nrhs", [1, 5])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_syncfree_bit_identical_to_level_launch_with_tails(nrhs, dt):
+    # ILU(1) factors with ELL width 2 (most entries in CSR tails), many levels
+    A = synth.diffusion3d(14, 12, 11, 1.5, seed=17)
+    L, U = oracle.iluk(A, 1)
+    b = synth.rhs(A.n, nrhs, 18)
+    for T, up in ((L, False), (U, True)):
+        uplo = "upper" if up else "lower"
+        outs = []
+        for s in ("level_launch", "syncfree"):
+            p = H.tri_analyze(T, uplo, unit_diag=not up, dtype=dt, tune=tune(s, ell_width=2, max_nrhs=nrhs))
+            bt = dev(b if dt == "f64" else b.astype(np.float32))
+            xt = torch.empty_like(bt)
+            (H.tri_solve_upper if up else H.tri_solve_lower)(p, bt, xt)
+            outs.append(xt.cpu().numpy())
+        assert np.array_equal(outs[0], outs[1])
