@@ -112,7 +112,7 @@ typedef struct hec_tune {
                                LEVEL_LAUNCH): one launch, each (row, rhs) waits only for its
                                own inputs, for solutions too large for LDS.  Schedule AUTO
                                picks it when the dataflow kernel does not fit and the levels
-                               are narrow (fewer than 2^20 (row, rhs) items per level on
+                               are narrow (fewer than 2^17 (row, rhs) items per level on
                                average), else one launch per level */
 } hec_tune_t;
 

@@ -980,7 +980,7 @@ TriHost analyze(const Csr &a, bool upper, bool unit, hec_dtype_t dt, const Tune 
             // launch per level when they are wide (cached gathers)
             tu.schedule = HEC_SCHED_LEVEL_LAUNCH;
             const double items = (double)a.n * std::max(1, tu.max_nrhs);
-            if (items < (double)(1 << 20) * std::max(1, t.lev.nlev)) t.variant = tu.variant = 5;
+            if (items < (double)(1 << 17) * std::max(1, t.lev.nlev)) t.variant = tu.variant = 5;
         } else {
             tu.variant = 2;
         }

@@ -310,7 +310,8 @@ void build_ilu(ilu_s &f, const Csr &L, const Csr &U, hec_dtype_t fdt, const Tune
     }
 }
 
-void ilu_apply_impl(ilu_s *f, const void *r, void *z, int32_t nrhs, hec_dtype_t vdt, hipStream_t st)
+void ilu_apply_impl(ilu_s *f, const void *r, void *z, int32_t nrhs, hec_dtype_t vdt, hipStream_t st,
+                    const int8_t *act = nullptr)
 {
     if (!f) fail(HEC_ERR_INVALID_ARG, "ilu is NULL");
     if (nrhs < 1) fail(HEC_ERR_INVALID_ARG, "nrhs must be >= 1");
@@ -321,9 +322,11 @@ void ilu_apply_impl(ilu_s *f, const void *r, void *z, int32_t nrhs, hec_dtype_t 
     check_device_error(f->U.d);
     ensure_workspace(f->L.d, nrhs);
     ensure_workspace(f->U.d, nrhs);
+    f->L.d.act = f->U.d.act = act;
     launch_tri(f->L.d, r, vdt, f->L.d.orig.as<int32_t>(), f->L.d.xw.p, nullptr, vdt, nullptr, nrhs, st);
     launch_tri(f->U.d, f->L.d.xw.p, f->fdt, f->qmap.as<int32_t>(), f->U.d.xw.p, z, vdt,
                f->U.d.orig.as<int32_t>(), nrhs, st);
+    f->L.d.act = f->U.d.act = nullptr;
 }
 
 // Device refactorization data of an ILU(0)/ILU(k) handle for A's pattern
@@ -428,7 +431,8 @@ void sync_host_factors(ilu_s &f)
     f.dev_newer = false;
 }
 
-void ras_apply_impl(ras_s *s, const double *r, double *z, int32_t nrhs, hipStream_t st)
+void ras_apply_impl(ras_s *s, const double *r, double *z, int32_t nrhs, hipStream_t st,
+                    const int8_t *act = nullptr)
 {
     if (!s) fail(HEC_ERR_INVALID_ARG, "ras is NULL");
     if (nrhs < 1) fail(HEC_ERR_INVALID_ARG, "nrhs must be >= 1");
@@ -441,9 +445,11 @@ void ras_apply_impl(ras_s *s, const double *r, double *z, int32_t nrhs, hipStrea
     ensure_workspace(f.L.d, nrhs);
     ensure_workspace(f.U.d, nrhs);
     // restriction fused into L's gather, restricted prolongation into U's scatter
+    f.L.d.act = f.U.d.act = act;
     launch_tri(f.L.d, r, HEC_F64, s->gather_L.as<int32_t>(), f.L.d.xw.p, nullptr, HEC_F64, nullptr, nrhs, st);
     launch_tri(f.U.d, f.L.d.xw.p, f.fdt, f.qmap.as<int32_t>(), f.U.d.xw.p, z, HEC_F64,
                s->scatter_U.as<int32_t>(), nrhs, st);
+    f.L.d.act = f.U.d.act = nullptr;
 }
 
 }  // namespace
@@ -467,12 +473,13 @@ void precond_check(const hec_precond_t &M, int32_t n)
     }
 }
 
-void precond_apply(const hec_precond_t &M, const double *r, double *z, int32_t R, hipStream_t st)
+void precond_apply(const hec_precond_t &M, const double *r, double *z, int32_t R, hipStream_t st,
+                   const int8_t *act)
 {
     if (M.kind == HEC_PRECOND_ILU)
-        ilu_apply_impl(static_cast<ilu_s *>(M.handle), r, z, R, HEC_F64, st);
+        ilu_apply_impl(static_cast<ilu_s *>(M.handle), r, z, R, HEC_F64, st, act);
     else
-        ras_apply_impl(static_cast<ras_s *>(M.handle), r, z, R, st);
+        ras_apply_impl(static_cast<ras_s *>(M.handle), r, z, R, st, act);
 }
 
 }  // namespace hec
@@ -624,6 +631,18 @@ hec_status_t batch_setup(int32_t n, const int32_t *rowptr, const int32_t *col, c
         factor(a, kind, k, tol, p, f->Lf, f->Uf, &f->sys_ptr);
         f->kind = kind;
         build_ilu(*f, f->Lf, f->Uf, fdt, tu);
+        if (!tu.host_only) {
+            // device row -> system, so that a solve can skip finished problems
+            for (tri_plan_s *pl : {&f->L, &f->U}) {
+                std::vector<int32_t> sg(n);
+                for (int32_t x = 0; x < n; ++x) {
+                    const int32_t i = pl->h.ex.orig[x];
+                    sg[x] = (int32_t)(std::upper_bound(f->sys_ptr.begin(), f->sys_ptr.end(), i) -
+                                      f->sys_ptr.begin()) - 1;
+                }
+                upload(pl->d.seg, sg);
+            }
+        }
         *out = f.release();
     });
 }

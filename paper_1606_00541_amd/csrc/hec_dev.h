@@ -94,6 +94,8 @@ struct TriArgs {
     const int32_t *rem_ptr, *rem_ent;       // owner schedule: cross-group entries per step
     const int32_t *imp_ptr, *imp_slot, *exp_row;  // dataflow owner kernel: imports and exports
     const int32_t *wave_ptr;                      // dataflow owner kernel: steps per wavefront
+    const int8_t *act;                            // barrier-free kernel: problems still to solve, or null
+    const int32_t *seg;                           // barrier-free kernel: device row -> system, or null
     int32_t chunk_rows;
     int32_t in_f64, out_f64;                // vector types of bin / xout
     void *mbox;          // [2][nexp][mbox_stride] values crossing workgroups
@@ -125,6 +127,8 @@ struct DevTri {
     int32_t variant = 0;           // persistent kernel choice (hec_tune_t.kernel_variant)
     bool dataflow = false;         // columns encode group-local imports (dataflow kernel only)
     DevMem imp_ptr, imp_slot, exp_row, wave_ptr;
+    DevMem seg;                    // device row -> independent system (batches; empty: one system)
+    const int8_t *act = nullptr;   // per-launch: active (system, rhs) problems; others may be skipped
     int32_t df_waves = 0;          // compute wavefronts per group (block = 64 * df_waves + 128)
     int32_t df_rows = 0, df_ints = 0;
     int32_t df_step_rows = 0;      // longest step (one wavefront covers step rows x nrhs)

@@ -396,7 +396,10 @@ struct Ctx {
 
 // Preconditioner application hooks defined in capi.hip.
 namespace hec {
-void precond_apply(const hec_precond_t &M, const double *r, double *z, int32_t R, hipStream_t st);
+// act: device mask of the (system, rhs) problems still being solved (or
+// null); a kernel may skip the others, whose output is then left stale.
+void precond_apply(const hec_precond_t &M, const double *r, double *z, int32_t R, hipStream_t st,
+                   const int8_t *act = nullptr);
 void precond_check(const hec_precond_t &M, int32_t n);
 }  // namespace hec
 
@@ -404,13 +407,14 @@ using namespace hec;
 
 namespace {
 
-void apply_M(const hec_precond_t &M, const double *r, double *z, int R, long n, hipStream_t st)
+void apply_M(const hec_precond_t &M, const double *r, double *z, int R, long n, hipStream_t st,
+             const int8_t *act = nullptr)
 {
     if (M.kind == HEC_PRECOND_NONE) {
         if (z != r) hip_check(hipMemcpyAsync(z, r, sizeof(double) * n * R, hipMemcpyDeviceToDevice, st), "copy");
         return;
     }
-    precond_apply(M, r, z, R, st);
+    precond_apply(M, r, z, R, st, act);
 }
 
 // Restarted (F)GMRES(m): right preconditioning with the preconditioned basis
@@ -491,7 +495,8 @@ hec_status_t gmres(const DevHec &A, const hec_precond_t &M, int m, const double 
         }
         int j = 0;
         for (; j < m; ++j) {
-            apply_M(M, Vi(j), Zi(j), R, n, st);
+            // problems already finished are skipped (their basis stops growing)
+            apply_M(M, Vi(j), Zi(j), R, n, st, c.actm.as<int8_t>());
             spmv(A, Zi(j), w, R, st);
             // two passes of classical Gram-Schmidt, coefficients kept on the
             // device; the Hessenberg column reaches the host once per step

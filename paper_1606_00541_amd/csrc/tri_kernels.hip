@@ -1208,14 +1208,17 @@ OwnerKernel split_kernel(int w, bool unit, size_t &lds, int rows, int CH)
 // Barrier-free solve of a level-ordered plan through global memory, for
 // solutions too large for LDS (the alternative to one launch per level).  The
 // (row, rhs) items in level order are cut into chunks of 64, dealt
-// round-robin to the resident wavefronts.  A chunk depends only on earlier
+// round-robin to the wavefronts of the grid.  A chunk depends only on earlier
 // chunks, and the earliest unfinished chunk belongs to a wavefront that has
 // finished all its earlier ones, so the solve progresses as long as every
-// wavefront is resident (the grid never exceeds co-residency).  xw starts as
-// the sentinel; an item reads its inputs with agent-scope loads and, once
-// none holds the sentinel, computes exactly as solve_item does and publishes
-// its value with an agent-scope store.  Lanes whose inputs are ready finish
-// inside the wait loop, so a wavefront never waits on one of its own lanes.
+// wavefront is resident: the grid is kept to a fraction of the kernel's
+// occupancy (claiming chunks from a shared counter instead removes that
+// condition but serializes on the counter: ~10x slower on a million chunks).
+// xw starts as the sentinel; an item reads its inputs with
+// agent-scope loads and, once none holds the sentinel, computes exactly as
+// solve_item does and publishes its value with an agent-scope store.  Lanes
+// whose inputs are ready finish inside the wait loop, so a wavefront never
+// waits on one of its own lanes.
 template <typename T, typename TIn, typename TOut>
 __global__ void __launch_bounds__(256) k_syncfree(TriArgs a, int waves)
 {
@@ -1230,6 +1233,8 @@ __global__ void __launch_bounds__(256) k_syncfree(TriArgs a, int waves)
         bool todo = t < items;
         const int x = todo ? (int)(t / a.R) : 0;
         const int k = todo ? (int)(t - (long)x * a.R) : 0;
+        // a finished problem's rows are skipped: they feed only that problem
+        if (todo && a.act && !a.act[(a.seg ? a.seg[x] : 0) * a.R + k]) todo = false;
         T b = T(0);
         if (todo) {
             b = static_cast<T>(static_cast<const TIn *>(a.bin)[(size_t)a.gather[x] * a.R + k]);
@@ -1296,9 +1301,14 @@ void launch_typed(DevTri &d, TriArgs a, hipStream_t st)
         const size_t cnt = ((size_t)d.n + 1) * a.R;
         hipLaunchKernelGGL(k_fill_sentinel<T>, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st,
                            static_cast<T *>(a.xw), cnt);
+        // about one wavefront per chunk of an average level (at least two
+        // workgroups per compute unit), and never above half the occupancy,
+        // so that every wavefront is resident with a wide margin
         const long chunks = ((long)d.n * a.R + 63) / 64;
         const int cap = capacity_of((const void *)k_syncfree<T, TIn, TOut>, 256, 0);
-        const int grid = (int)std::max<long>(1, std::min<long>(cap, (chunks + 3) / 4));
+        const long per_level = chunks / std::max(1, d.nlev);
+        const long lim = std::min<long>(std::max(1, cap / 2), std::max<long>(2L * device_cus(), per_level / 4));
+        const int grid = (int)std::max<long>(1, std::min<long>(lim, (chunks + 3) / 4));
         hipLaunchKernelGGL((k_syncfree<T, TIn, TOut>), dim3(grid), dim3(256), 0, st, a, grid * 4);
         hip_check(hipGetLastError(), "k_syncfree launch");
         return;
@@ -1513,6 +1523,8 @@ void launch_tri(DevTri &d, const void *bin, hec_dtype_t in_dt, const int32_t *ga
     a.imp_slot = d.imp_slot.as<int32_t>();
     a.exp_row = d.exp_row.as<int32_t>();
     a.wave_ptr = d.wave_ptr.as<int32_t>();
+    a.act = d.act;
+    a.seg = d.seg.p ? d.seg.as<int32_t>() : nullptr;
     a.trace = d.trace;
     a.trace_stride = d.trace_stride;
     a.in_f64 = in_dt == HEC_F64 ? 1 : 0;
