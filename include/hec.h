@@ -5,8 +5,9 @@
  * The library implements the method of Chen, Liu and Yang, "Parallel
  * Triangular Solvers on GPU": sparse lower and upper triangular solves on the
  * HEC (hybrid ELL + CSR) format, scheduled by level sets, applied as ILU(0),
- * ILU(k), ILUT and Restricted Additive Schwarz preconditioners inside
- * restarted GMRES and BiCGSTAB.
+ * ILU(k), ILUT, block ILU and Restricted Additive Schwarz preconditioners
+ * inside restarted GMRES and BiCGSTAB, plus a device refactorization of
+ * ILU(0)/ILU(k) factors and an SOR / Gauss-Seidel smoother on the same solves.
  *
  * Conventions shared by every entry point:
  *  - Indices are int32_t and 0-based.  Host CSR inputs (rowptr[n+1], col[nnz],
@@ -17,7 +18,8 @@
  *    index fastest.  Input and output vectors must not overlap unless a
  *    function says otherwise.
  *  - Every device call takes a hipStream_t and is asynchronous on it, except
- *    krylov_solve, which synchronizes the stream to return its info.
+ *    krylov_solve, krylov_solve_batch and ilu_refactor, which synchronize the
+ *    stream to return their outcome.
  *  - Every function returns hec_status_t; on error the handle outputs are left
  *    untouched and hec_last_error() returns a thread-local description.  No
  *    C++ exception crosses this interface.
