@@ -391,6 +391,7 @@ void build_refactor(ilu_s &f, const int32_t *rowptr, const int32_t *col)
         }
     }
     const Levels &lv = f.L.h.lev;
+    r->max_row = std::max(1, maxrow);
     r->levelptr = lv.levelptr;
     r->nnz_a = nnz_a;
     r->nnz_f = (int64_t)fci.size();

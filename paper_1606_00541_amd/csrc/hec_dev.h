@@ -151,7 +151,7 @@ struct DevTri {
 // -1 - tail index).
 constexpr int kRefactorMaxRow = 1024;   // longest factor row (LDS staging)
 struct DevRefactor {
-    int32_t n = 0;
+    int32_t n = 0, max_row = 1;           // longest factor row
     int64_t nnz_a = 0, nnz_f = 0, nl = 0, nu = 0;
     std::vector<int32_t> a_rp, a_ci;      // pattern of A the map was built for
     std::vector<int32_t> levelptr;        // levels of L (host bounds into rows)

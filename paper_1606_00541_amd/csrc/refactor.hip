@@ -39,16 +39,32 @@ __global__ void __launch_bounds__(256) k_scatter_a(const double *aval, const int
     if (t < nnz) f[a2f[t]] = aval[t];
 }
 
+// LDS bytes of k_ilu_row for factor rows of at most `maxrow` entries.
+size_t ilu_row_lds(int maxrow)
+{
+    const int np = maxrow < kRowThreads ? maxrow : kRowThreads;
+    return (size_t)maxrow * sizeof(double) + (size_t)np * sizeof(double) + (size_t)maxrow * sizeof(int32_t) +
+           2 * (size_t)np * sizeof(int32_t);
+}
+
 // One workgroup (one wavefront) per row of the level.  The row is staged in
-// LDS; lane-parallel over the entries of each pivot row.
+// LDS (sized for the pattern's longest row, so that many rows are resident);
+// lane-parallel over the entries of each pivot row.
 __global__ void __launch_bounds__(kRowThreads) k_ilu_row(const int32_t *rows, int nrows, const int32_t *rp,
                                                          const int32_t *ci, const int32_t *dpos, double *f,
-                                                         int *err)
+                                                         int *err, int maxrow)
 {
     // the host factorization rounds the product and the difference separately
 #pragma clang fp contract(off)
-    __shared__ int32_t scol[kRefactorMaxRow];
-    __shared__ double sval[kRefactorMaxRow];
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int np = maxrow < kRowThreads ? maxrow : kRowThreads;
+    double *sval = reinterpret_cast<double *>(smem);
+    // the first np pivot rows' pivot value, diagonal position and end,
+    // fetched by one lane each before the elimination starts
+    double *spiv = sval + maxrow;
+    int32_t *scol = reinterpret_cast<int32_t *>(spiv + np);
+    int32_t *spk = scol + maxrow;
+    int32_t *spe = spk + np;
     const int q = blockIdx.x;
     if (q >= nrows) return;
     const int i = rows[q];
@@ -57,14 +73,22 @@ __global__ void __launch_bounds__(kRowThreads) k_ilu_row(const int32_t *rows, in
         scol[t] = ci[b + t];
         sval[t] = f[b + t];
     }
+    if (threadIdx.x < di && threadIdx.x < np) {
+        const int k = ci[b + threadIdx.x];
+        const int pk = dpos[k];
+        spk[threadIdx.x] = pk;
+        spe[threadIdx.x] = rp[k + 1];
+        spiv[threadIdx.x] = f[pk];
+    }
     __syncthreads();
     for (int kk = 0; kk < di; ++kk) {
+        const bool tab = kk < np;
         const int k = scol[kk];
-        const int pk = dpos[k];
-        const double lik = sval[kk] / f[pk];
+        const int pk = tab ? spk[kk] : dpos[k];
+        const double lik = sval[kk] / (tab ? spiv[kk] : f[pk]);
         __syncthreads();
         if (threadIdx.x == 0) sval[kk] = lik;
-        const int pe = rp[k + 1];
+        const int pe = tab ? spe[kk] : rp[k + 1];
         for (int p = pk + 1 + threadIdx.x; p < pe; p += kRowThreads) {
             const int j = ci[p];
             // row i's entries after kk are sorted: binary search for column j
@@ -151,8 +175,8 @@ void refactor_numeric(DevRefactor &r, const double *aval, hipStream_t st)
     for (size_t k = 0; k + 1 < r.levelptr.size(); ++k) {
         const int nr = r.levelptr[k + 1] - r.levelptr[k];
         if (nr == 0) continue;
-        hipLaunchKernelGGL(k_ilu_row, dim3(nr), dim3(kRowThreads), 0, st, rows + r.levelptr[k], nr,
-                           r.frp.as<int32_t>(), r.fci.as<int32_t>(), r.fdpos.as<int32_t>(), f, err);
+        hipLaunchKernelGGL(k_ilu_row, dim3(nr), dim3(kRowThreads), ilu_row_lds(r.max_row), st, rows + r.levelptr[k],
+                           nr, r.frp.as<int32_t>(), r.fci.as<int32_t>(), r.fdpos.as<int32_t>(), f, err, r.max_row);
     }
     hip_check(hipGetLastError(), "refactor launch");
     int flag = 0;
