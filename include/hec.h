@@ -308,6 +308,18 @@ hec_status_t ras_setup_ilu(int32_t n, const int32_t *rowptr, const int32_t *col,
                            int32_t k, double tol, int32_t p, hec_dtype_t factor_dt,
                            const hec_tune_t *tune, ras_t *out);
 hec_status_t ras_apply(ras_t ras, const double *r, double *z, int32_t nrhs, hipStream_t stream);
+/* Device refactorization of a RAS / block ILU handle built with ILU(0) or
+ * ILU(k) subdomain factors, as ilu_refactor: `val` (device FP64, in the order
+ * of A's host pattern rowptr/col) holds new values of A; every subdomain
+ * matrix A_s = A[ext_s, ext_s] is gathered from them on the device and
+ * refactored over its fixed pattern, and the plans are rewritten in place
+ * (bit-identical to a new setup with these values).  rowptr = col = NULL
+ * reuses the previous call's pattern.  Synchronizes `stream`.
+ * Errors: INVALID_ARG (ILUT subdomains, NULL arrays, no earlier pattern, an
+ * entry of a subdomain matrix missing from A's pattern), ZERO_PIVOT, CAPACITY,
+ * NO_DEVICE for a host-only setup. */
+hec_status_t ras_refactor(ras_t ras, const int32_t *rowptr, const int32_t *col, const double *val,
+                          hipStream_t stream);
 /* Extended-subdomain sizes (ext[nsub], may be NULL) and total extended rows. */
 hec_status_t ras_info(ras_t ras, int32_t *nsub, int64_t *total_ext, int32_t *ext_sizes);
 /* Borrowed plan handles of the block-diagonal L and U. */

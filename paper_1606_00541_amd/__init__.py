@@ -100,6 +100,7 @@ SIGNATURES = {
     "ras_info": (_i32, [_vp, _P(_i32), _P(_i64), _vp]),
     "ras_plans": (_i32, [_vp, _P(_vp), _P(_vp)]),
     "ras_destroy": (None, [_vp]),
+    "ras_refactor": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "sor_setup": (_i32, [_i32, _vp, _vp, _vp, ctypes.c_double, _P(Tune), _P(_vp)]),
     "sor_apply": (_i32, [_vp, _vp, _vp, _i32, _i32, _i32, _vp]),
     "sor_destroy": (None, [_vp]),
@@ -473,6 +474,28 @@ def sor_apply(s: Sor, b, x, sweeps=1, symmetric=False, stream=None):
     if R != R2 or db != HEC_F64 or dx != HEC_F64:
         raise ValueError("sor_apply takes FP64 b and x of equal shape")
     _check(lib().sor_apply(s.ptr, pb, px, R, int(sweeps), int(bool(symmetric)), _stream(stream)))
+
+
+def ras_refactor(s: Ras, A=None, val=None, stream=None):
+    """Refactor a RAS / block ILU handle on the device with new values of A
+    (same pattern); arguments as ilu_refactor."""
+    import torch
+
+    if A is None:
+        if val is None:
+            raise ValueError("val is required when A is None")
+        rp = ci = None
+    else:
+        n, rp, ci, v = _csr(A)
+        if val is None:
+            val = torch.from_numpy(np.ascontiguousarray(v, dtype=np.float64)).cuda()
+        if val.numel() != ci.shape[0]:
+            raise ValueError("val must hold nnz(A) values")
+    if val.dtype != torch.float64 or not val.is_cuda:
+        raise ValueError("val must be a device FP64 tensor")
+    val = val.contiguous()
+    _check(lib().ras_refactor(s.ptr, _ptr(rp) if rp is not None else None, _ptr(ci) if ci is not None else None,
+                              ctypes.c_void_p(val.data_ptr()), _stream(stream)))
 
 
 def ras_apply(s: Ras, r, z, stream=None):

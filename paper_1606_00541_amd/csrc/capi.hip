@@ -164,6 +164,11 @@ void check_device_error(const DevTri &d)
 
 using namespace hec;
 
+namespace hec {
+// dst[t] = src[idx[t]] on the device (refactor.hip)
+void gather_f64(const double *src, const int32_t *idx, int64_t cnt, double *dst, hipStream_t st);
+}  // namespace hec
+
 struct tri_plan_s {
     TriHost h;
     DevTri d;
@@ -196,6 +201,10 @@ struct ras_s {
     int32_t n = 0, nsub = 0;
     RasLayout lay;
     ilu_s f;                     // factors of the block-diagonal matrix
+    // device refactorization: A's pattern, each block-diagonal entry's index in A's
+    // values, and the gathered block-diagonal values
+    std::vector<int32_t> a_rp, a_ci;
+    DevMem a2bd, bdval;
     DevMem gather_L;             // L device row -> global row of r
     DevMem scatter_U;            // U device row -> global row of z, or -1 when not owned
 };
@@ -703,6 +712,55 @@ hec_status_t ilu_refactor(ilu_t f, const int32_t *rowptr, const int32_t *col, co
     });
 }
 
+hec_status_t ras_refactor(ras_t s, const int32_t *rowptr, const int32_t *col, const double *val, hipStream_t st)
+{
+    return guard([&] {
+        if (!s) fail(HEC_ERR_INVALID_ARG, "ras is NULL");
+        ilu_s &f = s->f;
+        if (f.kind == HEC_ILUT) fail(HEC_ERR_INVALID_ARG, "ILUT's pattern depends on the values; refactor needs ILU(0) or ILU(k)");
+        require_device(f.L);
+        const int32_t n = s->n;
+        if (!rowptr && !col) {
+            if (s->a_rp.empty()) fail(HEC_ERR_INVALID_ARG, "no pattern given and none from an earlier call");
+        } else {
+            if (!rowptr || (!col && rowptr[n] > 0)) fail(HEC_ERR_INVALID_ARG, "rowptr or col is NULL");
+            const bool same = s->a_rp.size() == (size_t)n + 1 && std::equal(s->a_rp.begin(), s->a_rp.end(), rowptr) &&
+                              (int64_t)s->a_ci.size() == (int64_t)rowptr[n] &&
+                              std::equal(s->a_ci.begin(), s->a_ci.end(), col);
+            if (!same) {
+                // each entry of A_s = A[ext_s, ext_s] is an entry of A
+                if (rowptr[0] != 0) fail(HEC_ERR_INVALID_ARG, "rowptr[0] must be 0");
+                const Csr &bd = s->lay.blockdiag;
+                std::vector<int32_t> idx((size_t)bd.nnz());
+                for (int32_t r = 0; r < bd.n; ++r) {
+                    const int32_t g = s->lay.ext[r];
+                    const int32_t *b = col + rowptr[g], *e = col + rowptr[g + 1];
+                    for (int32_t q = bd.rp[r]; q < bd.rp[r + 1]; ++q) {
+                        const int32_t gc = s->lay.ext[bd.ci[q]];
+                        const int32_t *it = std::lower_bound(b, e, gc);
+                        if (it == e || *it != gc)
+                            fail(HEC_ERR_INVALID_ARG, "entry (" + std::to_string(g) + ", " + std::to_string(gc) +
+                                 ") of a subdomain matrix is not in A's pattern");
+                        idx[q] = (int32_t)(it - col);
+                    }
+                }
+                upload(s->a2bd, idx);
+                s->bdval.alloc(std::max<size_t>(1, idx.size()) * sizeof(double));
+                if (!f.rf) build_refactor(f, bd.rp.data(), bd.ci.data());
+                s->a_rp.assign(rowptr, rowptr + n + 1);
+                s->a_ci.assign(col, col + rowptr[n]);
+            }
+        }
+        if (s->lay.blockdiag.nnz() > 0 && !val) fail(HEC_ERR_INVALID_ARG, "val is NULL");
+        check_device_error(f.L.d);
+        check_device_error(f.U.d);
+        gather_f64(val, s->a2bd.as<int32_t>(), s->lay.blockdiag.nnz(), s->bdval.as<double>(), st);
+        refactor_numeric(*f.rf, s->bdval.as<double>(), st);
+        refactor_refill(*f.rf, f.L.d, f.U.d, st);
+        f.dev_newer = true;
+    });
+}
+
 hec_status_t ras_setup(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val, int32_t nsub,
                        const int32_t *owner, int32_t overlap, hec_dtype_t fdt, const hec_tune_t *tune, ras_t *out)
 {
@@ -725,6 +783,7 @@ hec_status_t ras_setup_ilu(int32_t n, const int32_t *rowptr, const int32_t *col,
         s->lay = ras_layout(a, nsub, owner, overlap);
         ilu_s &f = s->f;
         factor(s->lay.blockdiag, kind, k, tol, p, f.Lf, f.Uf, &s->lay.ext_ptr);
+        f.kind = kind;
         build_ilu(f, f.Lf, f.Uf, fdt, tu);
         if (!tu.host_only) {
             const int32_t m = s->lay.blockdiag.n;

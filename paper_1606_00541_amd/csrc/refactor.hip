@@ -141,6 +141,12 @@ __global__ void __launch_bounds__(256) k_refill_dinv(const double *f, const int3
     if (t < n) dinv[t] = (T)(1.0 / f[src[t]]);
 }
 
+__global__ void __launch_bounds__(256) k_gather_f64(const double *src, const int32_t *idx, long cnt, double *dst)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < cnt) dst[t] = src[idx[t]];
+}
+
 int grid_for(long cnt) { return (int)((cnt + 255) / 256); }
 
 template <typename T>
@@ -183,6 +189,13 @@ void refactor_numeric(DevRefactor &r, const double *aval, hipStream_t st)
     hip_check(hipMemcpyAsync(&flag, err, sizeof(int), hipMemcpyDeviceToHost, st), "refactor flag copy");
     hip_check(hipStreamSynchronize(st), "refactor synchronize");
     if (flag) fail(HEC_ERR_ZERO_PIVOT, "zero or non-finite pivot in the device refactorization");
+}
+
+void gather_f64(const double *src, const int32_t *idx, int64_t cnt, double *dst, hipStream_t st)
+{
+    if (cnt <= 0) return;
+    hipLaunchKernelGGL(k_gather_f64, dim3(grid_for(cnt)), dim3(256), 0, st, src, idx, (long)cnt, dst);
+    hip_check(hipGetLastError(), "gather launch");
 }
 
 void refactor_refill(const DevRefactor &r, DevTri &L, DevTri &U, hipStream_t st)

@@ -224,6 +224,11 @@ def test_refactor_needs_a_device_and_a_fixed_pattern_kind():
         f = H.ilu_setup(A, kind, p=4, tol=1e-2, tune=HOST)
         rc = H.lib().ilu_refactor(f.ptr, H._ptr(rp), H._ptr(ci), None, None)
         assert H.STATUS_NAMES[rc] == code
+    owner = synth.grid_bisection(6, 6, 1, 4)
+    for kind, code in (("iluk", "NO_DEVICE"), ("ilut", "INVALID_ARG")):
+        s = H.ras_setup_ilu(A, 4, owner, overlap=1, kind=kind, k=1, p=4, tol=1e-2, tune=HOST)
+        rc = H.lib().ras_refactor(s.ptr, H._ptr(rp), H._ptr(ci), None, None)
+        assert H.STATUS_NAMES[rc] == code
 
 
 def test_sor_setup_validation():

@@ -121,3 +121,27 @@ def test_refactor_rejects_ilut_and_foreign_patterns():
     with pytest.raises(H.HecError) as e:
         H.ilu_refactor(g, CSR(64, Bs.indptr.astype(np.int32), Bs.indices.astype(np.int32), Bs.data.copy()))
     assert e.value.name == "INVALID_ARG"
+
+
+@pytest.mark.parametrize("kind,overlap,fdt", [("ilu0", 1, "f64"), ("iluk", 0, "f64"), ("ilu0", 1, "f32")])
+def test_ras_refactor_equals_new_setup(kind, overlap, fdt):
+    A1 = synth.diffusion3d(14, 12, 10, 1.0, seed=70)
+    A2 = synth.diffusion3d(14, 12, 10, 2.0, seed=71)
+    owner = synth.grid_bisection(14, 12, 10, 6)
+    t = H.tune_default(max_nrhs=2)
+    s = H.ras_setup_ilu(A1, 6, owner, overlap=overlap, kind=kind, k=1, factor_dtype=fdt, tune=t)
+    g = H.ras_setup_ilu(A2, 6, owner, overlap=overlap, kind=kind, k=1, factor_dtype=fdt, tune=t)
+    r = synth.rhs(A2.n, 2, 72)
+
+    def ras(h):
+        rt = torch.from_numpy(np.ascontiguousarray(r)).cuda()
+        zt = torch.empty_like(rt)
+        H.ras_apply(h, rt, zt)
+        return zt.cpu().numpy()
+
+    H.ras_refactor(s, A2)
+    assert np.array_equal(ras(s), ras(g))
+    # the previous pattern again, values already on the device
+    H.ras_refactor(s, None, val=torch.from_numpy(A1.val.copy()).cuda())
+    H.ras_refactor(s, None, val=torch.from_numpy(A2.val.copy()).cuda())
+    assert np.array_equal(ras(s), ras(g))
