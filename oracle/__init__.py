@@ -322,8 +322,11 @@ def ilut(A: CSR, p: int, tau: float):
     drop by tau * ||a_i||_2, keep the p largest in each of L and U (ties to
     the smaller column), diagonal always kept.  Returns (L, U) as ``ilu0``.
 
-    Pinned only at its limits (tau = 0 with p >= n is the exact LU; p = 0
-    gives L = I, U = diag(A)); between them parity unpinned.
+    Pinned at its limits (tau = 0 with p >= n is the exact LU; p = 0 gives
+    L = I, U = diag(A)) and between them by a 6x6 worked example derived by
+    hand (tests/golden/ilut_6x6_p2_tau0125.txt) on which a multiplier
+    dropped after its division, a fill entry dropped by the final test, the
+    p-largest rule, the tie rule and the inclusive threshold each matter.
     """
     rp, ci = _csr_args(A)
     v = np.ascontiguousarray(A.val, dtype=np.float64)
