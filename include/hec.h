@@ -58,9 +58,10 @@ typedef enum hec_uplo { HEC_LOWER = 0, HEC_UPPER = 1 } hec_uplo_t;
 /* How the level sets are executed on the device (all give bit-identical
  * results for the same plan, since every row is computed the same way). */
 typedef enum hec_schedule {
-    HEC_SCHED_AUTO = 0,              /* the owner schedule on the dataflow kernel when its LDS
-                                        holds every part for max_nrhs right-hand sides, else
-                                        one launch per level */
+    HEC_SCHED_AUTO = 0,              /* the owner schedule on the dataflow kernel: one part
+                                        per workgroup when the LDS holds every part for
+                                        max_nrhs right-hand sides, else parts taken from a
+                                        queue (kernel_variant 6) */
     HEC_SCHED_LEVEL_LAUNCH = 1,      /* one kernel launch per level (Algorithm 2 shape) */
     HEC_SCHED_LEVEL_PERSISTENT = 2,  /* one persistent launch; each level split into
                                         per-workgroup chunks; a chunk polls the values it
@@ -112,19 +113,29 @@ typedef struct hec_tune {
                                max_nrhs at most 64; 5 = barrier-free kernel over the
                                level-ordered layout in global memory (schedule AUTO or
                                LEVEL_LAUNCH): one launch, each (row, rhs) waits only for its
-                               own inputs, for solutions too large for LDS.  Schedule AUTO
-                               picks it when the dataflow kernel does not fit and the levels
-                               are narrow (fewer than 2^17 (row, rhs) items per level on
-                               average), else one launch per level */
+                               own inputs; 6 = the dataflow kernel with more parts than
+                               workgroups (schedule AUTO or OWNER_PERSISTENT): every
+                               independent system (batch_setup's systems, RAS subdomains, or
+                               the whole matrix) is cut into contiguous ranges of its problem
+                               order that fit the LDS (part_rows sets a first cut), systems
+                               with the most levels first, and the workgroups take parts from
+                               a queue in that order: a part reads only from earlier parts,
+                               so the solve needs no co-residency.  Schedule AUTO picks 4 when
+                               every part fits one workgroup per part, else 6; 5 or one launch
+                               per level only when neither applies */
 } hec_tune_t;
 
 /* Per-RHS outcome of krylov_solve. */
 typedef struct hec_krylov_info {
-    int32_t status;          /* HEC_OK, HEC_ERR_NOT_CONVERGED or HEC_ERR_BREAKDOWN */
+    int32_t status;          /* HEC_OK (true relative residual <= rtol), HEC_ERR_NOT_CONVERGED
+                                (maxit reached), HEC_ERR_BREAKDOWN (a zero or non-finite
+                                scalar, or a non-finite residual, stopped this RHS) or
+                                HEC_ERR_INVALID_ARG (b holds a NaN or infinity; not iterated) */
     int32_t iters;           /* Krylov iterations (Arnoldi steps / BiCGSTAB steps) */
     int32_t restarts;        /* completed restart cycles */
     int32_t precond_applies; /* preconditioner applications */
-    double relres;           /* final true ||b - A x||_2 / ||b||_2, computed in FP64 */
+    double relres;           /* final true ||b - A x||_2 / ||b||_2, computed in FP64 (||b - A x||_2
+                                for b = 0; NaN when b is not finite) */
 } hec_krylov_info_t;
 
 /* Statistics of a triangular plan. */
@@ -138,6 +149,8 @@ typedef struct tri_stats {
     int32_t crit_hops;       /* most workgroup-to-workgroup handoffs along one dependency chain */
     int32_t dataflow;        /* 1 when the plan runs on the dataflow owner kernel */
     int32_t syncfree;        /* 1 when the plan runs on the barrier-free global-memory kernel */
+    int32_t queue;           /* 1 when the dataflow kernel takes its parts from a queue
+                                (num_groups then counts parts, not workgroups) */
 } tri_stats_t;
 
 typedef struct hec_matrix_s *hec_matrix_t;
@@ -226,6 +239,22 @@ hec_status_t tri_plan_layout(tri_plan_t plan, int32_t *xperm, int32_t *owner);
  * (steps beyond stride-1 are not recorded) and needs 16 bytes of LDS per
  * recorded step.  Pass NULL to stop tracing. */
 hec_status_t tri_plan_trace(tri_plan_t plan, void *trace, int32_t stride);
+
+/* Bounded waits.  Every device-side wait of a persistent launch (a row's
+ * input from another workgroup or wavefront) gives up after a number of
+ * polls; the launch then raises the plan's abort flag, every workgroup exits,
+ * the output of that launch is unspecified, and the next call on the plan
+ * (tri_solve_*, ilu_apply, ras_apply, krylov_solve, or tri_plan_check)
+ * returns HEC_ERR_TIMEOUT and clears the flag, so the call after it runs
+ * normally.  tri_plan_set_wait_limit sets the plan's limit in polls (0 = the
+ * default 2^22, about a second; at most 2^27): a smaller limit detects a hung
+ * solve sooner, and a limit of a few polls makes any wait give up (to test a
+ * caller's handling of the TIMEOUT path).  Errors: INVALID_ARG.
+ * tri_plan_check reports (and clears) an abort of an earlier launch without
+ * launching anything: call it after synchronizing the stream to learn whether
+ * the last solve completed.  Returns HEC_OK or HEC_ERR_TIMEOUT. */
+hec_status_t tri_plan_set_wait_limit(tri_plan_t plan, uint32_t polls);
+hec_status_t tri_plan_check(tri_plan_t plan);
 
 /* Solve L x = b (Algorithm 2): b is gathered into level order, the levels are
  * solved in order with all rows of a level computed simultaneously, and x is
@@ -375,7 +404,10 @@ void sor_destroy(sor_t sor);
  * BiCGSTAB: van der Vorst's right-preconditioned recurrence.  Convergence is
  * declared on the true residual ||b - A x|| / ||b|| <= rtol.  b, x: device FP64
  * [n][nrhs]; x holds x0 on entry.  info: host array of nrhs entries.
- * Returns HEC_OK if every RHS converged, else NOT_CONVERGED or BREAKDOWN.
+ * A NaN never counts as converged: each RHS stops on its own at a non-finite
+ * value, and its x is then left as it was before the step that produced it.
+ * Returns HEC_OK if every RHS converged; else the first INVALID_ARG or
+ * BREAKDOWN among the RHS, else NOT_CONVERGED (per-RHS outcome in info).
  * ------------------------------------------------------------------------- */
 hec_status_t krylov_solve(hec_matrix_t A, hec_precond_t M, hec_krylov_t method, int32_t m,
                           const double *b, double *x, int32_t nrhs, double rtol, int32_t maxit,

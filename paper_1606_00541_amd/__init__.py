@@ -61,7 +61,8 @@ class TriStats(ctypes.Structure):
         "n", "nlev", "ell_width", "ld", "num_groups", "nsteps", "nexport", "schedule")] + [
         ("nnz_offdiag", ctypes.c_int64), ("nnz_tail", ctypes.c_int64), ("lds_rows", ctypes.c_int64),
         ("nremote", ctypes.c_int64), ("unit_diag", ctypes.c_int32), ("dtype", ctypes.c_int32),
-        ("crit_hops", ctypes.c_int32), ("dataflow", ctypes.c_int32), ("syncfree", ctypes.c_int32)]
+        ("crit_hops", ctypes.c_int32), ("dataflow", ctypes.c_int32), ("syncfree", ctypes.c_int32),
+        ("queue", ctypes.c_int32)]
 
 
 class Precond(ctypes.Structure):
@@ -84,6 +85,8 @@ SIGNATURES = {
     "tri_plan_stats": (_i32, [_vp, _P(TriStats)]),
     "tri_plan_layout": (_i32, [_vp, _vp, _vp]),
     "tri_plan_trace": (_i32, [_vp, _vp, _i32]),
+    "tri_plan_set_wait_limit": (_i32, [_vp, ctypes.c_uint32]),
+    "tri_plan_check": (_i32, [_vp]),
     "tri_solve_lower": (_i32, [_vp, _vp, _vp, _i32, _i32, _vp]),
     "tri_solve_upper": (_i32, [_vp, _vp, _vp, _i32, _i32, _vp]),
     "tri_plan_destroy": (None, [_vp]),
@@ -322,6 +325,17 @@ def tri_plan_trace(plan, trace=None, stride=0):
     2*groups*stride entries receiving per-step start/end shader clocks."""
     ptr = ctypes.c_void_p(trace.data_ptr()) if trace is not None else None
     _check(lib().tri_plan_trace(plan.ptr, ptr, int(stride)))
+
+
+def tri_plan_set_wait_limit(plan, polls=0):
+    """Polls before a bounded device-side wait gives up (0 = default)."""
+    _check(lib().tri_plan_set_wait_limit(plan.ptr, int(polls)))
+
+
+def tri_plan_check(plan):
+    """Raise HecError(TIMEOUT) if an earlier launch of the plan aborted a wait
+    (and clear the flag); the caller synchronizes the stream first."""
+    _check(lib().tri_plan_check(plan.ptr))
 
 
 def tri_solve_lower(plan, b, x, stream=None):

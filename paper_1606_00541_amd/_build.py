@@ -39,9 +39,18 @@ def up_to_date() -> bool:
     return os.path.exists(LIB) and os.path.getmtime(LIB) >= _deps_mtime()
 
 
-def build(force: bool = True, verbose: bool = False) -> str:
+def _stale(src: str, obj: str) -> bool:
+    """An object older than its source or any header."""
+    if not os.path.exists(obj):
+        return True
+    deps = [src] + [os.path.join(CSRC, h) for h in HEADERS] + [os.path.join(ROOT, "include", "hec.h")]
+    return os.path.getmtime(obj) < max(os.path.getmtime(d) for d in deps)
+
+
+def build(force: bool = True, verbose: bool = False, incremental: bool = False) -> str:
     """Compile every translation unit and link libhec.so (always rebuilds
-    when ``force``)."""
+    when ``force``; with ``incremental`` only objects older than their
+    sources or headers are recompiled)."""
     if not force and up_to_date():
         return LIB
     os.makedirs(BUILD, exist_ok=True)
@@ -49,11 +58,13 @@ def build(force: bool = True, verbose: bool = False) -> str:
     objs = []
     for f in HOST_SRCS:
         o = os.path.join(BUILD, f + ".o")
-        jobs.append(["g++"] + HOST_FLAGS + ["-c", os.path.join(CSRC, f), "-o", o])
+        if not incremental or _stale(os.path.join(CSRC, f), o):
+            jobs.append(["g++"] + HOST_FLAGS + ["-c", os.path.join(CSRC, f), "-o", o])
         objs.append(o)
     for f in HIP_SRCS:
         o = os.path.join(BUILD, f + ".o")
-        jobs.append([HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, f), "-o", o])
+        if not incremental or _stale(os.path.join(CSRC, f), o):
+            jobs.append([HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, f), "-o", o])
         objs.append(o)
     procs = [(j, subprocess.Popen(j, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)) for j in jobs]
     failed = []
@@ -77,4 +88,4 @@ def build(force: bool = True, verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(force=True, verbose=True))
+    print(build(force=True, verbose=True, incremental="--incremental" in sys.argv))

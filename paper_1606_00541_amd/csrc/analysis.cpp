@@ -41,7 +41,7 @@ Tune tune_from(const hec_tune_t *t)
     u.chunk_rows = t->chunk_rows > 0 ? t->chunk_rows : std::max(256, u.block_threads);
     u.partition = t->partition;
     u.variant = t->kernel_variant;
-    if (u.variant < 0 || u.variant > 5) fail(HEC_ERR_INVALID_ARG, "tune.kernel_variant out of range");
+    if (u.variant < 0 || u.variant > 6) fail(HEC_ERR_INVALID_ARG, "tune.kernel_variant out of range");
     if (u.variant == 5 && u.schedule != HEC_SCHED_AUTO && u.schedule != HEC_SCHED_LEVEL_LAUNCH)
         fail(HEC_ERR_INVALID_ARG, "kernel_variant 5 runs the level-ordered layout (schedule AUTO or LEVEL_LAUNCH)");
     if (u.partition < 0 || u.partition > 3) fail(HEC_ERR_INVALID_ARG, "tune.partition out of range");
@@ -680,6 +680,88 @@ void make_dataflow(Schedule &s, ExecHost &ex, const std::vector<int32_t> &xlev,
     s.dataflow = true;
 }
 
+// Parts of the queue-mode dataflow kernel.  Every independent system (the
+// diagonal blocks sys_ptr, or the whole matrix) is cut into contiguous
+// ranges of the problem order (ascending rows for a lower triangle,
+// descending for an upper one), so a part reads only from earlier parts of
+// its own system: numbered system by system, the parts form a queue in
+// which each part depends on lower numbers only.  Systems come deepest
+// first (most levels, then most rows), so the longest dependency chains
+// start first.  A part whose LDS need (solution, right-hand side and imported
+// values, plus the index lists, bounded from above) exceeds the workgroup's
+// LDS is halved until every part fits.  Returns the part of every row and
+// sets `parts`.
+std::vector<int32_t> queue_parts(const Csr &a, bool upper, const Levels &lv, const std::vector<int32_t> *sys_ptr,
+                                 const Tune &tune, const DeviceShape &dev, hec_dtype_t dt, int32_t &parts)
+{
+    const int32_t n = a.n;
+    std::vector<int32_t> sp = sys_ptr && sys_ptr->size() >= 2 ? *sys_ptr : std::vector<int32_t>{0, n};
+    const int32_t nsys = (int32_t)sp.size() - 1;
+    const int32_t R = std::max(1, tune.max_nrhs);
+    const size_t ts = dt == HEC_F64 ? 8 : 4;
+    const size_t cap = dev.lds > 0 ? (size_t)dev.lds : 163840;
+    // a first cut: parts of about as many rows as the LDS holds with no imports
+    const int32_t prow = tune.part_rows > 0 ? tune.part_rows
+                                            : std::max<int32_t>(64, (int32_t)(cap / (2 * R * ts + 16)));
+    std::vector<int32_t> depth(nsys, 0);
+    for (int32_t q = 0; q < nsys; ++q)
+        for (int32_t i = sp[q]; i < sp[q + 1]; ++i) depth[q] = std::max(depth[q], lv.level[i]);
+    std::vector<int32_t> order(nsys);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+        if (depth[x] != depth[y]) return depth[x] > depth[y];
+        return sp[x + 1] - sp[x] > sp[y + 1] - sp[y];
+    });
+    // ranges of the problem order: [first, last) positions q, row = upper ? n-1-q : q
+    std::vector<std::pair<int32_t, int32_t>> ranges;
+    for (int32_t sy : order) {
+        const int32_t m = sp[sy + 1] - sp[sy];
+        if (m <= 0) continue;
+        const int32_t q0 = upper ? n - sp[sy + 1] : sp[sy];
+        const int32_t k = (m + prow - 1) / prow;
+        for (int32_t c = 0; c < k; ++c)
+            ranges.push_back({q0 + (int32_t)((int64_t)m * c / k), q0 + (int32_t)((int64_t)m * (c + 1) / k)});
+    }
+    auto row_at = [&](int32_t q) { return upper ? n - 1 - q : q; };
+    std::vector<int32_t> stamp(n, -1), seen(n, -1);
+    auto need = [&](int32_t q0, int32_t q1, int32_t tag) {
+        for (int32_t q = q0; q < q1; ++q) stamp[row_at(q)] = tag;
+        int64_t nimp = 0;
+        for (int32_t q = q0; q < q1; ++q) {
+            const int32_t i = row_at(q);
+            for (int32_t p = a.rp[i]; p < a.rp[i + 1]; ++p) {
+                const int32_t j = a.ci[p];
+                if (j == i || stamp[j] == tag || seen[j] == tag) continue;
+                seen[j] = tag;
+                ++nimp;
+            }
+        }
+        const int64_t win = q1 - q0;
+        return (size_t)(2 * win + nimp + 1) * R * ts + 4 * (size_t)(nimp + 3 * win) + 64;
+    };
+    std::vector<std::pair<int32_t, int32_t>> out;
+    int32_t tag = 0;
+    for (size_t r = 0; r < ranges.size(); ++r) {
+        std::vector<std::pair<int32_t, int32_t>> work{ranges[r]};
+        while (!work.empty()) {
+            auto cur = work.back();
+            work.pop_back();
+            if (cur.second - cur.first > 1 && need(cur.first, cur.second, tag++) > cap) {
+                const int32_t mid = cur.first + (cur.second - cur.first) / 2;
+                work.push_back({mid, cur.second});  // processed after the first half
+                work.push_back({cur.first, mid});
+                continue;
+            }
+            out.push_back(cur);
+        }
+    }
+    std::vector<int32_t> po(n, 0);
+    for (size_t g = 0; g < out.size(); ++g)
+        for (int32_t q = out[g].first; q < out[g].second; ++q) po[row_at(q)] = (int32_t)g;
+    parts = std::max<int32_t>(1, (int32_t)out.size());
+    return po;
+}
+
 }  // namespace
 
 void build_exec(TriHost &t, const Csr &a, const Tune &tune, const DeviceShape &dev,
@@ -710,7 +792,8 @@ void build_exec(TriHost &t, const Csr &a, const Tune &tune, const DeviceShape &d
     const int32_t R = std::max(1, tune.max_nrhs);
     const int32_t merge = tune.merge_rows > 0 ? tune.merge_rows : std::max(1, tune.block_threads / R);
     // the dataflow owner kernel: one wavefront per piece of a part
-    const bool want_df = kind == HEC_SCHED_OWNER_PERSISTENT && tune.variant == 4;
+    const bool want_df = kind == HEC_SCHED_OWNER_PERSISTENT && (tune.variant == 4 || tune.variant == 6);
+    const bool queue = want_df && tune.variant == 6;
     const int32_t df_waves = std::max(1, tune.block_threads / 64);
     std::vector<std::vector<int32_t>> run_wave;  // dataflow: wavefront of each run
 
@@ -747,7 +830,7 @@ void build_exec(TriHost &t, const Csr &a, const Tune &tune, const DeviceShape &d
         parts = std::max(1, std::min(parts, std::max(1, n)));
         std::vector<int32_t> part_of;
         int32_t gx = 0, gy = 0, gz = 0;
-        const bool grid = (tune.partition == 0 || tune.partition == 3) && detect_grid(a, gx, gy, gz);
+        const bool grid = !queue && (tune.partition == 0 || tune.partition == 3) && detect_grid(a, gx, gy, gz);
         auto contiguous = [&]() {
             std::vector<int32_t> po(n);
             for (int32_t g = 0; g < parts; ++g) {
@@ -756,7 +839,9 @@ void build_exec(TriHost &t, const Csr &a, const Tune &tune, const DeviceShape &d
             }
             return po;
         };
-        if (grid) {
+        if (queue) {
+            part_of = queue_parts(a, t.upper, lv, sys_ptr, tune, dev, t.dt, parts);
+        } else if (grid) {
             part_of = grid_parts(n, gx, gy, gz, parts);
             if (tune.partition == 0) {
                 // automatic: grid blocks unless contiguous ranges put fewer
@@ -812,7 +897,7 @@ void build_exec(TriHost &t, const Csr &a, const Tune &tune, const DeviceShape &d
         // share an L2 domain (workgroup i runs on domain i % xcds), so that
         // most part-to-part handoffs stay inside one XCD.
         const int32_t X = std::max(1, dev.xcds);
-        if (parts % X == 0 && parts >= X) {
+        if (!queue && parts % X == 0 && parts >= X) {
             const int32_t per = parts / X;
             std::vector<int32_t> gid(parts);
             for (int32_t p = 0; p < parts; ++p) gid[p] = (p % per) * X + p / per;
@@ -907,6 +992,7 @@ void build_exec(TriHost &t, const Csr &a, const Tune &tune, const DeviceShape &d
             std::vector<int32_t> xlev(n);
             for (int32_t x2 = 0; x2 < n; ++x2) xlev[x2] = lv.level[ex.orig[x2]];
             make_dataflow(ex.sched, ex, xlev, run_wave, df_waves);
+            ex.sched.queue = queue;
             const size_t lds_cap = dev.lds > 0 ? (size_t)dev.lds : 163840;
             const size_t need = dataflow_lds_bytes(ex.sched.df_rows, ex.sched.df_ints, R, t.dt == HEC_F64 ? 8 : 4);
             if (need > lds_cap)
@@ -938,7 +1024,7 @@ TriHost analyze(const Csr &a, bool upper, bool unit, hec_dtype_t dt, const Tune 
         // 1..8, 10, 12, 16).  Its CSR tail is read with an exposed load
         // latency on the dependency chain, so the automatic width covers the
         // longest row when that fits; padding costs bytes, not latency.
-        if (u.variant == 4 && u.schedule == HEC_SCHED_OWNER_PERSISTENT) {
+        if ((u.variant == 4 || u.variant == 6) && u.schedule == HEC_SCHED_OWNER_PERSISTENT) {
             if (u.ell_width < 0) {
                 int32_t wmax = 0;
                 for (int32_t i = 0; i < a.n; ++i) wmax = std::max(wmax, offdiag_count(a, i));
@@ -963,15 +1049,36 @@ TriHost analyze(const Csr &a, bool upper, bool unit, hec_dtype_t dt, const Tune 
     }
     const bool auto_sched = tu.schedule == HEC_SCHED_AUTO;
     if (auto_sched) tu.schedule = HEC_SCHED_OWNER_PERSISTENT;
+    if (tu.variant == 6) {
+        if (tu.schedule != HEC_SCHED_OWNER_PERSISTENT)
+            fail(HEC_ERR_INVALID_ARG, "kernel_variant 6 runs the owner schedule (schedule AUTO or OWNER_PERSISTENT)");
+        attempt(tu);
+        return t;
+    }
     if (tu.schedule == HEC_SCHED_OWNER_PERSISTENT && tu.variant == 0) {
         Tune d = tu;
         d.variant = 4;
-        if (d.block_threads <= 640 && d.max_nrhs <= 64 && d.ell_width <= 16) {
+        const bool df_ok = d.block_threads <= 640 && d.max_nrhs <= 64 && d.ell_width <= 16;
+        if (df_ok) {
             try {
                 attempt(d);
                 return t;
             } catch (const Error &e) {
                 if (e.code != HEC_ERR_CAPACITY) throw;
+            }
+            // too large for one part per workgroup: the same kernel with more
+            // parts than workgroups, taken from a queue (every part fits the
+            // LDS; parts are cut per system and split until they do)
+            if (auto_sched) {
+                d.variant = 6;
+                try {
+                    t.variant = 6;
+                    attempt(d);
+                    return t;
+                } catch (const Error &e) {
+                    if (e.code != HEC_ERR_CAPACITY) throw;
+                    t.variant = tu.variant;
+                }
             }
         }
         if (auto_sched) {

@@ -128,13 +128,14 @@ void upload_tri(DevTri &d, const TriHost &t, int32_t max_nrhs)
             d.df_rows = s.df_rows;
             d.df_ints = s.df_ints;
             d.df_waves = s.df_waves;
+            d.queue = s.queue;
             upload(d.wave_ptr, s.wave_ptr);
             d.df_step_rows = 0;
             for (int32_t q = 0; q < s.nsteps(); ++q)
                 d.df_step_rows = std::max(d.df_step_rows, s.step_row[2 * q + 1] - s.step_row[2 * q]);
         }
         d.max_lanes_one = std::all_of(s.step_lanes.begin(), s.step_lanes.end(), [](int32_t v) { return v == 1; });
-        d.epoch.alloc(2 * sizeof(unsigned int));
+        d.epoch.alloc(4 * sizeof(unsigned int));  // epoch, workgroups done, part queue
         hip_check(hipMemset(d.epoch.p, 0, d.epoch.bytes), "hipMemset");
     }
     d.err.alloc(sizeof(int));
@@ -149,15 +150,28 @@ void upload_tri(DevTri &d, const TriHost &t, int32_t max_nrhs)
     hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
 }
 
+namespace {
+// Read and clear a plan's abort flags; true if a launch had aborted.
+bool take_abort(const DevTri &d)
+{
+    if (!d.err_host) return false;
+    volatile int *f = d.err_host;
+    if (*f == 0) return false;
+    *f = 0;
+    (void)hipMemset(d.err.p, 0, sizeof(int));
+    return true;
+}
+}  // namespace
+
 void check_device_error(const DevTri &d)
 {
-    if (!d.err_host) return;
-    volatile int *f = d.err_host;
-    if (*f != 0) {
-        *f = 0;
-        (void)hipMemset(d.err.p, 0, sizeof(int));
-        fail(HEC_ERR_TIMEOUT, "a persistent solve aborted a device-side wait (spin limit reached)");
-    }
+    if (take_abort(d)) fail(HEC_ERR_TIMEOUT, "a persistent solve aborted a device-side wait (spin limit reached)");
+}
+
+void check_device_error(const DevTri &a, const DevTri &b)
+{
+    const bool ea = take_abort(a), eb = take_abort(b);  // both cleared: one report per abort
+    if (ea || eb) fail(HEC_ERR_TIMEOUT, "a persistent solve aborted a device-side wait (spin limit reached)");
 }
 
 }  // namespace hec
@@ -232,10 +246,13 @@ DeviceShape device_shape(const Tune &tu, hec_dtype_t dt)
     return s;
 }
 
-void build_plan(tri_plan_s &p, const Csr &a, bool upper, bool unit, hec_dtype_t dt, const Tune &tu)
+// blocks: independent diagonal blocks (batched systems, RAS subdomains) that
+// the owner schedule's queue mode cuts into parts separately
+void build_plan(tri_plan_s &p, const Csr &a, bool upper, bool unit, hec_dtype_t dt, const Tune &tu,
+                const std::vector<int32_t> *blocks = nullptr)
 {
     p.upper = upper;
-    p.h = analyze(a, upper, unit, dt, tu, device_shape(tu, dt));
+    p.h = analyze(a, upper, unit, dt, tu, device_shape(tu, dt), blocks);
     p.d.block = tu.block_threads;
     p.d.variant = p.h.variant;
     if (!tu.host_only) {
@@ -302,12 +319,13 @@ void factor(const Csr &a, hec_ilu_kind_t kind, int32_t k, double tol, int32_t p,
 
 // Plans of L (unit lower) and U, and the map joining them: U's solve reads L's
 // device-order output through qmap (eq. (1): y never returns to natural order).
-void build_ilu(ilu_s &f, const Csr &L, const Csr &U, hec_dtype_t fdt, const Tune &tu)
+void build_ilu(ilu_s &f, const Csr &L, const Csr &U, hec_dtype_t fdt, const Tune &tu,
+               const std::vector<int32_t> *blocks = nullptr)
 {
     f.n = L.n;
     f.fdt = fdt;
-    build_plan(f.L, L, false, true, fdt, tu);
-    build_plan(f.U, U, true, false, fdt, tu);
+    build_plan(f.L, L, false, true, fdt, tu, blocks);
+    build_plan(f.U, U, true, false, fdt, tu, blocks);
     if (!tu.host_only) {
         const int32_t n = L.n;
         std::vector<int32_t> q(n);
@@ -327,8 +345,7 @@ void ilu_apply_impl(ilu_s *f, const void *r, void *z, int32_t nrhs, hec_dtype_t 
     check_vec(vdt);
     require_device(f->L);
     if (f->n > 0 && (!r || !z)) fail(HEC_ERR_INVALID_ARG, "vector pointer is NULL");
-    check_device_error(f->L.d);
-    check_device_error(f->U.d);
+    check_device_error(f->L.d, f->U.d);
     ensure_workspace(f->L.d, nrhs);
     ensure_workspace(f->U.d, nrhs);
     f->L.d.act = f->U.d.act = act;
@@ -450,8 +467,7 @@ void ras_apply_impl(ras_s *s, const double *r, double *z, int32_t nrhs, hipStrea
     if (s->n > 0 && (!r || !z)) fail(HEC_ERR_INVALID_ARG, "vector pointer is NULL");
     if (r == z) fail(HEC_ERR_INVALID_ARG, "ras_apply needs distinct r and z");
     ilu_s &f = s->f;
-    check_device_error(f.L.d);
-    check_device_error(f.U.d);
+    check_device_error(f.L.d, f.U.d);
     ensure_workspace(f.L.d, nrhs);
     ensure_workspace(f.U.d, nrhs);
     // restriction fused into L's gather, restricted prolongation into U's scatter
@@ -480,6 +496,17 @@ void precond_check(const hec_precond_t &M, int32_t n)
         require_device(s->f.L);
     } else {
         fail(HEC_ERR_INVALID_ARG, "unknown preconditioner kind");
+    }
+}
+
+void precond_check_error(const hec_precond_t &M)
+{
+    if (M.kind == HEC_PRECOND_ILU) {
+        ilu_s *f = static_cast<ilu_s *>(M.handle);
+        check_device_error(f->L.d, f->U.d);
+    } else if (M.kind == HEC_PRECOND_RAS) {
+        ras_s *s = static_cast<ras_s *>(M.handle);
+        check_device_error(s->f.L.d, s->f.U.d);
     }
 }
 
@@ -566,6 +593,7 @@ hec_status_t tri_plan_stats(tri_plan_t p, tri_stats_t *s)
         s->crit_hops = h.ex.sched.crit_hops;
         s->dataflow = h.ex.sched.dataflow ? 1 : 0;
         s->syncfree = (h.ex.sched.kind == HEC_SCHED_LEVEL_LAUNCH && h.variant == 5) ? 1 : 0;
+        s->queue = h.ex.sched.dataflow && h.ex.sched.queue ? 1 : 0;
         s->unit_diag = h.unit ? 1 : 0;
         s->dtype = h.dt;
     });
@@ -586,6 +614,23 @@ hec_status_t tri_plan_trace(tri_plan_t p, void *trace, int32_t stride)
         if (!p || stride < 0) fail(HEC_ERR_INVALID_ARG, "bad arguments");
         p->d.trace = static_cast<unsigned long long *>(trace);
         p->d.trace_stride = trace ? stride : 0;
+    });
+}
+
+hec_status_t tri_plan_set_wait_limit(tri_plan_t p, uint32_t polls)
+{
+    return guard([&] {
+        if (!p) fail(HEC_ERR_INVALID_ARG, "plan is NULL");
+        if (polls > kMaxSpin) fail(HEC_ERR_INVALID_ARG, "wait limit above 2^27 polls");
+        p->d.spin = polls == 0 ? kDefaultSpin : polls;
+    });
+}
+
+hec_status_t tri_plan_check(tri_plan_t p)
+{
+    return guard([&] {
+        if (!p) fail(HEC_ERR_INVALID_ARG, "plan is NULL");
+        check_device_error(p->d);
     });
 }
 
@@ -640,7 +685,7 @@ hec_status_t batch_setup(int32_t n, const int32_t *rowptr, const int32_t *col, c
         f->sys_ptr.assign(sys_ptr, sys_ptr + nsys + 1);
         factor(a, kind, k, tol, p, f->Lf, f->Uf, &f->sys_ptr);
         f->kind = kind;
-        build_ilu(*f, f->Lf, f->Uf, fdt, tu);
+        build_ilu(*f, f->Lf, f->Uf, fdt, tu, &f->sys_ptr);
         if (!tu.host_only) {
             // device row -> system, so that a solve can skip finished problems
             for (tri_plan_s *pl : {&f->L, &f->U}) {
@@ -701,11 +746,15 @@ hec_status_t ilu_refactor(ilu_t f, const int32_t *rowptr, const int32_t *col, co
                               std::equal(f->rf->a_rp.begin(), f->rf->a_rp.end(), rowptr) &&
                               (int64_t)f->rf->a_ci.size() == (int64_t)rowptr[n] &&
                               std::equal(f->rf->a_ci.begin(), f->rf->a_ci.end(), col);
-            if (!same) build_refactor(*f, rowptr, col);
+            if (!same) {
+                // the new maps start without factors: bring the current ones
+                // (held only by the device) to the host first
+                sync_host_factors(*f);
+                build_refactor(*f, rowptr, col);
+            }
         }
         if (f->rf->nnz_a > 0 && !val) fail(HEC_ERR_INVALID_ARG, "val is NULL");
-        check_device_error(f->L.d);
-        check_device_error(f->U.d);
+        check_device_error(f->L.d, f->U.d);
         refactor_numeric(*f->rf, val, st);
         refactor_refill(*f->rf, f->L.d, f->U.d, st);
         f->dev_newer = true;
@@ -752,8 +801,7 @@ hec_status_t ras_refactor(ras_t s, const int32_t *rowptr, const int32_t *col, co
             }
         }
         if (s->lay.blockdiag.nnz() > 0 && !val) fail(HEC_ERR_INVALID_ARG, "val is NULL");
-        check_device_error(f.L.d);
-        check_device_error(f.U.d);
+        check_device_error(f.L.d, f.U.d);
         gather_f64(val, s->a2bd.as<int32_t>(), s->lay.blockdiag.nnz(), s->bdval.as<double>(), st);
         refactor_numeric(*f.rf, s->bdval.as<double>(), st);
         refactor_refill(*f.rf, f.L.d, f.U.d, st);
@@ -784,7 +832,7 @@ hec_status_t ras_setup_ilu(int32_t n, const int32_t *rowptr, const int32_t *col,
         ilu_s &f = s->f;
         factor(s->lay.blockdiag, kind, k, tol, p, f.Lf, f.Uf, &s->lay.ext_ptr);
         f.kind = kind;
-        build_ilu(f, f.Lf, f.Uf, fdt, tu);
+        build_ilu(f, f.Lf, f.Uf, fdt, tu, &s->lay.ext_ptr);
         if (!tu.host_only) {
             const int32_t m = s->lay.blockdiag.n;
             std::vector<int32_t> g(m), sc(m);
@@ -1050,6 +1098,8 @@ hec_status_t tri_autotune(int32_t n, const int32_t *rowptr, const int32_t *col, 
                 for (int rep = 0; rep < reps; ++rep) solve_one(&p, b.p, x.p, nrhs, vdt, st, upper);
                 hip_check(hipEventRecord(e1, st), "hipEventRecord");
                 hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+                // a candidate whose waits gave up exits early: never time it
+                check_device_error(p.d);
                 float ms = 0.f;
                 hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
                 const double us = 1000.0 * ms / reps;
@@ -1058,7 +1108,7 @@ hec_status_t tri_autotune(int32_t n, const int32_t *rowptr, const int32_t *col, 
                     best_tune = t;
                 }
             } catch (const Error &e) {
-                if (e.code != HEC_ERR_CAPACITY && e.code != HEC_ERR_ALLOC) {
+                if (e.code != HEC_ERR_CAPACITY && e.code != HEC_ERR_ALLOC && e.code != HEC_ERR_TIMEOUT) {
                     (void)hipEventDestroy(e0);
                     (void)hipEventDestroy(e1);
                     throw;

@@ -112,7 +112,16 @@ struct TriArgs {
     int32_t write_xw;            // persistent: also store every row to xw
     unsigned long long *trace;   // optional per-step clocks [groups][trace_stride][2]
     int32_t trace_stride;
+    unsigned spin;               // polls before a bounded wait gives up
+    int32_t nparts;              // dataflow kernel: parts of the plan
+    int32_t queue;               // dataflow kernel: workgroups take parts from a counter (epoch[2])
 };
+
+// Polls of a bounded device-side wait before it is declared hung (a plan may
+// set its own, tri_plan_set_wait_limit); at most kMaxSpin so that the
+// sixteen-fold limit of LDS polls stays within 32 bits.
+constexpr unsigned kDefaultSpin = 1u << 22;
+constexpr unsigned kMaxSpin = 1u << 27;
 
 // Device copy of one triangular plan.
 struct DevTri {
@@ -132,6 +141,7 @@ struct DevTri {
     int32_t df_waves = 0;          // compute wavefronts per group (block = 64 * df_waves + 128)
     int32_t df_rows = 0, df_ints = 0;
     int32_t df_step_rows = 0;      // longest step (one wavefront covers step rows x nrhs)
+    bool queue = false;            // dataflow parts taken from a counter (more parts than workgroups)
     int32_t chunk_rows = 0;
     bool max_lanes_one = true;     // every step runs one thread per (row, rhs)
     DevMem epoch, err, mbox;
@@ -141,6 +151,7 @@ struct DevTri {
     int32_t ws_R = 0;
     unsigned long long *trace = nullptr;  // caller-owned profiling buffer
     int32_t trace_stride = 0;
+    unsigned spin = kDefaultSpin;         // bounded-wait limit of this plan's launches
     ~DevTri();
 };
 
@@ -156,10 +167,13 @@ struct DevRefactor {
     std::vector<int32_t> a_rp, a_ci;      // pattern of A the map was built for
     std::vector<int32_t> levelptr;        // levels of L (host bounds into rows)
     DevMem a2f, frp, fci, fdpos, fval, rows, err;
+    DevMem fwork;                         // elimination target; swapped with fval on success
     DevMem l_src, l_dst, u_src, u_dst, u_diag, d_src;
 };
 // Scatter A's device values into F and eliminate level by level; synchronizes
-// `st` and throws ZERO_PIVOT on a zero or non-finite pivot.
+// `st` and throws ZERO_PIVOT on a zero or non-finite pivot.  The elimination
+// runs in fwork, which replaces fval only on success: after a failure fval
+// still holds the last good factors.
 void refactor_numeric(DevRefactor &r, const double *aval, hipStream_t st);
 // Write F's values into the plans (L as is, U scaled by its reciprocal
 // diagonal, U's reciprocal diagonal array).
@@ -181,6 +195,8 @@ void launch_tri(DevTri &d, const void *bin, hec_dtype_t in_dt, const int32_t *ga
                 void *xout, hec_dtype_t out_dt, const int32_t *scatter, int32_t R, hipStream_t st);
 // Throws HEC_ERR_TIMEOUT if a persistent launch of this plan aborted a wait.
 void check_device_error(const DevTri &d);
+// Both plans of a preconditioner: clears both flags, throws once.
+void check_device_error(const DevTri &a, const DevTri &b);
 
 // ---- Krylov / SpMV / vector support (krylov.hip) ----
 struct DevHec {   // general HEC matrix for y = A x

@@ -92,6 +92,9 @@ struct Schedule {
     int32_t df_ints = 0;             // max over groups of imports + exports + 2 * steps
     int32_t df_waves = 0;            // compute wavefronts per group
     std::vector<int32_t> wave_ptr;   // [groups*df_waves+1]: steps of wavefront w of group g
+    // queue mode: `groups` parts, more than the workgroups that run them; the
+    // parts are numbered so that every part reads only lower-numbered ones
+    bool queue = false;
     int32_t nsteps() const { return (int32_t)step_lanes.size(); }
 };
 

@@ -158,14 +158,19 @@ struct LinArgs {
     double *out2;        // optional second output receiving the same value
 };
 
-// out[:,c] = sum_t coef[t][c] * in_t[:,c]
+// out[:,c] = sum_t coef[t][c] * in_t[:,c]; terms with a zero coefficient are
+// left out, so a stopped problem's stale vectors (possibly NaN) never reach
+// its output
 __global__ void __launch_bounds__(256) k_lincomb(LinArgs a, long total, int R, int P, const int32_t *seg)
 {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total) return;
     const int c = col_of(t, R, seg);
     double s = 0.0;
-    for (int q = 0; q < a.nt; ++q) s += a.coef[q * P + c] * a.in[q][t];
+    for (int q = 0; q < a.nt; ++q) {
+        const double cf = a.coef[q * P + c];
+        if (cf != 0.0) s += cf * a.in[q][t];
+    }
     a.out[t] = s;
     if (a.out2) a.out2[t] = s;
 }
@@ -184,13 +189,17 @@ __global__ void __launch_bounds__(256) k_gs_update(double *w, const double *V, l
     w[t] = s;
 }
 
-// x[:,c] += sum_{i<nv} y[i][c] * Z_i[:,c]
-__global__ void __launch_bounds__(256) k_basis_update(double *x, const double *Z, long stride, const double *y, int nv,
-                                                     long total, int R, int P, const int32_t *seg)
+// x[:,c] += sum_{i<kd[c]} y[i][c] * Z_i[:,c]: each problem sums only the
+// basis vectors it built in this cycle (the others hold whatever an earlier
+// use of the memory left there, possibly a NaN pattern)
+__global__ void __launch_bounds__(256) k_basis_update(double *x, const double *Z, long stride, const double *y,
+                                                     const int32_t *kd, long total, int R, int P, const int32_t *seg)
 {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total) return;
     const int c = col_of(t, R, seg);
+    const int nv = kd[c];
+    if (nv == 0) return;
     double s = 0.0;
     for (int i = 0; i < nv; ++i) s += y[i * P + c] * Z[i * stride + t];
     x[t] += s;
@@ -204,8 +213,8 @@ __global__ void __launch_bounds__(256) k_normalize(double *v, const double *w, c
     if (t >= total) return;
     const int c = col_of(t, R, seg);
     const double hn = sqrt(fmax(0.0, d[c]));
-    const double cf = (act[c] && hn > 0.0) ? 1.0 / hn : 0.0;
-    v[t] = cf * w[t];
+    // a stopped problem gets exact zeros, whatever its w holds
+    v[t] = (act[c] && hn > 0.0) ? (1.0 / hn) * w[t] : 0.0;
 }
 
 template <typename TS, typename TD>
@@ -213,6 +222,74 @@ __global__ void __launch_bounds__(256) k_convert(const TS *s, TD *d, long count)
 {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < count) d[t] = (TD)s[t];
+}
+
+__global__ void __launch_bounds__(256) k_fill_i32(int32_t *p, long count, int32_t v)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < count) p[t] = v;
+}
+
+// One Arnoldi step's small work, one thread per problem c still active:
+// the new Hessenberg column h_{0..j+1, j} (the two Gram-Schmidt passes'
+// coefficients summed, and ||w||), the earlier Givens rotations applied to
+// it, a new rotation annihilating h_{j+1,j}, the rotated right-hand side g,
+// and the stopping test |g_{j+1}| / ||b|| <= rtol.  A zero or non-finite
+// column stops the problem with BREAKDOWN and leaves its basis at j
+// vectors.  H holds the rotated upper triangle, column j at H[(j*m + i)*P + c].
+__global__ void __launch_bounds__(256) k_arnoldi(int j, int m, int P, const double *d1, const double *d2,
+                                                 const double *dn, double *H, double *cs, double *sn, double *g,
+                                                 const double *bnorm, double rtol, int maxit, int8_t *act,
+                                                 int32_t *kdim, int32_t *iters, int32_t *status, int32_t *flag)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= P || !act[c]) return;
+    double h[kMaxPairs + 1];
+    for (int i = 0; i <= j; ++i) h[i] = d1[i * P + c] + d2[i * P + c];
+    const double hn = sqrt(fmax(0.0, dn[c]));
+    h[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+        const double ci = cs[i * P + c], si = sn[i * P + c];
+        const double t = ci * h[i] + si * h[i + 1];
+        h[i + 1] = -si * h[i] + ci * h[i + 1];
+        h[i] = t;
+    }
+    const int it = iters[c] + 1;
+    iters[c] = it;
+    const double den = hypot(h[j], h[j + 1]);
+    if (!(den > 0.0) || !isfinite(den)) {
+        status[c] = HEC_ERR_BREAKDOWN;
+        act[c] = 0;
+        return;
+    }
+    const double cj = h[j] / den, sj = h[j + 1] / den;
+    cs[j * P + c] = cj;
+    sn[j * P + c] = sj;
+    for (int i = 0; i < j; ++i) H[((size_t)j * m + i) * P + c] = h[i];
+    H[((size_t)j * m + j) * P + c] = den;
+    const double gj = g[j * P + c];
+    g[(j + 1) * P + c] = -sj * gj;
+    g[j * P + c] = cj * gj;
+    kdim[c] = j + 1;
+    if (fabs(g[(j + 1) * P + c]) / bnorm[c] <= rtol || hn == 0.0 || it >= maxit) act[c] = 0;
+    else atomicOr(flag + j, 1);
+}
+
+// y = R^{-1} g per problem over its kdim[c] columns (back substitution on the
+// rotated Hessenberg triangle); counts a completed cycle for every problem
+// that extended its basis.
+__global__ void __launch_bounds__(256) k_hess_solve(int m, int P, const double *H, const double *g,
+                                                    const int32_t *kdim, double *y, int32_t *restarts)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= P) return;
+    const int kk = kdim[c];
+    for (int i = kk - 1; i >= 0; --i) {
+        double s = g[i * P + c];
+        for (int l = i + 1; l < kk; ++l) s -= H[((size_t)l * m + i) * P + c] * y[l * P + c];
+        y[i * P + c] = s / H[((size_t)i * m + i) * P + c];
+    }
+    if (kk > 0) restarts[c] += 1;
 }
 
 inline int blocks_for(long total) { return (int)std::max<long>(1, (total + 255) / 256); }
@@ -271,7 +348,7 @@ struct Ctx {
     int R, P;
     DevMem partial, dots, coef, segm, browm, bptrm, bsysm;
     DevMem d1m, d2m, dnm, actm;     // device-resident Gram-Schmidt coefficients and active mask
-    double *hb2 = nullptr;          // pinned: [2*kMaxPairs + 1][P] copies of d1, d2, dn
+    DevMem kdm;                     // basis length of each problem in the current cycle
     int8_t *hact = nullptr;         // pinned staging of the active mask
     const int32_t *seg = nullptr;  // row -> system (batches only)
     double *hbuf = nullptr;        // pinned host scalars
@@ -316,13 +393,12 @@ struct Ctx {
         d2m.alloc(sizeof(double) * kMaxPairs * P);
         dnm.alloc(sizeof(double) * P);
         actm.alloc((size_t)P);
-        hip_check(hipHostMalloc((void **)&hb2, sizeof(double) * (2 * (size_t)kMaxPairs + 1) * P, 0), "hipHostMalloc");
+        kdm.alloc(sizeof(int32_t) * (size_t)P);
         hip_check(hipHostMalloc((void **)&hact, (size_t)P, 0), "hipHostMalloc");
     }
     ~Ctx()
     {
         if (hbuf) (void)hipHostFree(hbuf);
-        if (hb2) (void)hipHostFree(hb2);
         if (hact) (void)hipHostFree(hact);
     }
     // inner products of np pairs, per problem, into out[p*P + c] on the device
@@ -401,6 +477,9 @@ namespace hec {
 void precond_apply(const hec_precond_t &M, const double *r, double *z, int32_t R, hipStream_t st,
                    const int8_t *act = nullptr);
 void precond_check(const hec_precond_t &M, int32_t n);
+// Throws HEC_ERR_TIMEOUT if an application of M aborted a device-side wait
+// (the stream must have been synchronized).
+void precond_check_error(const hec_precond_t &M);
 }  // namespace hec
 
 using namespace hec;
@@ -417,10 +496,40 @@ void apply_M(const hec_precond_t &M, const double *r, double *z, int R, long n, 
     precond_apply(M, r, z, R, st, act);
 }
 
+// Final outcome of every problem from its true residual norm^2 rr2[k]: a
+// finite relative residual at most rtol is a success (also after a lucky
+// breakdown); otherwise a problem keeps the error it stopped with
+// (INVALID_ARG: non-finite b; BREAKDOWN: zero or non-finite scalars) or is
+// NOT_CONVERGED.  A NaN never compares as converged.  The call returns the
+// first INVALID_ARG or BREAKDOWN, else the first NOT_CONVERGED, else OK.
+hec_status_t final_status(hec_krylov_info_t *info, const std::vector<double> &bnorm, const double *rr2, int P,
+                          double rtol, hec_status_t hint)
+{
+    hec_status_t out = HEC_OK;
+    for (int k = 0; k < P; ++k) {
+        const double rn = std::sqrt(rr2[k]);
+        info[k].relres = !std::isfinite(bnorm[k]) ? std::nan("") : (bnorm[k] > 0 ? rn / bnorm[k] : rn);
+        if (info[k].status != HEC_ERR_INVALID_ARG && info[k].relres <= rtol) {
+            info[k].status = HEC_OK;
+            continue;
+        }
+        if (info[k].status == HEC_OK)
+            info[k].status = hint == HEC_ERR_BREAKDOWN ? HEC_ERR_BREAKDOWN : HEC_ERR_NOT_CONVERGED;
+        if (out == HEC_OK || (out == HEC_ERR_NOT_CONVERGED && info[k].status != HEC_ERR_NOT_CONVERGED))
+            out = (hec_status_t)info[k].status;
+    }
+    return out;
+}
+
 // Restarted (F)GMRES(m): right preconditioning with the preconditioned basis
-// Z stored (flexible form), CGS with one re-orthogonalization, Givens
-// rotations on the host.  Every RHS runs its own Arnoldi process in lockstep;
-// an RHS whose rotated residual reaches rtol stops extending its basis.
+// Z stored (flexible form), CGS with one re-orthogonalization.  Every
+// problem runs its own Arnoldi process in lockstep with the others; the
+// Hessenberg columns, Givens rotations, rotated residual and each problem's
+// stopping test live on the device (k_arnoldi), so the host does not wait
+// for a step to finish before issuing the next: it keeps two steps in
+// flight and reads back one "any problem still active" flag per step, then
+// synchronizes once per restart cycle for the true residual.  A problem whose
+// rotated residual reaches rtol stops extending its basis.
 hec_status_t gmres(const DevHec &A, const hec_precond_t &M, int m, const double *b, double *x, int R, double rtol,
                    int maxit, hec_krylov_info_t *info, hipStream_t st, int nsys, const int32_t *sys_ptr)
 {
@@ -428,16 +537,37 @@ hec_status_t gmres(const DevHec &A, const hec_precond_t &M, int m, const double 
     const long nR = n * R;
     Ctx c(n, R, st, nsys, sys_ptr);
     const int P = c.P;
-    DevMem Vm, Zm, wm, rm;
+    DevMem Vm, Zm, wm, rm, Hm, csm, snm, gm, bnm, cnt, flg;
     Vm.alloc(sizeof(double) * (size_t)(m + 1) * nR);
     Zm.alloc(sizeof(double) * (size_t)m * nR);
     wm.alloc(sizeof(double) * (size_t)nR);
     rm.alloc(sizeof(double) * (size_t)nR);
+    Hm.alloc(sizeof(double) * (size_t)m * m * P);     // upper triangle of the rotated H, [j][i][P]
+    csm.alloc(sizeof(double) * (size_t)m * P);
+    snm.alloc(sizeof(double) * (size_t)m * P);
+    gm.alloc(sizeof(double) * (size_t)(m + 1) * P);
+    bnm.alloc(sizeof(double) * (size_t)P);
+    cnt.alloc(sizeof(int32_t) * 4 * (size_t)P);        // iters, restarts, status, spare
+    flg.alloc(sizeof(int32_t) * (size_t)m);            // per step: some problem still active
     double *V = Vm.as<double>(), *Z = Zm.as<double>(), *w = wm.as<double>(), *r = rm.as<double>();
+    int32_t *d_iters = cnt.as<int32_t>(), *d_rest = d_iters + P, *d_stat = d_iters + 2 * P;
     auto Vi = [&](int i) { return V + (size_t)i * nR; };
     auto Zi = [&](int i) { return Z + (size_t)i * nR; };
+    int32_t *hflag = nullptr;
+    hip_check(hipHostMalloc((void **)&hflag, sizeof(int32_t) * (size_t)m, 0), "hipHostMalloc");
+    std::unique_ptr<int32_t, void (*)(int32_t *)> hflag_own(hflag, [](int32_t *q) { (void)hipHostFree(q); });
+    std::vector<hipEvent_t> ev(m, nullptr);
+    for (auto &e : ev) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+    struct EvFree {
+        std::vector<hipEvent_t> *v;
+        ~EvFree()
+        {
+            for (auto e : *v)
+                if (e) (void)hipEventDestroy(e);
+        }
+    } ev_free{&ev};
 
-    std::vector<double> bnorm(P), relres(P, 0.0);
+    std::vector<double> bnorm(P);
     {
         const double *a[1] = {b};
         c.dots_to_host(a, a, 1);
@@ -445,9 +575,16 @@ hec_status_t gmres(const DevHec &A, const hec_precond_t &M, int m, const double 
     }
     std::vector<char> done(P, 0);
     bool zero_rhs = false;
+    hec_status_t status = HEC_OK;
     for (int k = 0; k < P; ++k) {
         info[k] = hec_krylov_info_t{HEC_OK, 0, 0, 0, 0.0};
-        if (bnorm[k] == 0.0) done[k] = 1, zero_rhs = true;
+        if (!std::isfinite(bnorm[k])) {
+            // a NaN or infinity in b: this problem is not iterated
+            done[k] = 1;
+            info[k].status = HEC_ERR_INVALID_ARG;
+        } else if (bnorm[k] == 0.0) {
+            done[k] = 1, zero_rhs = true;
+        }
     }
     if (zero_rhs) {
         // a zero right-hand side has the solution x = 0
@@ -455,16 +592,21 @@ hec_status_t gmres(const DevHec &A, const hec_precond_t &M, int m, const double 
         for (int k = 0; k < P; ++k) keep[k] = bnorm[k] == 0.0 ? 0.0 : 1.0;
         c.lincomb(x, {x}, keep);
     }
-    std::vector<double> H((size_t)(m + 1) * m * P), cs((size_t)m * P), sn((size_t)m * P), g((size_t)(m + 1) * P);
-    auto h_at = [&](int i, int j, int k) -> double & { return H[((size_t)i * m + j) * P + k]; };
-    std::vector<int> kdim(P, 0);
-    std::vector<char> active(P, 0);
+    {
+        std::vector<double> bn(bnorm);
+        for (double &v : bn) v = std::isfinite(v) && v > 0 ? v : 1.0;
+        c.upload_coef(bn);
+        hip_check(hipMemcpyAsync(bnm.p, c.coef.p, sizeof(double) * P, hipMemcpyDeviceToDevice, st), "copy");
+    }
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(4L * P)), dim3(256), 0, st, d_iters, 4L * P, 0);
+    hip_check(hipGetLastError(), "k_fill_i32");
+    std::vector<int32_t> hcnt(4 * (size_t)P, 0);
     std::vector<const double *> pa(kMaxPairs), pb(kMaxPairs);
-    int iters = 0;
-    hec_status_t status = HEC_OK;
     for (;;) {
-        // true residual and convergence test
+        // true residual and convergence test (the one full synchronization
+        // of a restart cycle)
         residual(A, b, x, r, R, st);
+        hip_check(hipMemcpyAsync(hcnt.data(), d_iters, sizeof(int32_t) * 4 * P, hipMemcpyDeviceToHost, st), "D2H");
         {
             const double *a[1] = {r};
             c.dots_to_host(a, a, 1);
@@ -473,33 +615,51 @@ hec_status_t gmres(const DevHec &A, const hec_precond_t &M, int m, const double 
         std::vector<double> beta(P);
         for (int k = 0; k < P; ++k) {
             beta[k] = std::sqrt(c.hbuf[k]);
-            relres[k] = bnorm[k] > 0 ? beta[k] / bnorm[k] : 0.0;
-            if (bnorm[k] == 0.0 || relres[k] <= rtol) done[k] = 1;
-            active[k] = !done[k];
-            any = any || active[k];
+            const double rr = bnorm[k] > 0 ? beta[k] / bnorm[k] : 0.0;
+            if (!done[k]) {
+                if (hcnt[2 * P + k] == HEC_ERR_BREAKDOWN || !std::isfinite(rr)) {
+                    // a zero or non-finite Hessenberg column, or a non-finite
+                    // iterate: stop this problem
+                    done[k] = 1;
+                    info[k].status = HEC_ERR_BREAKDOWN;
+                } else if (rr <= rtol) {
+                    done[k] = 1;
+                }
+            }
+            any = any || !done[k];
         }
+        int max_iters = 0;
+        for (int k = 0; k < P; ++k) max_iters = std::max(max_iters, done[k] ? 0 : (int)hcnt[k]);
         if (!any) break;
-        if (iters >= maxit) {
+        if (max_iters >= maxit) {
             status = HEC_ERR_NOT_CONVERGED;
             break;
         }
-        // v_0 = r / beta
+        // v_0 = r / beta, g = beta e_1, active mask
         std::vector<double> cf(P);
-        for (int k = 0; k < P; ++k) cf[k] = active[k] ? 1.0 / beta[k] : 0.0;
+        for (int k = 0; k < P; ++k) cf[k] = done[k] ? 0.0 : 1.0 / beta[k];
         c.lincomb(Vi(0), {r}, cf);
+        std::vector<double> g0((size_t)(m + 1) * P, 0.0);
+        for (int k = 0; k < P; ++k) g0[k] = done[k] ? 0.0 : beta[k];
+        c.upload_coef(g0);
+        hip_check(hipMemcpyAsync(gm.p, c.coef.p, sizeof(double) * (m + 1) * P, hipMemcpyDeviceToDevice, st), "copy");
+        std::vector<char> active(P);
+        for (int k = 0; k < P; ++k) active[k] = !done[k];
         c.upload_active(active);
-        std::fill(g.begin(), g.end(), 0.0);
-        for (int k = 0; k < P; ++k) {
-            g[k] = active[k] ? beta[k] : 0.0;
-            kdim[k] = 0;
-        }
-        int j = 0;
-        for (; j < m; ++j) {
+        hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(P)), dim3(256), 0, st, c.kdm.as<int32_t>(), (long)P, 0);
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, flg.as<int32_t>(), (long)m, 0);
+        hip_check(hipGetLastError(), "k_fill_i32");
+        int steps = 0;
+        for (int j = 0; j < m; ++j) {
+            // two steps stay in flight: before issuing step j, wait for step
+            // j-2 and stop if it left no problem active
+            if (j >= 2) {
+                hip_check(hipEventSynchronize(ev[j - 2]), "hipEventSynchronize");
+                if (!hflag[j - 2]) break;
+            }
             // problems already finished are skipped (their basis stops growing)
             apply_M(M, Vi(j), Zi(j), R, n, st, c.actm.as<int8_t>());
             spmv(A, Zi(j), w, R, st);
-            // two passes of classical Gram-Schmidt, coefficients kept on the
-            // device; the Hessenberg column reaches the host once per step
             for (int i = 0; i <= j; ++i) {
                 pa[i] = Vi(i);
                 pb[i] = w;
@@ -515,94 +675,42 @@ hec_status_t gmres(const DevHec &A, const hec_precond_t &M, int m, const double 
                 const double *a[1] = {w};
                 c.dots_dev(a, a, 1, c.dnm.as<double>(), c.actm.as<int8_t>());
             }
+            // v_{j+1} = w / h_{j+1,j} for the problems still active at step j
             hipLaunchKernelGGL(k_normalize, dim3(blocks_for(nR)), dim3(256), 0, st, Vi(j + 1), w, c.dnm.as<double>(),
                                c.actm.as<int8_t>(), nR, R, c.seg);
-            hip_check(hipGetLastError(), "k_normalize");
-            const size_t hb = (size_t)(j + 1) * P;
-            hip_check(hipMemcpyAsync(c.hb2, c.d1m.p, sizeof(double) * hb, hipMemcpyDeviceToHost, st), "D2H");
-            hip_check(hipMemcpyAsync(c.hb2 + (size_t)kMaxPairs * P, c.d2m.p, sizeof(double) * hb,
-                                     hipMemcpyDeviceToHost, st), "D2H");
-            hip_check(hipMemcpyAsync(c.hb2 + 2 * (size_t)kMaxPairs * P, c.dnm.p, sizeof(double) * P,
-                                     hipMemcpyDeviceToHost, st), "D2H");
-            hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
-            std::vector<double> hcol(hb);
-            for (size_t q = 0; q < hb; ++q) hcol[q] = c.hb2[q] + c.hb2[(size_t)kMaxPairs * P + q];
-            std::vector<double> hn(P);
-            for (int k = 0; k < P; ++k) hn[k] = std::sqrt(std::max(0.0, c.hb2[2 * (size_t)kMaxPairs * P + k]));
-            ++iters;
-            bool still = false;
-            for (int k = 0; k < P; ++k) {
-                if (!active[k]) continue;
-                info[k].iters += 1;
-                info[k].precond_applies += 1;
-                for (int i = 0; i <= j; ++i) h_at(i, j, k) = hcol[(size_t)i * P + k];
-                h_at(j + 1, j, k) = hn[k];
-                for (int i = 0; i < j; ++i) {
-                    const double t = cs[i * P + k] * h_at(i, j, k) + sn[i * P + k] * h_at(i + 1, j, k);
-                    h_at(i + 1, j, k) = -sn[i * P + k] * h_at(i, j, k) + cs[i * P + k] * h_at(i + 1, j, k);
-                    h_at(i, j, k) = t;
-                }
-                const double den = std::hypot(h_at(j, j, k), h_at(j + 1, j, k));
-                if (den == 0.0) {
-                    status = HEC_ERR_BREAKDOWN;
-                    info[k].status = HEC_ERR_BREAKDOWN;
-                    active[k] = 0;
-                    done[k] = 1;
-                    continue;
-                }
-                cs[j * P + k] = h_at(j, j, k) / den;
-                sn[j * P + k] = h_at(j + 1, j, k) / den;
-                h_at(j, j, k) = den;
-                h_at(j + 1, j, k) = 0.0;
-                g[(j + 1) * P + k] = -sn[j * P + k] * g[j * P + k];
-                g[j * P + k] = cs[j * P + k] * g[j * P + k];
-                kdim[k] = j + 1;
-                if (std::fabs(g[(j + 1) * P + k]) / bnorm[k] <= rtol || hn[k] == 0.0 || iters >= maxit)
-                    active[k] = 0;
-                still = still || active[k];
-            }
-            c.upload_active(active);
-            if (!still) {
-                ++j;
-                break;
-            }
+            hipLaunchKernelGGL(k_arnoldi, dim3(blocks_for(P)), dim3(256), 0, st, j, m, P, c.d1m.as<double>(),
+                               c.d2m.as<double>(), c.dnm.as<double>(), Hm.as<double>(), csm.as<double>(),
+                               snm.as<double>(), gm.as<double>(), bnm.as<double>(), rtol, maxit, c.actm.as<int8_t>(),
+                               c.kdm.as<int32_t>(), d_iters, d_stat, flg.as<int32_t>());
+            hip_check(hipGetLastError(), "k_arnoldi");
+            hip_check(hipMemcpyAsync(hflag + j, flg.as<int32_t>() + j, sizeof(int32_t), hipMemcpyDeviceToHost, st),
+                      "D2H");
+            hip_check(hipEventRecord(ev[j], st), "hipEventRecord");
+            ++steps;
         }
-        // y = H^{-1} g per RHS, x += Z y
-        const int nv = *std::max_element(kdim.begin(), kdim.end());
-        if (nv > 0) {
-            std::vector<double> y((size_t)nv * P, 0.0);
-            for (int k = 0; k < P; ++k) {
-                const int kk = kdim[k];
-                for (int i = kk - 1; i >= 0; --i) {
-                    double s = g[i * P + k];
-                    for (int l = i + 1; l < kk; ++l) s -= h_at(i, l, k) * y[l * P + k];
-                    y[i * P + k] = s / h_at(i, i, k);
-                }
-                if (kk > 0) info[k].restarts += 1;
-            }
-            c.upload_coef(y);
+        // y = H^{-1} g per problem, x += Z y (each problem over its own basis)
+        if (steps > 0) {
+            hipLaunchKernelGGL(k_hess_solve, dim3(blocks_for(P)), dim3(256), 0, st, m, P, Hm.as<double>(),
+                               gm.as<double>(), c.kdm.as<int32_t>(), c.coef.as<double>(), d_rest);
             hipLaunchKernelGGL(k_basis_update, dim3(blocks_for(nR)), dim3(256), 0, st, x, Z, nR, c.coef.as<double>(),
-                               nv, nR, R, P, c.seg);
+                               c.kdm.as<int32_t>(), nR, R, P, c.seg);
             hip_check(hipGetLastError(), "k_basis_update");
         }
-        if (status == HEC_ERR_BREAKDOWN) {
-            // keep the partial update; the final residual decides
-        }
     }
+    hip_check(hipMemcpyAsync(hcnt.data(), d_iters, sizeof(int32_t) * 4 * P, hipMemcpyDeviceToHost, st), "D2H");
     residual(A, b, x, r, R, st);
     {
         const double *a[1] = {r};
         c.dots_to_host(a, a, 1);
     }
-    hec_status_t out = HEC_OK;
     for (int k = 0; k < P; ++k) {
-        info[k].relres = bnorm[k] > 0 ? std::sqrt(c.hbuf[k]) / bnorm[k] : 0.0;
-        if (info[k].relres > rtol) {
-            if (info[k].status == HEC_OK) info[k].status = HEC_ERR_NOT_CONVERGED;
-            out = (hec_status_t)info[k].status;
-        }
+        info[k].iters = hcnt[k];
+        info[k].precond_applies = hcnt[k];
+        info[k].restarts = hcnt[P + k];
+        if (info[k].status == HEC_OK && hcnt[2 * P + k] == HEC_ERR_BREAKDOWN) info[k].status = HEC_ERR_BREAKDOWN;
     }
-    return out;
+    precond_check_error(M);  // an aborted application voids the iterates
+    return final_status(info, bnorm, c.hbuf, P, rtol, status);
 }
 
 // Right-preconditioned BiCGSTAB (van der Vorst) per RHS, shadow residual
@@ -624,8 +732,15 @@ hec_status_t bicgstab(const DevHec &A, const hec_precond_t &M, const double *b, 
         c.dots_to_host(a, a, 1);
         for (int k = 0; k < P; ++k) bnorm[k] = std::sqrt(c.hbuf[k]);
     }
-    for (int k = 0; k < P; ++k) info[k] = hec_krylov_info_t{HEC_OK, 0, 0, 0, 0.0};
     std::vector<char> done(P, 0);
+    for (int k = 0; k < P; ++k) {
+        info[k] = hec_krylov_info_t{HEC_OK, 0, 0, 0, 0.0};
+        if (!std::isfinite(bnorm[k])) {
+            // a NaN or infinity in b: this problem is not iterated
+            done[k] = 1;
+            info[k].status = HEC_ERR_INVALID_ARG;
+        }
+    }
     {
         std::vector<double> keep(P);
         bool zero_rhs = false;
@@ -646,8 +761,14 @@ hec_status_t bicgstab(const DevHec &A, const hec_precond_t &M, const double *b, 
         }
         bool any = false;
         for (int k = 0; k < P; ++k) {
+            if (done[k]) continue;
             const double rr = bnorm[k] > 0 ? std::sqrt(c.hbuf[k]) / bnorm[k] : 0.0;
-            if (bnorm[k] == 0.0 || rr <= rtol) done[k] = 1;
+            if (!std::isfinite(rr)) {
+                done[k] = 1;
+                info[k].status = HEC_ERR_BREAKDOWN;
+            } else if (bnorm[k] == 0.0 || rr <= rtol) {
+                done[k] = 1;
+            }
             any = any || !done[k];
         }
         if (!any) break;
@@ -667,6 +788,12 @@ hec_status_t bicgstab(const DevHec &A, const hec_precond_t &M, const double *b, 
         std::fill(omega.begin(), omega.end(), 1.0);
         std::vector<char> act(P);
         for (int k = 0; k < P; ++k) act[k] = !done[k];
+        // a non-finite scalar stops its problem before it reaches x
+        auto stop_bad = [&](int k) {
+            act[k] = 0;
+            done[k] = 1;
+            info[k].status = HEC_ERR_BREAKDOWN;
+        };
         bool restart = false;
         while (iters < maxit && !restart) {
             {
@@ -675,6 +802,7 @@ hec_status_t bicgstab(const DevHec &A, const hec_precond_t &M, const double *b, 
             }
             for (int k = 0; k < P; ++k) {
                 rho[k] = c.hbuf[k];
+                if (act[k] && !std::isfinite(rho[k])) stop_bad(k);
                 if (act[k] && rho[k] == 0.0) restart = true;
             }
             if (restart) {
@@ -698,6 +826,7 @@ hec_status_t bicgstab(const DevHec &A, const hec_precond_t &M, const double *b, 
                 c.dots_to_host(a, bb, 1);
             }
             for (int k = 0; k < P; ++k) {
+                if (act[k] && !std::isfinite(c.hbuf[k])) stop_bad(k);
                 if (!act[k]) {
                     alpha[k] = 0.0;
                     continue;
@@ -737,6 +866,7 @@ hec_status_t bicgstab(const DevHec &A, const hec_precond_t &M, const double *b, 
                 c.dots_to_host(a, bb, 2);
             }
             for (int k = 0; k < P; ++k) {
+                if (act[k] && !sdone[k] && !(std::isfinite(c.hbuf[k]) && std::isfinite(c.hbuf[P + k]))) stop_bad(k);
                 if (!act[k] || sdone[k]) {
                     omega[k] = 0.0;
                     continue;
@@ -782,15 +912,8 @@ hec_status_t bicgstab(const DevHec &A, const hec_precond_t &M, const double *b, 
         const double *a[1] = {r};
         c.dots_to_host(a, a, 1);
     }
-    hec_status_t out = HEC_OK;
-    for (int k = 0; k < P; ++k) {
-        info[k].relres = bnorm[k] > 0 ? std::sqrt(c.hbuf[k]) / bnorm[k] : 0.0;
-        if (info[k].relres > rtol) {
-            info[k].status = status == HEC_ERR_BREAKDOWN ? HEC_ERR_BREAKDOWN : HEC_ERR_NOT_CONVERGED;
-            out = (hec_status_t)info[k].status;
-        }
-    }
-    return out;
+    precond_check_error(M);  // an aborted application voids the iterates
+    return final_status(info, bnorm, c.hbuf, P, rtol, status);
 }
 
 }  // namespace

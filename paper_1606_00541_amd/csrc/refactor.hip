@@ -14,6 +14,8 @@
 // U's scaled by the reciprocal diagonal, which itself fills U's diagonal array.
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 #include "hec_dev.h"
 
 namespace hec {
@@ -169,7 +171,8 @@ void refill_typed(const DevRefactor &r, DevTri &L, DevTri &U, hipStream_t st)
 
 void refactor_numeric(DevRefactor &r, const double *aval, hipStream_t st)
 {
-    double *f = r.fval.as<double>();
+    if (r.fwork.bytes < r.fval.bytes) r.fwork.alloc(r.fval.bytes);
+    double *f = r.fwork.as<double>();
     int *err = r.err.as<int>();
     if (r.nnz_f > 0)
         hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(r.nnz_f)), dim3(256), 0, st, f, (long)r.nnz_f);
@@ -189,6 +192,8 @@ void refactor_numeric(DevRefactor &r, const double *aval, hipStream_t st)
     hip_check(hipMemcpyAsync(&flag, err, sizeof(int), hipMemcpyDeviceToHost, st), "refactor flag copy");
     hip_check(hipStreamSynchronize(st), "refactor synchronize");
     if (flag) fail(HEC_ERR_ZERO_PIVOT, "zero or non-finite pivot in the device refactorization");
+    std::swap(r.fval.p, r.fwork.p);
+    std::swap(r.fval.bytes, r.fwork.bytes);
 }
 
 void gather_f64(const double *src, const int32_t *idx, int64_t cnt, double *dst, hipStream_t st)

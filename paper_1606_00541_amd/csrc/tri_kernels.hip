@@ -34,7 +34,6 @@ namespace hec {
 
 namespace {
 
-constexpr unsigned kSpinLimit = 1u << 22;  // polls before a wait is declared hung
 
 int32_t capacity_of(const void *kern, int32_t block, size_t lds);
 
@@ -43,6 +42,19 @@ template <> __device__ __forceinline__ double sentinel<double>() { return __long
 template <> __device__ __forceinline__ float sentinel<float>() { return __uint_as_float(kSentinel32); }
 __device__ __forceinline__ bool is_sentinel(double v) { return __double_as_longlong(v) == (long long)kSentinel64; }
 __device__ __forceinline__ bool is_sentinel(float v) { return __float_as_uint(v) == kSentinel32; }
+
+// A right-hand-side value as a kernel publishes it: an input whose bits
+// happen to equal the sentinel becomes the canonical quiet NaN, so that no
+// input value can stand for "not solved yet" (a row without dependencies
+// publishes its right-hand side unchanged).
+template <typename T> __device__ __forceinline__ T canon(T v)
+{
+    return is_sentinel(v) ? __builtin_nan("") : v;
+}
+template <> __device__ __forceinline__ float canon<float>(float v)
+{
+    return is_sentinel(v) ? __builtin_nanf("") : v;
+}
 
 // Right-hand side times the reciprocal diagonal, rounded on its own (never
 // contracted into the first multiply-add), identically in every kernel.
@@ -71,7 +83,7 @@ template <typename T> struct Ctx {
 // value itself is the signal, so no flag, fence or cache-wide writeback is
 // needed.  The poll is bounded; on expiry it raises the abort flags.
 template <typename T>
-__device__ __forceinline__ T poll_slot(const T *p, int *err_dev, int *err_host, int *abort)
+__device__ __forceinline__ T poll_slot(const T *p, int *err_dev, int *err_host, int *abort, unsigned limit)
 {
     T v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (!is_sentinel(v)) return v;
@@ -81,8 +93,8 @@ __device__ __forceinline__ T poll_slot(const T *p, int *err_dev, int *err_host, 
         v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (!is_sentinel(v)) return v;
         ++spins;
-        if ((spins & 255u) == 0 &&
-            (spins > kSpinLimit || __hip_atomic_load(err_dev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+        if (spins > limit ||
+            ((spins & 255u) == 0 && __hip_atomic_load(err_dev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
             __hip_atomic_store(err_dev, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(err_host, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
             *abort = 1;
@@ -97,7 +109,7 @@ __device__ __forceinline__ T dep_value(const TriArgs &a, const Ctx<T> &cx, int c
 {
     if (PERS && c > a.n)
         return poll_slot<T>(cx.mbox_rd + (size_t)(c - a.n - 1) * a.mbox_stride + k, a.err_dev, a.err_host,
-                            cx.abort);
+                            cx.abort, a.spin);
     if (LDS && c >= cx.lo && c < cx.hi) return cx.xl[(c - cx.lo) * a.R + k];
     const T *p = static_cast<const T *>(a.xw) + (size_t)c * a.R + k;
     // a value of this workgroup from an earlier step (persistent) or of an
@@ -110,7 +122,7 @@ template <typename T, typename TIn, bool LDS>
 __device__ __forceinline__ T rhs_value(const TriArgs &a, const Ctx<T> &cx, int x, int k)
 {
     if (LDS) return cx.xl[(x - cx.lo) * a.R + k];  // gathered (and scaled) at kernel start
-    const T b = static_cast<T>(static_cast<const TIn *>(a.bin)[(size_t)a.gather[x] * a.R + k]);
+    const T b = canon(static_cast<T>(static_cast<const TIn *>(a.bin)[(size_t)a.gather[x] * a.R + k]));
     return a.dinv ? scale_rhs(b, static_cast<const T *>(a.dinv)[x]) : b;
 }
 
@@ -250,7 +262,7 @@ __global__ void __launch_bounds__(1024) k_persistent(TriArgs a)
         const int items = (cx.hi - cx.lo) * a.R;
         for (int t = threadIdx.x; t < items; t += blockDim.x) {
             const int q = t / a.R, k = t - q * a.R;
-            const T b = static_cast<T>(bin[(size_t)a.gather[cx.lo + q] * a.R + k]);
+            const T b = canon(static_cast<T>(bin[(size_t)a.gather[cx.lo + q] * a.R + k]));
             cx.xl[t] = a.dinv ? scale_rhs(b, static_cast<const T *>(a.dinv)[cx.lo + q]) : b;
         }
         __syncthreads();
@@ -335,8 +347,8 @@ __global__ void __launch_bounds__(1024) k_owner(TriArgs a)
         for (int t = tid; t < items; t += nt) {
             const int q = t / R, k = t - q * R;
             const size_t src = (size_t)a.gather[lo + q] * R + k;
-            const T b = a.in_f64 ? static_cast<T>(static_cast<const double *>(a.bin)[src])
-                                 : static_cast<T>(static_cast<const float *>(a.bin)[src]);
+            const T b = canon(a.in_f64 ? static_cast<T>(static_cast<const double *>(a.bin)[src])
+                                       : static_cast<T>(static_cast<const float *>(a.bin)[src]));
             xl[t] = UNIT ? b : scale_rhs(b, static_cast<const T *>(a.dinv)[lo + q]);
         }
     }
@@ -422,7 +434,7 @@ __global__ void __launch_bounds__(1024) k_owner(TriArgs a)
                         T dep;
                         if (c > n)
                             dep = poll_slot<T>(mrd + (size_t)(c - n - 1) * a.mbox_stride + k, a.err_dev, a.err_host,
-                                               &s_abort);
+                                               &s_abort, a.spin);
                         else
                             dep = xl[(c - lo) * R + k];
                         sv -= vb[e * CH + i] * dep;
@@ -576,8 +588,8 @@ __global__ void __launch_bounds__(128) k_owner_split(TriArgs a)
     }
     for (int t = tid; t < hi - lo; t += blockDim.x) {
         const size_t src = (size_t)a.gather[lo + t];
-        const T b = a.in_f64 ? static_cast<T>(static_cast<const double *>(a.bin)[src])
-                             : static_cast<T>(static_cast<const float *>(a.bin)[src]);
+        const T b = canon(a.in_f64 ? static_cast<T>(static_cast<const double *>(a.bin)[src])
+                                   : static_cast<T>(static_cast<const float *>(a.bin)[src]));
         xl[t] = UNIT ? b : scale_rhs(b, static_cast<const T *>(a.dinv)[lo + t]);
     }
     __syncthreads();
@@ -605,7 +617,7 @@ __global__ void __launch_bounds__(128) k_owner_split(TriArgs a)
                     const int need = a.chunk_step[2 * (q_next - kWsBuffers) + 1] - 1;
                     unsigned spins = 0;
                     while (*v_done < need && !*v_abort) {
-                        if (++spins > kSpinLimit) raise();
+                        if (++spins > a.spin) raise();
                         __builtin_amdgcn_s_sleep(1);
                     }
                     if (*v_abort) break;
@@ -690,7 +702,7 @@ __global__ void __launch_bounds__(128) k_owner_split(TriArgs a)
                 idle = 0;
                 while (qa + 1 < q_next && a.chunk_step[2 * qa + 1] <= pub + 1) ++qa;
             } else {
-                if (++idle > kSpinLimit) {
+                if (++idle > a.spin) {
                     raise();
                     break;
                 }
@@ -710,7 +722,7 @@ __global__ void __launch_bounds__(128) k_owner_split(TriArgs a)
             unsigned spins = 0;
             while (*v_fetched < s) {
                 if (*v_abort) break;
-                if (++spins > (kSpinLimit << 4)) {
+                if (++spins > (a.spin << 4)) {
                     raise();
                     break;
                 }
@@ -806,7 +818,7 @@ __global__ void __launch_bounds__(W > 8 ? 512 : 768) k_dataflow(TriArgs a)
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ unsigned s_epoch;
     __shared__ int s_abort;
-    const int g = blockIdx.x;
+    __shared__ int s_part;
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -821,6 +833,20 @@ __global__ void __launch_bounds__(W > 8 ? 512 : 768) k_dataflow(TriArgs a)
     T *mbox = static_cast<T *>(a.mbox);
     const size_t half = (size_t)a.nexp * a.mbox_stride;
     T *mrd = mbox + (par ? half : 0);
+    // Parts: workgroup g runs part g, or (queue mode) the workgroups take
+    // parts from a counter in index order until none is left.  Queue-mode
+    // parts are numbered so that a part reads only from lower-numbered ones,
+    // and a part is taken only by a running workgroup, so the solve needs no
+    // more workgroups resident than one.
+    for (int round = 0;; ++round) {
+    if (a.queue) {
+        if (tid == 0) s_part = (int)__hip_atomic_fetch_add(&a.epoch[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+    } else if (round > 0) {
+        break;
+    }
+    const int g = a.queue ? s_part : (int)blockIdx.x;
+    if (g >= a.nparts) break;
     const int lo = a.window[2 * g], hi = a.window[2 * g + 1], win = hi - lo;
     const int i0 = a.imp_ptr[g], nimp = a.imp_ptr[g + 1] - i0;
     const int e0 = a.exp_ptr[g], nex = a.exp_ptr[g + 1] - e0;
@@ -861,7 +887,7 @@ __global__ void __launch_bounds__(W > 8 ? 512 : 768) k_dataflow(TriArgs a)
 #pragma unroll
             for (int u = 0; u < kFill; ++u) {
                 const int t = min(t0 + u * nt, win * R - 1);
-                bv[u] = static_cast<T>(bin[(size_t)gi[u] * R + (R1 ? 0 : t % R)]);
+                bv[u] = canon(static_cast<T>(bin[(size_t)gi[u] * R + (R1 ? 0 : t % R)]));
                 if (!UNIT) dd[u] = static_cast<const T *>(a.dinv)[lo + (R1 ? t : t / R)];
             }
             if (!UNIT) {
@@ -951,7 +977,7 @@ __global__ void __launch_bounds__(W > 8 ? 512 : 768) k_dataflow(TriArgs a)
                         aborted = true;
                         break;
                     }
-                    if (spins > (kSpinLimit << 4)) {
+                    if (spins > (a.spin << 4)) {
                         lds_put(&s_abort, 2);
                         aborted = true;
                         break;
@@ -974,7 +1000,7 @@ __global__ void __launch_bounds__(W > 8 ? 512 : 768) k_dataflow(TriArgs a)
                                 aborted = true;
                                 break;
                             }
-                            if (sp > (kSpinLimit << 4)) {
+                            if (sp > (a.spin << 4)) {
                                 lds_put(&s_abort, 2);
                                 aborted = true;
                                 break;
@@ -1081,7 +1107,7 @@ __global__ void __launch_bounds__(W > 8 ? 512 : 768) k_dataflow(TriArgs a)
                 }
                 if (fresh) {
                     idle = 0;
-                } else if (++idle > kSpinLimit) {
+                } else if (++idle > a.spin) {
                     lds_put(&s_abort, 2);
                     it = items;
                 } else if ((idle & 255u) == 0 &&
@@ -1106,7 +1132,7 @@ __global__ void __launch_bounds__(W > 8 ? 512 : 768) k_dataflow(TriArgs a)
                                        __HIP_MEMORY_SCOPE_AGENT);
                     it += 64;
                     idle = 0;
-                } else if (++idle > (kSpinLimit << 4)) {
+                } else if (++idle > (a.spin << 4)) {
                     lds_put(&s_abort, 2);
                     it = items;
                 }
@@ -1119,6 +1145,7 @@ __global__ void __launch_bounds__(W > 8 ? 512 : 768) k_dataflow(TriArgs a)
     if (tid == 0 && s_abort == 2) {
         __hip_atomic_store(a.err_dev, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(a.err_host, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        s_abort = 1;
     }
     if (a.trace) {
         const int ntr = min(ns, a.trace_stride - 1);
@@ -1144,10 +1171,14 @@ __global__ void __launch_bounds__(W > 8 ? 512 : 768) k_dataflow(TriArgs a)
             }
         }
     }
-    __syncthreads();
+    __syncthreads();  // LDS is refilled by the next part
+    if (s_abort) break;
+    }  // parts
     if (tid == 0) {
         const unsigned done = __hip_atomic_fetch_add(&a.epoch[1], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         if (done == gridDim.x - 1) {
+            // last workgroup out: every claim is over; reset the queue
+            __hip_atomic_store(&a.epoch[2], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&a.epoch[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&a.epoch[0], s_epoch + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -1237,7 +1268,7 @@ __global__ void __launch_bounds__(256) k_syncfree(TriArgs a, int waves)
         if (todo && a.act && !a.act[(a.seg ? a.seg[x] : 0) * a.R + k]) todo = false;
         T b = T(0);
         if (todo) {
-            b = static_cast<T>(static_cast<const TIn *>(a.bin)[(size_t)a.gather[x] * a.R + k]);
+            b = canon(static_cast<T>(static_cast<const TIn *>(a.bin)[(size_t)a.gather[x] * a.R + k]));
             if (a.dinv) b = scale_rhs(b, static_cast<const T *>(a.dinv)[x]);
         }
         unsigned spins = 0;
@@ -1275,7 +1306,7 @@ __global__ void __launch_bounds__(256) k_syncfree(TriArgs a, int waves)
             if (__ballot(todo)) {
                 __builtin_amdgcn_s_sleep(1);
                 if ((++spins & 255u) == 0 &&
-                    (spins > kSpinLimit ||
+                    (spins > a.spin ||
                      __hip_atomic_load(a.err_dev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
                     __hip_atomic_store(a.err_dev, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     __hip_atomic_store(a.err_host, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -1336,9 +1367,18 @@ void launch_typed(DevTri &d, TriArgs a, hipStream_t st)
         if (block > dataflow_max_block(d.w)) fail(HEC_ERR_INVALID_ARG, "dataflow kernel: block too large");
         if (lds > (size_t)device_max_lds())
             fail(HEC_ERR_CAPACITY, "dataflow kernel: LDS need exceeds the device limit at this nrhs");
-        if (capacity_of((const void *)k, block, lds) < d.groups)
+        const int32_t cap = capacity_of((const void *)k, block, lds);
+        a.nparts = d.groups;
+        a.queue = d.queue ? 1 : 0;
+        int32_t grid = d.groups;
+        if (d.queue) {
+            // parts wait only on lower-numbered parts, which running
+            // workgroups hold: any grid size makes progress
+            grid = std::max(1, std::min(d.groups, cap));
+        } else if (cap < d.groups) {
             fail(HEC_ERR_CAPACITY, "dataflow grid exceeds the co-resident capacity");
-        hipLaunchKernelGGL(k, dim3(d.groups), dim3(block), lds, st, a);
+        }
+        hipLaunchKernelGGL(k, dim3(grid), dim3(block), lds, st, a);
         hip_check(hipGetLastError(), "k_dataflow launch");
         return;
     }
@@ -1527,6 +1567,7 @@ void launch_tri(DevTri &d, const void *bin, hec_dtype_t in_dt, const int32_t *ga
     a.seg = d.seg.p ? d.seg.as<int32_t>() : nullptr;
     a.trace = d.trace;
     a.trace_stride = d.trace_stride;
+    a.spin = d.spin;
     a.in_f64 = in_dt == HEC_F64 ? 1 : 0;
     a.out_f64 = out_dt == HEC_F64 ? 1 : 0;
     if (d.dt == HEC_F64) launch_in<double>(d, a, in_dt, out_dt, st);

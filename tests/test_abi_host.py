@@ -45,7 +45,9 @@ def test_tune_defaults_and_validation():
     with pytest.raises(H.HecError):
         H.tri_analyze(L, tune=H.tune_default(host_only=1, group_lanes=3))
     with pytest.raises(H.HecError):
-        H.tri_analyze(L, tune=H.tune_default(host_only=1, kernel_variant=6))
+        H.tri_analyze(L, tune=H.tune_default(host_only=1, kernel_variant=7))
+    with pytest.raises(H.HecError):  # the queue-mode dataflow kernel runs the owner schedule only
+        H.tri_analyze(L, tune=H.tune_default(host_only=1, kernel_variant=6, schedule="level_launch"))
     with pytest.raises(H.HecError):  # the barrier-free kernel runs the level-ordered layout only
         H.tri_analyze(L, tune=H.tune_default(host_only=1, kernel_variant=5, schedule="owner_persistent"))
     p = H.tri_analyze(L, tune=H.tune_default(host_only=1, kernel_variant=5))
@@ -261,16 +263,21 @@ def test_auto_tuning_picks_the_dataflow_kernel_when_it_fits():
     L, _ = oracle.ilu0(A)
     st = H.tri_plan_stats(H.tri_analyze(L, unit_diag=True, tune=HOST))
     assert st["schedule"] == 3 and st["dataflow"] == 1
-    # one group cannot hold every row in LDS: the level-ordered layout, run by
-    # the barrier-free kernel when levels are narrow ...
+    # one group cannot hold every row in LDS: the same kernel with more parts
+    # than workgroups, taken from a queue
     A = synth.poisson2d(160)
     L, _ = oracle.ilu0(A)
     st = H.tri_plan_stats(H.tri_analyze(L, unit_diag=True, tune=H.tune_default(host_only=1, num_groups=1)))
+    assert st["schedule"] == 3 and st["dataflow"] == 1 and st["queue"] == 1 and st["num_groups"] > 1
+    # no dataflow kernel at all (more than 64 right-hand sides): the
+    # level-ordered layout, run by the barrier-free kernel when levels are
+    # narrow ...
+    st = H.tri_plan_stats(H.tri_analyze(L, unit_diag=True, tune=H.tune_default(host_only=1, max_nrhs=65)))
     assert st["schedule"] == 1 and st["dataflow"] == 0 and st["syncfree"] == 1
     # ... and by one launch per level when they are wide (2^17 items and more)
     n = (1 << 17) + 64
     D = CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.full(n, 2.0))
-    st = H.tri_plan_stats(H.tri_analyze(D, tune=H.tune_default(host_only=1, num_groups=1)))
+    st = H.tri_plan_stats(H.tri_analyze(D, tune=H.tune_default(host_only=1, max_nrhs=65)))
     assert st["schedule"] == 1 and st["nlev"] == 1 and st["syncfree"] == 0
     # an explicit owner schedule falls back to the LDS-chunked owner kernel
     st = H.tri_plan_stats(H.tri_analyze(L, unit_diag=True, tune=H.tune_default(
@@ -321,3 +328,47 @@ def test_owner_partitions():
     c1 = H.tri_plan_stats(H.tri_analyze(R, tune=H.tune_default(host_only=1, schedule="owner_persistent",
                                                                num_groups=16, partition=1)))
     assert a1["crit_hops"] == c1["crit_hops"] and a1["nexport"] == c1["nexport"]
+
+
+def test_queue_parts_read_only_earlier_parts():
+    # The queue-mode dataflow kernel needs every part to read only from parts
+    # with lower numbers (a part is taken only when all lower ones have been
+    # taken by running workgroups); parts never span two independent systems,
+    # and the systems with the most levels come first.
+    mats = [synth.diffusion2d(30, 21, 1.0, seed=1), synth.diffusion3d(11, 10, 9, 1.0, seed=2),
+            synth.poisson2d(7, 3), synth.diffusion3d(14, 13, 12, 1.0, seed=4), synth.poisson2d(45, 2)]
+    import scipy.sparse as sp
+    m = sp.block_diag([M.to_scipy() for M in mats]).tocsr()
+    m.sort_indices()
+    A = CSR(m.shape[0], m.indptr.astype(np.int32), m.indices.astype(np.int32), m.data.copy())
+    sys_ptr = np.cumsum([0] + [M.n for M in mats]).astype(np.int32)
+    n = A.n
+    t = H.tune_default(host_only=1, max_nrhs=8, part_rows=400, schedule="owner_persistent", kernel_variant=6)
+    f = H.batch_setup(A, sys_ptr, "iluk", k=1, tune=t)
+    sysof = np.searchsorted(sys_ptr, np.arange(n), side="right") - 1
+    for which, plan in enumerate(H.ilu_plans(f)):
+        st = H.tri_plan_stats(plan)
+        assert st["queue"] == 1 and st["dataflow"] == 1 and st["num_groups"] >= len(mats)
+        xperm, owner = H.tri_plan_layout(plan)
+        part = np.empty(n, np.int64)
+        part[xperm] = owner
+        rp, ci, _ = H.ilu_factor(f, which)
+        rows = np.repeat(np.arange(n), np.diff(rp))
+        off = rows != ci
+        assert np.all(part[ci[off]] <= part[rows[off]])
+        for g in np.unique(part):
+            members = np.flatnonzero(part == g)
+            assert len(np.unique(sysof[members])) == 1
+            assert len(members) <= 400  # the first cut is an upper bound
+            # a contiguous range of the problem order
+            assert members.max() - members.min() + 1 == len(members)
+        # deepest system first: system 0 (30 x 21 2D grid, 2*21+30-2 levels in ILU(1)... )
+        lev_depth = []
+        nlev, lp, perm = H.tri_plan_info(plan)
+        level = np.empty(n, np.int64)
+        for k in range(nlev):
+            level[perm[lp[k]:lp[k + 1]]] = k + 1
+        depth = [level[sys_ptr[s]:sys_ptr[s + 1]].max() for s in range(len(mats))]
+        first_part = [part[sys_ptr[s]:sys_ptr[s + 1]].min() for s in range(len(mats))]
+        order = sorted(range(len(mats)), key=lambda s: first_part[s])
+        assert [depth[s] for s in order] == sorted(depth, reverse=True)

@@ -1,0 +1,275 @@
+"""GPU failure paths: non-finite inputs, bounded waits that give up, a failed
+device refactorization, and stale memory under the batched Krylov solver.
+
+Every case either ends normally or through a bounded wait that the host
+shortens on purpose (tri_plan_set_wait_limit); no kernel is made to fault.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth import CSR
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1606_00541_amd as H  # noqa: E402
+
+SENT64 = np.uint64(0x7FF4DEADBEEF0001)  # the solve's "not yet solved" bit pattern
+SENT32 = np.uint32(0x7FA0BEEF)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def close(x, ref, tol):
+    """Normwise and element-wise agreement with the oracle."""
+    scale = max(np.abs(ref).max(), 1e-300)
+    assert np.abs(x - ref).max() <= tol * scale
+    assert np.linalg.norm(x - ref) <= tol * max(np.linalg.norm(ref), 1e-300)
+
+
+def tune_for(kernel, **kw):
+    if kernel == "dataflow":
+        return H.tune_default(schedule="owner_persistent", kernel_variant=4, **kw)
+    if kernel == "syncfree":
+        return H.tune_default(schedule="level_launch", kernel_variant=5, **kw)
+    if kernel == "owner":
+        return H.tune_default(schedule="owner_persistent", kernel_variant=2, **kw)
+    return H.tune_default(schedule=kernel, **kw)
+
+
+KERNELS = ["dataflow", "syncfree", "owner", "level_persistent", "level_launch"]
+
+
+# ---- non-finite right-hand sides -------------------------------------------
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_nan_in_b_reaches_only_its_dependents(kernel):
+    # eq. (2): row i depends on row j iff a path j -> i exists in the DAG of L;
+    # a NaN in b_j must reach exactly those rows (the oracle's substitution
+    # propagates it the same way) and every other row keeps its value
+    A = synth.poisson2d(40)
+    L, _ = oracle.ilu0(A)
+    f = H.tri_analyze(L, "lower", unit_diag=True, tune=tune_for(kernel, max_nrhs=2))
+    b = synth.rhs(A.n, 2, 81)
+    b[13 + 40 * 17, 0] = np.nan
+    ref = oracle.lower_solve(L, b, unit=True)
+    xt = torch.empty(A.n, 2, dtype=torch.float64, device="cuda")
+    H.tri_solve_lower(f, dev(b), xt)
+    torch.cuda.synchronize()
+    H.tri_plan_check(f)
+    x = xt.cpu().numpy()
+    assert np.array_equal(np.isnan(x), np.isnan(ref))
+    assert np.isnan(ref[:, 0]).sum() == (40 - 13) * (40 - 17)  # the quadrant x >= 13, y >= 17
+    ok = ~np.isnan(ref)
+    close(x[ok], ref[ok], 1e-12)
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_sentinel_bits_in_b_do_not_stall(kernel, dtype):
+    # row 0 of a unit lower triangle has no dependencies and publishes its
+    # right-hand side unchanged: an input equal to the "not yet solved" pattern
+    # must not make its consumers wait for it
+    A = synth.poisson2d(24)
+    L, _ = oracle.ilu0(A)
+    f = H.tri_analyze(L, "lower", unit_diag=True, dtype=dtype, tune=tune_for(kernel))
+    H.tri_plan_set_wait_limit(f, 1 << 16)  # a stall would end in TIMEOUT within milliseconds
+    npdt = np.float64 if dtype == "f64" else np.float32
+    b = synth.rhs(A.n, 1, 82).astype(npdt)
+    b.view(np.uint64 if dtype == "f64" else np.uint32)[0, 0] = SENT64 if dtype == "f64" else SENT32
+    xt = torch.empty(A.n, 1, dtype=torch.float64 if dtype == "f64" else torch.float32, device="cuda")
+    H.tri_solve_lower(f, dev(b), xt)
+    torch.cuda.synchronize()
+    H.tri_plan_check(f)  # raises TIMEOUT if a wait gave up
+    x = xt.cpu().numpy()
+    assert np.all(np.isnan(x))  # every row depends on row 0 in a 2D natural-order ILU(0)
+
+
+@pytest.mark.parametrize("method", ["fgmres", "bicgstab"])
+def test_krylov_nan_in_one_rhs_is_reported_for_that_rhs(method):
+    A = synth.poisson3d(16)
+    f = H.ilu_setup(A, "ilu0", tune=H.tune_default(max_nrhs=3))
+    M = H.hec_from_csr(A)
+    b = synth.rhs(A.n, 3, 83)
+    b[100, 1] = np.nan
+    xt = torch.zeros(A.n, 3, dtype=torch.float64, device="cuda")
+    st, info = H.krylov_solve(M, f, dev(b), xt, method=method, m=30, rtol=1e-10)
+    assert st == 1  # INVALID_ARG: a NaN never counts as converged
+    assert info[1].status == 1 and np.isnan(info[1].relres) and info[1].iters == 0
+    x = xt.cpu().numpy()
+    assert np.all(x[:, 1] == 0.0)  # not iterated: x0 kept
+    for k in (0, 2):
+        assert info[k].status == 0
+        true = np.linalg.norm(b[:, k] - oracle.spmv(A, x[:, k])) / np.linalg.norm(b[:, k])
+        assert true <= 1e-10
+
+
+def test_krylov_batch_nan_in_one_problem():
+    mats = [synth.diffusion2d(25, 20, 1.0, seed=84), synth.diffusion3d(9, 8, 7, 1.0, seed=85),
+            synth.diffusion2d(31, 11, 1.0, seed=86)]
+    import scipy.sparse as sp
+    m = sp.block_diag([Mi.to_scipy() for Mi in mats]).tocsr()
+    m.sort_indices()
+    A = CSR(m.shape[0], m.indptr.astype(np.int32), m.indices.astype(np.int32), m.data.copy())
+    sys_ptr = np.cumsum([0] + [Mi.n for Mi in mats]).astype(np.int32)
+    f = H.batch_setup(A, sys_ptr, "iluk", k=1, tune=H.tune_default(max_nrhs=2))
+    M = H.hec_from_csr(A)
+    b = synth.rhs(A.n, 2, 87)
+    b[int(sys_ptr[1]) + 5, 0] = np.inf
+    xt = torch.zeros(A.n, 2, dtype=torch.float64, device="cuda")
+    st, info = H.krylov_solve_batch(M, f, sys_ptr, dev(b), xt, method="fgmres", m=30, rtol=1e-10)
+    assert st == 1
+    bad = 1 * 2 + 0
+    x = xt.cpu().numpy()
+    for q in range(len(mats) * 2):
+        s, k = divmod(q, 2)
+        seg = slice(int(sys_ptr[s]), int(sys_ptr[s + 1]))
+        if q == bad:
+            assert info[q].status == 1 and np.all(x[seg, k] == 0.0)
+            continue
+        assert info[q].status == 0
+        bs = b[seg, k]
+        assert np.linalg.norm(bs - oracle.spmv(mats[s], x[seg, k])) / np.linalg.norm(bs) <= 1e-10
+
+
+@pytest.mark.parametrize("kernel", ["auto", "syncfree"])
+def test_batch_gmres_ignores_stale_basis_memory(kernel):
+    # Problems stop at different steps; a stopped problem's basis vectors are
+    # not written any more, and the memory they occupy may hold anything (here
+    # a freed plan's sentinel-filled mailbox is likely to be reused).  The
+    # final update must use only the vectors each problem built.
+    big = synth.poisson3d(48)
+    junk = H.tri_analyze(oracle.ilu0(big)[0], "lower", unit_diag=True,
+                         tune=H.tune_default(schedule="owner_persistent", kernel_variant=4, max_nrhs=8))
+    del junk
+    torch.cuda.synchronize()
+    mats = [synth.poisson2d(6, 5), synth.diffusion3d(12, 11, 10, 2.0, seed=88), synth.diffusion2d(40, 30, 1.0, seed=89)]
+    import scipy.sparse as sp
+    m = sp.block_diag([Mi.to_scipy() for Mi in mats]).tocsr()
+    m.sort_indices()
+    A = CSR(m.shape[0], m.indptr.astype(np.int32), m.indices.astype(np.int32), m.data.copy())
+    sys_ptr = np.cumsum([0] + [Mi.n for Mi in mats]).astype(np.int32)
+    kw = {"schedule": "level_launch", "kernel_variant": 5} if kernel == "syncfree" else {}
+    f = H.batch_setup(A, sys_ptr, "ilu0", tune=H.tune_default(max_nrhs=2, **kw))
+    M = H.hec_from_csr(A)
+    b = synth.rhs(A.n, 2, 90)
+    xt = torch.zeros(A.n, 2, dtype=torch.float64, device="cuda")
+    st, info = H.krylov_solve_batch(M, f, sys_ptr, dev(b), xt, method="fgmres", m=30, rtol=1e-10)
+    assert st == 0
+    its = [q.iters for q in info]
+    assert len(set(its)) > 1  # the problems did stop at different steps
+    x = xt.cpu().numpy()
+    assert np.all(np.isfinite(x))
+    for s, Ms in enumerate(mats):
+        seg = slice(int(sys_ptr[s]), int(sys_ptr[s + 1]))
+        for k in range(2):
+            bs = b[seg, k]
+            assert np.linalg.norm(bs - oracle.spmv(Ms, x[seg, k])) / np.linalg.norm(bs) <= 1e-10
+
+
+# ---- bounded waits ------------------------------------------------------------
+
+def _chain(n):
+    # unit lower bidiagonal: one level per row, so every workgroup waits on
+    # the one before it for the whole solve
+    rp = np.concatenate([[0], np.arange(1, 2 * n, 2, dtype=np.int32)]).astype(np.int32)
+    col = np.empty(2 * n - 1, np.int32)
+    val = np.empty(2 * n - 1)
+    col[0], val[0] = 0, 1.0
+    col[1::2] = np.arange(0, n - 1)
+    val[1::2] = -0.5
+    col[2::2] = np.arange(1, n)
+    val[2::2] = 1.0
+    return CSR(n, rp, col, val)
+
+
+@pytest.mark.parametrize("kernel", ["dataflow", "syncfree", "owner"])
+def test_wait_limit_timeout_is_reported_then_recovers(kernel):
+    n = 1 << 15
+    L = _chain(n)
+    kw = {"partition": 1} if kernel in ("dataflow", "owner") else {}
+    f = H.tri_analyze(L, "lower", unit_diag=True, tune=tune_for(kernel, **kw))
+    b = synth.rhs(n, 1, 91)
+    ref = oracle.lower_solve(L, b, unit=True)
+    bt = dev(b)
+    xt = torch.empty_like(bt)
+    H.tri_plan_set_wait_limit(f, 4)  # waits give up almost at once
+    H.tri_solve_lower(f, bt, xt)  # asynchronous: returns OK
+    torch.cuda.synchronize()
+    with pytest.raises(H.HecError) as e:
+        H.tri_solve_lower(f, bt, xt)  # the abort of the previous launch is reported here
+    assert e.value.name == "TIMEOUT"
+    H.tri_plan_set_wait_limit(f, 0)  # back to the default
+    H.tri_solve_lower(f, bt, xt)
+    torch.cuda.synchronize()
+    H.tri_plan_check(f)
+    close(xt.cpu().numpy(), ref, 1e-12)
+    H.tri_solve_lower(f, bt, xt)  # and the launch after it as well
+    torch.cuda.synchronize()
+    H.tri_plan_check(f)
+    close(xt.cpu().numpy(), ref, 1e-12)
+
+
+def test_krylov_reports_an_aborted_preconditioner():
+    A = synth.poisson3d(20)
+    f = H.ilu_setup(A, "ilu0", tune=H.tune_default(schedule="owner_persistent", kernel_variant=4, partition=1))
+    pl, pu = H.ilu_plans(f)
+    H.tri_plan_set_wait_limit(pl, 1)
+    H.tri_plan_set_wait_limit(pu, 1)
+    M = H.hec_from_csr(A)
+    b = synth.rhs(A.n, 1, 92)
+    xt = torch.zeros(A.n, 1, dtype=torch.float64, device="cuda")
+    with pytest.raises(H.HecError) as e:
+        H.krylov_solve(M, f, dev(b), xt, method="fgmres", m=10, rtol=1e-10, maxit=5)
+    assert e.value.name == "TIMEOUT"
+    H.tri_plan_set_wait_limit(pl, 0)
+    H.tri_plan_set_wait_limit(pu, 0)
+    xt.zero_()
+    st, info = H.krylov_solve(M, f, dev(b), xt, method="fgmres", m=30, rtol=1e-10)
+    assert st == 0 and info[0].relres <= 1e-10
+
+
+# ---- failed device refactorization ----------------------------------------------
+
+def test_failed_refactor_keeps_the_last_good_factors():
+    A1 = synth.diffusion2d(17, 13, 1.0, seed=93)
+    A2 = synth.diffusion2d(17, 13, 2.0, seed=94)
+    f = H.ilu_setup(A1, "ilu0", tune=H.tune_default(max_nrhs=1))
+    H.ilu_refactor(f, A2)
+    bad = A2.val.copy()
+    bad[A2.rowptr[0]] = 0.0  # a_00 = 0
+    with pytest.raises(H.HecError) as e:
+        H.ilu_refactor(f, CSR(A2.n, A2.rowptr, A2.col, bad))
+    assert e.value.name == "ZERO_PIVOT"
+    L2, U2 = oracle.ilu0(A2)
+    for w, T in ((0, L2), (1, U2)):
+        rp, ci, v = H.ilu_factor(f, w)
+        assert np.array_equal(rp, T.rowptr) and np.array_equal(ci, T.col) and np.array_equal(v, T.val)
+    r = synth.rhs(A2.n, 1, 95)
+    zt = torch.empty(A2.n, 1, dtype=torch.float64, device="cuda")
+    H.ilu_apply(f, dev(r), zt)
+    close(zt.cpu().numpy(), oracle.ilu_apply(L2, U2, r), 1e-12)
+
+
+def test_failed_ras_refactor_keeps_the_last_good_factors():
+    A1 = synth.diffusion3d(12, 10, 9, 1.0, seed=96)
+    A2 = synth.diffusion3d(12, 10, 9, 2.0, seed=97)
+    owner = synth.grid_bisection(12, 10, 9, 4)
+    s = H.ras_setup(A1, 4, owner, overlap=1)
+    g = H.ras_setup(A2, 4, owner, overlap=1)
+    H.ras_refactor(s, A2)
+    bad = A2.val.copy()
+    bad[A2.rowptr[0]] = 0.0
+    with pytest.raises(H.HecError) as e:
+        H.ras_refactor(s, CSR(A2.n, A2.rowptr, A2.col, bad))
+    assert e.value.name == "ZERO_PIVOT"
+    r = dev(synth.rhs(A2.n, 1, 98))
+    z1, z2 = torch.empty_like(r), torch.empty_like(r)
+    H.ras_apply(s, r, z1)
+    H.ras_apply(g, r, z2)
+    torch.cuda.synchronize()
+    assert torch.equal(z1, z2)

@@ -11,12 +11,11 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 import paper_1606_00541_amd as H  # noqa: E402
+from parity import relerr  # noqa: E402  (normwise and element-wise)
 
 TOL = 1e-12
 
 
-def relerr(x, ref):
-    return float(np.linalg.norm(x - ref) / max(np.linalg.norm(ref), 1e-300))
 
 
 @pytest.mark.parametrize("omega", [1.0, 0.8, 1.3])

@@ -11,6 +11,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 import paper_1606_00541_amd as H  # noqa: E402
+from parity import relerr  # noqa: E402  (normwise and element-wise)
 
 SCHEDS = ["level_launch", "level_persistent", "owner_persistent", "owner_dataflow", "syncfree"]
 FP64_TOL = 1e-12
@@ -32,8 +33,6 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def relerr(x, ref):
-    return float(np.linalg.norm(x - ref) / max(np.linalg.norm(ref), 1e-300))
 
 
 def transpose(T):
