@@ -187,6 +187,241 @@ def _tune(H, args, **kw):
     return H.tune_default(schedule=sched, kernel_variant=args.kernel_variant, **kw)
 
 
+def _kernel_name(st):
+    """The kernel a plan runs (from tri_plan_stats)."""
+    if st["dataflow"]:
+        return "k_dataflow" + (" (part queue)" if st.get("queue") else "")
+    if st["syncfree"]:
+        return "k_syncfree"
+    return "k_level" if st["schedule"] == 1 else "k_persistent"
+
+
+def _roofline(st, bytes_per_apply, ms):
+    """Roofline of the dominant kernel: the L and U launches share it, so its
+    average launch moves half the counted bytes in half the application."""
+    launches = st["nlev"] * 2 if (st["schedule"] == 1 and not st["syncfree"]) else 2
+    per_launch = bytes_per_apply / launches
+    achieved = per_launch / (ms / launches * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": _kernel_name(st), "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+            "algorithmic_bytes_per_launch": int(per_launch), "traffic": None}
+
+
+def _graph_ms(H, torch, M, r, z, reps):
+    """One application replayed from a captured HIP graph (hec_graph_capture)."""
+    g = H.hec_graph_capture(M, r, z)
+    for _ in range(2):
+        H.hec_graph_launch(g)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        H.hec_graph_launch(g)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def _cpu_time(fn, budget):
+    """Seconds per call of fn over about `budget` seconds (at least one call)."""
+    fn()
+    reps, t0 = 0, time.time()
+    while True:
+        fn()
+        reps += 1
+        if time.time() - t0 >= budget:
+            break
+    return (time.time() - t0) / reps, reps
+
+
+def _relerr(np, x, ref):
+    d = x - ref
+    return float(max(np.linalg.norm(d) / np.linalg.norm(ref), np.abs(d).max() / np.abs(ref).max()))
+
+
+def _cfg3(H, torch, np, synth, args):
+    """Heterogeneous 100^3 diffusion (sigma 2), ILUT(1e-3, 10): FP64 factors
+    against FP32 factors with FP64 refinement, FGMRES(30) to 1e-10."""
+    import oracle
+
+    A = synth.diffusion3d(100, None, None, 2.0, seed=3)
+    n = A.n
+    Aop = H.hec_from_csr(A)
+    b = torch.from_numpy(synth.rhs(n, 1, 3)).cuda()
+    res, xs = {}, {}
+    for fdt in ("f64", "f32"):
+        _log("config 3: ILUT setup, %s factors" % fdt)
+        t0 = time.time()
+        f = H.ilu_setup(A, "ilut", p=10, tol=1e-3, factor_dtype=fdt, tune=_tune(H, args))
+        setup = time.time() - t0
+        pl, pu = H.ilu_plans(f)
+        stl, stu = H.tri_plan_stats(pl), H.tri_plan_stats(pu)
+        sv = 8 if fdt == "f64" else 4
+        B = counted_bytes(n, stl["nnz_offdiag"], stu["nnz_offdiag"], 1, sv=sv)
+        z = torch.empty_like(b)
+        _log("config 3: timing applies (%s)" % fdt)
+        ms = _time_apply(H, torch, f, b, z, args.steps, args.warmup)
+        row = {"apply_ms": round(ms, 4), "apply_GBps": round(B / (ms * 1e-3) / 1e9, 3),
+               "counted_bytes_per_apply": int(B), "roofline": _roofline(stl, B, ms),
+               "nlev_L": stl["nlev"], "nlev_U": stu["nlev"], "nnz_offdiag_L": stl["nnz_offdiag"],
+               "nnz_offdiag_U": stu["nnz_offdiag"], "ell_width_L": stl["ell_width"],
+               "nnz_tail_L": stl["nnz_tail"], "setup_s": round(setup, 3)}
+        if not args.no_krylov:
+            _log("config 3: FGMRES (%s)" % fdt)
+            xs[fdt], row["fgmres"] = _krylov(H, torch, f, Aop, b, "fgmres")
+        if fdt == "f64" and not args.no_cpu_baseline:
+            # the oracle's substitution on the same factors (the host factors
+            # are the oracle's, bit for bit)
+            L = synth.CSR(n, *H.ilu_factor(f, 0))
+            U = synth.CSR(n, *H.ilu_factor(f, 1))
+            rr = b.cpu().numpy()
+            cs, reps = _cpu_time(lambda: oracle.ilu_apply(L, U, rr), args.cpu_seconds / 5)
+            row["parity_relerr_vs_oracle"] = _relerr(np, z.cpu().numpy(), oracle.ilu_apply(L, U, rr))
+            res["cpu_baseline"] = {"value": round(B / cs / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+                                   "sample": "%d full L+U applications of the 100^3 ILUT system (serial C "
+                                             "substitution, FP64 factors)" % reps,
+                                   "seconds_per_apply": round(cs, 5)}
+        res[fdt] = row
+    out = {"workload": "heterogeneous 3D 7-point diffusion 100^3 (n=1000000), lognormal sigma=2 seed 3, "
+                       "ILUT(tol 1e-3, p 10), 1 RHS; FGMRES(30) to 1e-10",
+           "fp64": res["f64"], "fp32_refined": res["f32"], "cpu_baseline": res.get("cpu_baseline")}
+    if not args.no_krylov:
+        out["fp32_time_ratio_vs_fp64"] = round(res["f32"]["fgmres"]["seconds"] / res["f64"]["fgmres"]["seconds"], 4)
+        out["rel_diff_fp32_vs_fp64_solution"] = (xs["f32"] - xs["f64"]).norm().item() / xs["f64"].norm().item()
+    return out
+
+
+def _cfg4(H, torch, np, synth, args):
+    """RAS on the 128^3 Poisson matrix: 64 seeded contiguous subdomains,
+    overlap 1, ILU(0) per subdomain in FP32, 16 RHS; FP64 BiCGSTAB."""
+    import oracle
+
+    A = synth.poisson3d(128)
+    n = A.n
+    owner, _ = synth.subdomain_cuts(n, 64, 8192, 61440, seed=4)
+    R = 16
+    _log("config 4: RAS setup")
+    t0 = time.time()
+    s = H.ras_setup(A, 64, owner, overlap=1, factor_dtype="f32", tune=_tune(H, args, max_nrhs=R))
+    setup = time.time() - t0
+    nsub, tot, ext = H.ras_info(s)
+    pl, pu = H.ras_plans(s)
+    stl, stu = H.tri_plan_stats(pl), H.tri_plan_stats(pu)
+    # FP32 factor side on the extended rows, FP64 gather of r and prolongation of z
+    B = (stl["nnz_offdiag"] + stu["nnz_offdiag"]) * 8 + tot * 4 + 2 * 4 * tot + R * (2 * tot * 4 + 2 * n * 8)
+    r = torch.from_numpy(synth.rhs(n, R, 4)).cuda()
+    z = torch.empty_like(r)
+    _log("config 4: timing applies")
+    reps = max(5, args.steps // 2)
+    ms = _time_apply(H, torch, s, r, z, reps, 2, ras=True)
+    out = {"workload": "RAS on 128^3 Poisson (n=2097152): 64 seeded contiguous subdomains (8192..61440 rows), "
+                       "overlap 1, ILU(0) per subdomain in FP32, 16 RHS; FP64 BiCGSTAB to 1e-10",
+           "apply_ms": round(ms, 4), "apply_GBps": round(B / (ms * 1e-3) / 1e9, 3), "counted_bytes_per_apply": int(B),
+           "solves_per_s": round(1000.0 * R / ms, 2), "roofline": _roofline(stl, B, ms),
+           "extended_rows": int(tot), "nlev_L": stl["nlev"], "nlev_U": stu["nlev"], "setup_s": round(setup, 3),
+           "parts_L": stl["num_groups"]}
+    zg = torch.empty_like(r)
+    out["apply_ms_graph_replay"] = round(_graph_ms(H, torch, s, r, zg, reps), 4)
+    torch.cuda.synchronize()
+    out["graph_equals_eager"] = bool(torch.equal(zg, z))
+    if not args.no_krylov:
+        _log("config 4: BiCGSTAB")
+        _, out["bicgstab"] = _krylov(H, torch, s, H.hec_from_csr(A), r, "bicgstab")
+    if not args.no_cpu_baseline:
+        _log("config 4: CPU oracle")
+        doms32 = oracle.ras_to_f32(oracle.ras_setup(A, owner, 64, overlap=1))
+        rr = r.cpu().numpy()
+        ref = oracle.ras_apply_f32(doms32, rr)
+        out["parity_relerr_vs_oracle"] = _relerr(np, z.cpu().numpy(), ref)
+        t0 = time.time()
+        oracle.ras_apply_f32(doms32, rr)
+        cs = time.time() - t0
+        out["cpu_baseline"] = {"value": round(B / cs / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+                               "sample": "1 full RAS application, 64 subdomains x 16 RHS (serial C substitution "
+                                         "per subdomain, FP32)", "seconds_per_apply": round(cs, 4)}
+    return out
+
+
+def _cfg5(H, torch, np, synth, args):
+    """256 independent systems (log-uniform 1e3..2e5 rows, 2D/3D lognormal
+    sigma 1), ILU(1), 8 RHS each: FP64 factors against FP32 factors with FP64
+    refinement; batched FGMRES(30), every (system, rhs) its own problem."""
+    import oracle
+
+    _log("config 5: generating systems")
+    shapes = synth.batch_systems(256, seed=5)
+    mats = []
+    for i, (dim, side) in enumerate(shapes):
+        if dim == 2:
+            mats.append(synth.diffusion2d(side, None, 1.0, seed=5000 + i))
+        else:
+            mats.append(synth.diffusion3d(side, None, None, 1.0, seed=5000 + i))
+    A, sys_ptr = _block_diag(mats)
+    n = A.n
+    R = 8
+    b = torch.from_numpy(synth.rhs(n, R, 5)).cuda()
+    Aop = H.hec_from_csr(A)
+    res = {}
+    z32 = None
+    for fdt in ("f64", "f32"):
+        _log("config 5: batch ILU(1) setup, %s factors" % fdt)
+        t0 = time.time()
+        f = H.batch_setup(A, sys_ptr, "iluk", k=1, factor_dtype=fdt, tune=_tune(H, args, max_nrhs=R))
+        setup = time.time() - t0
+        pl, pu = H.ilu_plans(f)
+        stl, stu = H.tri_plan_stats(pl), H.tri_plan_stats(pu)
+        sv = 8 if fdt == "f64" else 4
+        B = counted_bytes(n, stl["nnz_offdiag"], stu["nnz_offdiag"], R, sv=sv)
+        z = torch.empty_like(b)
+        _log("config 5: timing applies (%s)" % fdt)
+        reps = max(5, args.steps // 2)
+        ms = _time_apply(H, torch, f, b, z, reps, 2)
+        row = {"apply_ms": round(ms, 4), "apply_GBps": round(B / (ms * 1e-3) / 1e9, 3),
+               "counted_bytes_per_apply": int(B), "roofline": _roofline(stl, B, ms),
+               "solves_per_s": round(1000.0 * len(mats) * R / ms, 1),
+               "nlev_L": stl["nlev"], "nlev_U": stu["nlev"], "setup_s": round(setup, 3), "parts_L": stl["num_groups"]}
+        zg = torch.empty_like(b)
+        row["apply_ms_graph_replay"] = round(_graph_ms(H, torch, f, b, zg, reps), 4)
+        torch.cuda.synchronize()
+        row["graph_equals_eager"] = bool(torch.equal(zg, z))
+        if not args.no_krylov:
+            _log("config 5: batched FGMRES, one problem per (system, rhs) (%s)" % fdt)
+            _, kr = _krylov_batch(H, torch, f, Aop, sys_ptr, b, "fgmres")
+            row["fgmres"] = kr
+            row["systems_per_s"] = round(len(mats) * R / kr["seconds"], 3)
+        res[fdt] = row
+        if fdt == "f32":
+            z32 = z.cpu().numpy()
+    out = {"workload": "256 independent systems (log-uniform 1e3..2e5 rows, 2D/3D lognormal sigma=1, n=%d), ILU(1), "
+                       "8 RHS each; batched FGMRES(30), each (system, rhs) to 1e-10" % n,
+           "systems": len(mats), "fp64": res["f64"], "fp32_refined": res["f32"]}
+    if not args.no_krylov:
+        out["fp32_speedup_vs_fp64_time_to_1e-10"] = round(res["f64"]["fgmres"]["seconds"] /
+                                                         res["f32"]["fgmres"]["seconds"], 4)
+    if not args.no_cpu_baseline:
+        _log("config 5: CPU oracle on a sample of systems")
+        pick = list(range(0, len(mats), 16))
+        rr = b.cpu().numpy()
+        bs, ts, errs = 0, 0.0, []
+        for s_ in pick:
+            M = mats[s_]
+            L, U = oracle.iluk(M, 1)
+            L32, U32 = oracle.to_f32(L), oracle.to_f32(U)
+            seg = slice(int(sys_ptr[s_]), int(sys_ptr[s_ + 1]))
+            t0 = time.time()
+            ref = oracle.ilu_apply_f32(L32, U32, rr[seg])
+            ts += time.time() - t0
+            bs += counted_bytes(M.n, L.nnz - M.n, U.nnz - M.n, R, sv=4)
+            errs.append(_relerr(np, z32[seg], ref))
+        out["parity_relerr_vs_oracle_sampled"] = max(errs)
+        out["cpu_baseline"] = {"value": round(bs / ts / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+                               "sample": "%d of the 256 systems (every 16th), one FP32 L+U application with 8 RHS "
+                                         "each (serial C substitution)" % len(pick),
+                               "seconds": round(ts, 4)}
+    return out
+
+
 def run_config(cfg, args):
     """Secondary workloads (one JSON line each): 3 = mixed precision on
     heterogeneous ILUT, 4 = RAS with 16 RHS, 5 = 256 batched systems,
@@ -201,113 +436,13 @@ def run_config(cfg, args):
     torch.cuda.set_device(0)
     out = {"metric": "L+U solve GB/s & solves/s, FP64 vs FP32+refine/batched, at 1e-10 rel resid",
            "unit": "GB/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic", "config": {}}
-    if cfg == 3:
-        A = synth.diffusion3d(100, None, None, 2.0, seed=3)
-        n = A.n
-        Aop = H.hec_from_csr(A)
-        b = torch.from_numpy(synth.rhs(n, 1, 3)).cuda()
-        res = {}
-        for fdt in ("f64", "f32"):
-            _log("config 3: ILUT setup, %s factors" % fdt)
-            t0 = time.time()
-            f = H.ilu_setup(A, "ilut", p=10, tol=1e-3, factor_dtype=fdt, tune=_tune(H, args))
-            setup = time.time() - t0
-            pl, pu = H.ilu_plans(f)
-            stl, stu = H.tri_plan_stats(pl), H.tri_plan_stats(pu)
-            sv = 8 if fdt == "f64" else 4
-            B = counted_bytes(n, stl["nnz_offdiag"], stu["nnz_offdiag"], 1, sv=sv)
-            z = torch.empty_like(b)
-            _log("config 3: timing applies (%s)" % fdt)
-            ms = _time_apply(H, torch, f, b, z, args.steps, args.warmup)
-            _log("config 3: FGMRES (%s)" % fdt)
-            x, kr = (torch.zeros_like(b), None) if args.no_krylov else _krylov(H, torch, f, Aop, b, "fgmres")
-            res[fdt] = {"apply_ms": round(ms, 4), "apply_GBps": round(B / (ms * 1e-3) / 1e9, 3),
-                        "nlev_L": stl["nlev"], "nlev_U": stu["nlev"], "nnz_offdiag_L": stl["nnz_offdiag"],
-                        "nnz_offdiag_U": stu["nnz_offdiag"], "setup_s": round(setup, 3), "fgmres": kr,
-                        "dataflow": stl["dataflow"], "ell_width_L": stl["ell_width"],
-                        "nnz_tail_L": stl["nnz_tail"], "x": x}
-        d = None if args.no_krylov else \
-            (res["f32"]["x"] - res["f64"]["x"]).norm().item() / res["f64"]["x"].norm().item()
-        for k in res:
-            res[k].pop("x")
-        out.update({"value": res["f32"]["apply_GBps"], "dtype": "f32 factors, f64 refinement",
-                    "ms_per_step": res["f32"]["apply_ms"],
-                    "config": {"workload": "heterogeneous 3D 7-point diffusion 100^3, lognormal sigma=2 seed 3, "
-                                           "ILUT(tol 1e-3, p 10); FGMRES(30) to 1e-10"},
-                    "fp64": res["f64"], "fp32_refined": res["f32"], "rel_diff_fp32_vs_fp64_solution": d,
-                    "fp32_time_ratio_vs_fp64": None if args.no_krylov else
-                    round(res["f32"]["fgmres"]["seconds"] / res["f64"]["fgmres"]["seconds"], 4)})
-    elif cfg == 4:
-        A = synth.poisson3d(128)
-        n = A.n
-        owner, sizes = synth.subdomain_cuts(n, 64, 8192, 61440, seed=4)
-        _log("config 4: RAS setup")
-        t0 = time.time()
-        s = H.ras_setup(A, 64, owner, overlap=1, factor_dtype="f32", tune=_tune(H, args, max_nrhs=16))
-        setup = time.time() - t0
-        nsub, tot, ext = H.ras_info(s)
-        pl, pu = H.ras_plans(s)
-        stl, stu = H.tri_plan_stats(pl), H.tri_plan_stats(pu)
-        R = 16
-        # FP32 factor side on the extended rows, FP64 gather of r and prolongation of z
-        B = (stl["nnz_offdiag"] + stu["nnz_offdiag"]) * 8 + tot * 4 + 2 * 4 * tot + R * (2 * tot * 4 + 2 * n * 8)
-        r = torch.from_numpy(synth.rhs(n, R, 4)).cuda()
-        z = torch.empty_like(r)
-        _log("config 4: timing applies")
-        ms = _time_apply(H, torch, s, r, z, max(3, args.steps // 5), 2, ras=True)
-        Aop = H.hec_from_csr(A)
-        _log("config 4: BiCGSTAB")
-        x, kr = (None, None) if args.no_krylov else _krylov(H, torch, s, Aop, r, "bicgstab")
-        out.update({"value": round(B / (ms * 1e-3) / 1e9, 3), "dtype": "f32 factors, f64 outer",
-                    "ms_per_step": round(ms, 4),
-                    "config": {"workload": "RAS on 128^3 Poisson: 64 seeded contiguous subdomains (8192..61440 "
-                                           "rows), overlap 1, ILU(0) per subdomain, 16 RHS; BiCGSTAB to 1e-10",
-                               "extended_rows": int(tot), "nlev_L": stl["nlev"], "nlev_U": stu["nlev"],
-                               "setup_s": round(setup, 3), "dataflow": stl["dataflow"],
-                               "syncfree": stl["syncfree"], "workgroups": stl["num_groups"]},
-                    "solves_per_s": round(1000.0 * R / ms, 2), "bicgstab": kr})
-    elif cfg == 5:
-        _log("config 5: generating systems")
-        shapes = synth.batch_systems(256, seed=5)
-        mats = []
-        for i, (dim, side) in enumerate(shapes):
-            if dim == 2:
-                mats.append(synth.diffusion2d(side, None, 1.0, seed=5000 + i))
-            else:
-                mats.append(synth.diffusion3d(side, None, None, 1.0, seed=5000 + i))
-        A, sys_ptr = _block_diag(mats)
-        n = A.n
-        R = 8
-        b = torch.from_numpy(synth.rhs(n, R, 5)).cuda()
-        Aop = H.hec_from_csr(A)
-        res = {}
-        for fdt in ("f64", "f32"):
-            _log("config 5: batch ILU(1) setup, %s factors" % fdt)
-            t0 = time.time()
-            f = H.batch_setup(A, sys_ptr, "iluk", k=1, factor_dtype=fdt, tune=_tune(H, args, max_nrhs=R))
-            setup = time.time() - t0
-            pl, pu = H.ilu_plans(f)
-            stl, stu = H.tri_plan_stats(pl), H.tri_plan_stats(pu)
-            sv = 8 if fdt == "f64" else 4
-            B = counted_bytes(n, stl["nnz_offdiag"], stu["nnz_offdiag"], R, sv=sv)
-            z = torch.empty_like(b)
-            _log("config 5: timing applies (%s)" % fdt)
-            ms = _time_apply(H, torch, f, b, z, max(3, args.steps // 5), 2)
-            _log("config 5: batched FGMRES, one problem per (system, rhs) (%s)" % fdt)
-            x, kr = (None, None) if args.no_krylov else _krylov_batch(H, torch, f, Aop, sys_ptr, b, "fgmres")
-            res[fdt] = {"apply_ms": round(ms, 4), "apply_GBps": round(B / (ms * 1e-3) / 1e9, 3),
-                        "nlev_L": stl["nlev"], "nlev_U": stu["nlev"], "setup_s": round(setup, 3), "fgmres": kr,
-                        "dataflow": stl["dataflow"], "syncfree": stl["syncfree"], "workgroups": stl["num_groups"],
-                        "systems_per_s": None if kr is None else round(len(mats) * R / kr["seconds"], 3)}
-        out.update({"value": res["f32"]["apply_GBps"], "dtype": "f32 factors, f64 refinement",
-                    "ms_per_step": res["f32"]["apply_ms"],
-                    "config": {"workload": "256 independent systems (log-uniform 1e3..2e5 rows, 2D/3D lognormal "
-                                           "sigma=1), ILU(1), 8 RHS each; batched FGMRES(30), each (system, rhs) "
-                                           "to 1e-10",
-                               "n_total": int(n), "systems": len(mats)},
-                    "fp64": res["f64"], "fp32_refined": res["f32"],
-                    "fp32_speedup_vs_fp64_time_to_1e-10": None if args.no_krylov else
-                    round(res["f64"]["fgmres"]["seconds"] / res["f32"]["fgmres"]["seconds"], 4)})
+    if cfg in (3, 4, 5):
+        d = {3: _cfg3, 4: _cfg4, 5: _cfg5}[cfg](H, torch, np, synth, args)
+        main = d if cfg == 4 else d["fp32_refined"]
+        out.update({"value": main["apply_GBps"], "ms_per_step": main["apply_ms"],
+                    "dtype": "f32 factors, f64 refinement" if cfg != 4 else "f32 factors, f64 outer",
+                    "config": {"workload": d["workload"]}, "roofline": main["roofline"],
+                    "cpu_baseline": d.get("cpu_baseline"), "detail": d})
     elif cfg == 6:
         out.update(_table1(H, torch, np, synth, args))
     elif cfg == 7:
@@ -453,6 +588,8 @@ def main(argv=None):
                     help="skip the device refactorization and the per-application (warm/cold) timings, so a "
                          "profiler sees only the warmup and timed applications")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="default run: skip the sub-results of configs 3, 4 and 5")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one device copy of this size (for counter calibration)")
@@ -630,6 +767,13 @@ def main(argv=None):
                                  "sample": "%d full L+U applications of the same system" % reps,
                                  "seconds_per_apply": round(cp, 5),
                                  "bit_identical_to_oracle": bool(np.array_equal(zp, zr))}
+    if not args.no_secondary:
+        # the metric's FP32+refinement and batched halves, on the other
+        # workloads of the benchmark family (each with its own roofline and
+        # CPU oracle baseline)
+        out["secondary"] = {"config3_ilut_mixed_precision": _cfg3(H, torch, np, synth, args),
+                            "config4_ras_16rhs": _cfg4(H, torch, np, synth, args),
+                            "config5_batch256": _cfg5(H, torch, np, synth, args)}
     out["paper_context"] = ("paper (Tesla C2050 vs Xeon X5570, FP64): triangular solves ~7x, "
                             "linear solver ~10x; another machine, not a target")
     print(json.dumps(out))
