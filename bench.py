@@ -223,6 +223,26 @@ def _graph_ms(H, torch, M, r, z, reps):
     return e0.elapsed_time(e1) / reps
 
 
+_NATIVE = {}
+
+
+def _native_oracle():
+    """Switch the oracle to a -O3 -march=native build made on this host (the
+    CPU baseline's build; same arithmetic as the test build).  Returns a
+    description of the build that is timed."""
+    import tempfile
+
+    import oracle
+
+    if "build" not in _NATIVE:
+        try:
+            oracle.use_native_build(tempfile.mkdtemp(prefix="orc_native_"))
+            _NATIVE["build"] = "gcc -O3 -march=native -ffp-contract=off, built on this host"
+        except Exception as e:  # no compiler: the test build (-O2) is timed instead
+            _NATIVE["build"] = "gcc -O2 -ffp-contract=off (native build failed: %s)" % e
+    return _NATIVE["build"]
+
+
 def _cpu_time(fn, budget):
     """Seconds per call of fn over about `budget` seconds (at least one call)."""
     fn()
@@ -276,12 +296,13 @@ def _cfg3(H, torch, np, synth, args):
             L = synth.CSR(n, *H.ilu_factor(f, 0))
             U = synth.CSR(n, *H.ilu_factor(f, 1))
             rr = b.cpu().numpy()
+            build = _native_oracle()
             cs, reps = _cpu_time(lambda: oracle.ilu_apply(L, U, rr), args.cpu_seconds / 5)
             row["parity_relerr_vs_oracle"] = _relerr(np, z.cpu().numpy(), oracle.ilu_apply(L, U, rr))
             res["cpu_baseline"] = {"value": round(B / cs / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
                                    "sample": "%d full L+U applications of the 100^3 ILUT system (serial C "
                                              "substitution, FP64 factors)" % reps,
-                                   "seconds_per_apply": round(cs, 5)}
+                                   "seconds_per_apply": round(cs, 5), "build": build}
         res[fdt] = row
     out = {"workload": "heterogeneous 3D 7-point diffusion 100^3 (n=1000000), lognormal sigma=2 seed 3, "
                        "ILUT(tol 1e-3, p 10), 1 RHS; FGMRES(30) to 1e-10",
@@ -330,6 +351,7 @@ def _cfg4(H, torch, np, synth, args):
         _, out["bicgstab"] = _krylov(H, torch, s, H.hec_from_csr(A), r, "bicgstab")
     if not args.no_cpu_baseline:
         _log("config 4: CPU oracle")
+        build = _native_oracle()
         doms32 = oracle.ras_to_f32(oracle.ras_setup(A, owner, 64, overlap=1))
         rr = r.cpu().numpy()
         ref = oracle.ras_apply_f32(doms32, rr)
@@ -339,7 +361,7 @@ def _cfg4(H, torch, np, synth, args):
         cs = time.time() - t0
         out["cpu_baseline"] = {"value": round(B / cs / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
                                "sample": "1 full RAS application, 64 subdomains x 16 RHS (serial C substitution "
-                                         "per subdomain, FP32)", "seconds_per_apply": round(cs, 4)}
+                                         "per subdomain, FP32)", "seconds_per_apply": round(cs, 4), "build": build}
     return out
 
 
@@ -401,6 +423,7 @@ def _cfg5(H, torch, np, synth, args):
                                                          res["f32"]["fgmres"]["seconds"], 4)
     if not args.no_cpu_baseline:
         _log("config 5: CPU oracle on a sample of systems")
+        build = _native_oracle()
         pick = list(range(0, len(mats), 16))
         rr = b.cpu().numpy()
         bs, ts, errs = 0, 0.0, []
@@ -418,7 +441,7 @@ def _cfg5(H, torch, np, synth, args):
         out["cpu_baseline"] = {"value": round(bs / ts / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
                                "sample": "%d of the 256 systems (every 16th), one FP32 L+U application with 8 RHS "
                                          "each (serial C substitution)" % len(pick),
-                               "seconds": round(ts, 4)}
+                               "seconds": round(ts, 4), "build": build}
     return out
 
 
@@ -740,6 +763,8 @@ def main(argv=None):
 
         L, U = oracle.ilu0(A)
         rr = synth.rhs(n, 1, 2)
+        z_test_build = oracle.ilu_apply(L, U, rr)
+        build = _native_oracle()
         oracle.ilu_apply(L, U, rr)  # warm
         reps, t2 = 0, time.time()
         while time.time() - t2 < args.cpu_seconds:
@@ -751,7 +776,8 @@ def main(argv=None):
         out["cpu_baseline"] = {"value": round(B / cs / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
                                "sample": "%d full L+U applications of the same %d^3 system (serial C "
                                          "substitution on CSR, natural order)" % (reps, s),
-                               "seconds_per_apply": round(cs, 5)}
+                               "seconds_per_apply": round(cs, 5), "build": build,
+                               "identical_to_test_build": bool(np.array_equal(zr, z_test_build))}
         out["parity_relerr_vs_oracle"] = err
         # multithreaded level-scheduled CPU solve (Algorithm 2 on all host
         # cores), bit-identical to the serial substitution above

@@ -58,10 +58,10 @@ typedef enum hec_uplo { HEC_LOWER = 0, HEC_UPPER = 1 } hec_uplo_t;
 /* How the level sets are executed on the device (all give bit-identical
  * results for the same plan, since every row is computed the same way). */
 typedef enum hec_schedule {
-    HEC_SCHED_AUTO = 0,              /* the owner schedule on the dataflow kernel: one part
-                                        per workgroup when the LDS holds every part for
-                                        max_nrhs right-hand sides, else parts taken from a
-                                        queue (kernel_variant 6) */
+    HEC_SCHED_AUTO = 0,              /* the owner schedule on the dataflow kernel when its LDS
+                                        holds every part for max_nrhs right-hand sides, else
+                                        the barrier-free kernel or one launch per level
+                                        (see kernel_variant) */
     HEC_SCHED_LEVEL_LAUNCH = 1,      /* one kernel launch per level (Algorithm 2 shape) */
     HEC_SCHED_LEVEL_PERSISTENT = 2,  /* one persistent launch; each level split into
                                         per-workgroup chunks; a chunk polls the values it
@@ -120,17 +120,19 @@ typedef struct hec_tune {
                                order that fit the LDS (part_rows sets a first cut), systems
                                with the most levels first, and the workgroups take parts from
                                a queue in that order: a part reads only from earlier parts,
-                               so the solve needs no co-residency.  Schedule AUTO picks 4 when
-                               every part fits one workgroup per part, else 6; 5 or one launch
-                               per level only when neither applies */
+                               so the solve needs no co-residency (on request only).
+                               Schedule AUTO picks the dataflow kernel when its LDS holds
+                               every part, else 5 when the levels are narrow (fewer than 2^17
+                               (row, rhs) items per level on average), else one launch per
+                               level */
 } hec_tune_t;
 
 /* Per-RHS outcome of krylov_solve. */
 typedef struct hec_krylov_info {
     int32_t status;          /* HEC_OK (true relative residual <= rtol), HEC_ERR_NOT_CONVERGED
-                                (maxit reached), HEC_ERR_BREAKDOWN (a zero or non-finite
-                                scalar, or a non-finite residual, stopped this RHS) or
-                                HEC_ERR_INVALID_ARG (b holds a NaN or infinity; not iterated) */
+                                (maxit reached) or HEC_ERR_BREAKDOWN (a zero or non-finite
+                                scalar or residual stopped this RHS; a b holding a NaN or an
+                                infinity is not iterated at all) */
     int32_t iters;           /* Krylov iterations (Arnoldi steps / BiCGSTAB steps) */
     int32_t restarts;        /* completed restart cycles */
     int32_t precond_applies; /* preconditioner applications */
@@ -406,8 +408,9 @@ void sor_destroy(sor_t sor);
  * [n][nrhs]; x holds x0 on entry.  info: host array of nrhs entries.
  * A NaN never counts as converged: each RHS stops on its own at a non-finite
  * value, and its x is then left as it was before the step that produced it.
- * Returns HEC_OK if every RHS converged; else the first INVALID_ARG or
- * BREAKDOWN among the RHS, else NOT_CONVERGED (per-RHS outcome in info).
+ * Returns HEC_OK if every RHS converged; else BREAKDOWN if any RHS broke
+ * down, else NOT_CONVERGED (per-RHS outcome in info); INVALID_ARG and the
+ * other codes report an unusable call (info is then not filled).
  * ------------------------------------------------------------------------- */
 hec_status_t krylov_solve(hec_matrix_t A, hec_precond_t M, hec_krylov_t method, int32_t m,
                           const double *b, double *x, int32_t nrhs, double rtol, int32_t maxit,
@@ -438,13 +441,28 @@ hec_status_t hec_graph_launch(hec_graph_t g, hipStream_t stream);
 void hec_graph_destroy(hec_graph_t g);
 
 /* ---------------------------------------------------------------------------
- * Autotuner: times candidate schedules, ELL widths, level-merge thresholds
- * and lane-group widths for the solve L x = b with nrhs right-hand sides on
- * the current device and writes the fastest tuning to *best (its time per
- * solve in microseconds to *best_us).  The inputs are those of tri_analyze.
- * ------------------------------------------------------------------------- */
+ * Autotuner: times candidate execution layouts of the solve L x = b (or
+ * U x = b) with nrhs right-hand sides on the current device and writes the
+ * fastest tuning to *best (its time per solve in microseconds to *best_us).
+ * Candidates, cheapest first: the automatic choice; the dataflow kernel with
+ * one part per workgroup for 2, 4 and 6 compute wavefronts (the rows each
+ * wavefront walks per level) and automatic, contiguous and bisection parts;
+ * the part queue (kernel_variant 6) for 4 and 6 wavefronts and automatic,
+ * 1024 and 4096 rows per part; the barrier-free kernel; one launch per
+ * level; the level-persistent schedule at two level-merge thresholds; and
+ * wider ELL parts when rows overflow the automatic width.  nsys > 0 with
+ * sys_ptr[nsys+1] marks independent diagonal blocks (batch_setup's systems,
+ * RAS subdomains), as the setups pass them.  max_seconds > 0 stops starting
+ * new candidates after that much time (the automatic choice is always
+ * timed).  cache_path (may be NULL): a file of JSON lines keyed by a
+ * signature of the problem (n, nnz, triangle, unit diagonal, nrhs, type,
+ * blocks and the histogram of level sizes); a hit returns the stored tuning
+ * without timing anything, a miss appends the new result.  The inputs are
+ * those of tri_analyze.  Errors: as tri_analyze, INVALID_ARG for an
+ * unwritable cache, CAPACITY when no candidate runs. */
 hec_status_t tri_autotune(int32_t n, const int32_t *rowptr, const int32_t *col, const void *val,
-                          hec_dtype_t dt, hec_uplo_t uplo, int32_t unit_diag, int32_t nrhs,
+                          hec_dtype_t dt, hec_uplo_t uplo, int32_t unit_diag, int32_t nrhs, int32_t nsys,
+                          const int32_t *sys_ptr, const char *cache_path, double max_seconds,
                           hipStream_t stream, hec_tune_t *best, double *best_us);
 
 #ifdef __cplusplus

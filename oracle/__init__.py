@@ -31,7 +31,23 @@ _lib = None
 def _L():
     global _lib
     if _lib is None:
-        lib = ctypes.CDLL(_build.build())
+        _lib = _bind(ctypes.CDLL(_build.build()))
+    return _lib
+
+
+def use_native_build(dest_dir: str) -> str:
+    """Switch this process to a -O3 -march=native build of the oracle made
+    for the current host in dest_dir (the benchmark's CPU baseline); the
+    arithmetic is unchanged (no contraction, no reassociation).  Returns the
+    library path."""
+    global _lib
+    path = _build.build_native(dest_dir)
+    _lib = _bind(ctypes.CDLL(path))
+    return path
+
+
+def _bind(lib):
+    if True:
         i32, vp = ctypes.c_int32, ctypes.c_void_p
         for name in ("orc_lower_solve", "orc_upper_solve", "orc_lower_solve_f32",
                      "orc_upper_solve_f32"):
@@ -55,8 +71,7 @@ def _L():
         lib.orc_sor.argtypes = [i32, vp, vp, vp, ctypes.c_double, i32, vp, vp, i32, ctypes.c_int]
         lib.orc_free.restype = None
         lib.orc_free.argtypes = [vp]
-        _lib = lib
-    return _lib
+    return lib
 
 
 class OracleError(RuntimeError):

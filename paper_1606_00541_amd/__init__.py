@@ -113,7 +113,8 @@ SIGNATURES = {
     "hec_graph_capture": (_i32, [Precond, _vp, _vp, _i32, _i32, _vp, _P(_vp)]),
     "hec_graph_launch": (_i32, [_vp, _vp]),
     "hec_graph_destroy": (None, [_vp]),
-    "tri_autotune": (_i32, [_i32, _vp, _vp, _vp, _i32, _i32, _i32, _i32, _vp, _P(Tune), _P(_f64)]),
+    "tri_autotune": (_i32, [_i32, _vp, _vp, _vp, _i32, _i32, _i32, _i32, _i32, _vp, ctypes.c_char_p, _f64, _vp,
+                            _P(Tune), _P(_f64)]),
 }
 
 _lib = None
@@ -356,12 +357,19 @@ def tri_solve_upper(plan, b, x, stream=None):
     _check(lib().tri_solve_upper(plan.ptr, pb, px, R, db, _stream(stream)))
 
 
-def tri_autotune(T, uplo="lower", unit_diag=False, dtype="f64", nrhs=1, stream=None):
+def tri_autotune(T, uplo="lower", unit_diag=False, dtype="f64", nrhs=1, sys_ptr=None, cache=None,
+                 max_seconds=0.0, stream=None):
+    """Fastest tuning for solving with T (and its time per solve in us);
+    sys_ptr marks independent systems, cache is a JSON-lines file path."""
     n, rp, ci, v = _csr(T, np.float64 if _dt(dtype) == HEC_F64 else np.float32)
     best = Tune()
     us = ctypes.c_double()
     up = HEC_UPPER if uplo in ("upper", HEC_UPPER) else HEC_LOWER
+    sp = None if sys_ptr is None else _np(sys_ptr, np.int32)
+    nsys = 0 if sp is None else len(sp) - 1
     _check(lib().tri_autotune(n, _ptr(rp), _ptr(ci), _ptr(v), _dt(dtype), up, int(bool(unit_diag)), int(nrhs),
+                              nsys, None if sp is None else sp.ctypes.data,
+                              None if cache is None else os.fsencode(cache), float(max_seconds),
                               _stream(stream), ctypes.byref(best), ctypes.byref(us)))
     return best, us.value
 

@@ -1066,20 +1066,6 @@ TriHost analyze(const Csr &a, bool upper, bool unit, hec_dtype_t dt, const Tune 
             } catch (const Error &e) {
                 if (e.code != HEC_ERR_CAPACITY) throw;
             }
-            // too large for one part per workgroup: the same kernel with more
-            // parts than workgroups, taken from a queue (every part fits the
-            // LDS; parts are cut per system and split until they do)
-            if (auto_sched) {
-                d.variant = 6;
-                try {
-                    t.variant = 6;
-                    attempt(d);
-                    return t;
-                } catch (const Error &e) {
-                    if (e.code != HEC_ERR_CAPACITY) throw;
-                    t.variant = tu.variant;
-                }
-            }
         }
         if (auto_sched) {
             // too large for LDS: the barrier-free kernel when levels are

@@ -6,6 +6,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <string>
+#include <cstdlib>
+#include <cstdio>
+#include <chrono>
 #include <functional>
 #include <memory>
 #include <new>
@@ -135,9 +139,10 @@ void upload_tri(DevTri &d, const TriHost &t, int32_t max_nrhs)
                 d.df_step_rows = std::max(d.df_step_rows, s.step_row[2 * q + 1] - s.step_row[2 * q]);
         }
         d.max_lanes_one = std::all_of(s.step_lanes.begin(), s.step_lanes.end(), [](int32_t v) { return v == 1; });
-        d.epoch.alloc(4 * sizeof(unsigned int));  // epoch, workgroups done, part queue
-        hip_check(hipMemset(d.epoch.p, 0, d.epoch.bytes), "hipMemset");
     }
+    // epoch, workgroups done, work counter (part queue / chunk batches)
+    d.epoch.alloc(4 * sizeof(unsigned int));
+    hip_check(hipMemset(d.epoch.p, 0, d.epoch.bytes), "hipMemset");
     d.err.alloc(sizeof(int));
     hip_check(hipMemset(d.err.p, 0, sizeof(int)), "hipMemset");
     void *hp = nullptr;
@@ -163,15 +168,26 @@ bool take_abort(const DevTri &d)
 }
 }  // namespace
 
+// Launches of the plan may still be in flight when an abort is seen (the
+// host issues work ahead): let them finish, so that none raises the flag
+// again after it is cleared, then clear and report once.
+static bool abort_seen(const DevTri &d) { return d.err_host && *static_cast<volatile int *>(d.err_host) != 0; }
+
 void check_device_error(const DevTri &d)
 {
-    if (take_abort(d)) fail(HEC_ERR_TIMEOUT, "a persistent solve aborted a device-side wait (spin limit reached)");
+    if (!abort_seen(d)) return;
+    (void)hipDeviceSynchronize();
+    take_abort(d);
+    fail(HEC_ERR_TIMEOUT, "a persistent solve aborted a device-side wait (spin limit reached)");
 }
 
 void check_device_error(const DevTri &a, const DevTri &b)
 {
-    const bool ea = take_abort(a), eb = take_abort(b);  // both cleared: one report per abort
-    if (ea || eb) fail(HEC_ERR_TIMEOUT, "a persistent solve aborted a device-side wait (spin limit reached)");
+    if (!abort_seen(a) && !abort_seen(b)) return;
+    (void)hipDeviceSynchronize();
+    take_abort(a);  // both cleared: one report per abort
+    take_abort(b);
+    fail(HEC_ERR_TIMEOUT, "a persistent solve aborted a device-side wait (spin limit reached)");
 }
 
 }  // namespace hec
@@ -1024,58 +1040,146 @@ hec_status_t hec_graph_launch(hec_graph_t g, hipStream_t st)
 void hec_graph_destroy(hec_graph_t g) { delete g; }
 
 hec_status_t tri_autotune(int32_t n, const int32_t *rowptr, const int32_t *col, const void *val, hec_dtype_t dt,
-                          hec_uplo_t uplo, int32_t unit_diag, int32_t nrhs, hipStream_t st, hec_tune_t *best,
+                          hec_uplo_t uplo, int32_t unit_diag, int32_t nrhs, int32_t nsys, const int32_t *sys_ptr,
+                          const char *cache_path, double max_seconds, hipStream_t st, hec_tune_t *best,
                           double *best_us)
 {
     return guard([&] {
         if (!best || nrhs < 1) fail(HEC_ERR_INVALID_ARG, "bad arguments");
         if (uplo != HEC_LOWER && uplo != HEC_UPPER) fail(HEC_ERR_INVALID_ARG, "bad uplo");
+        if (nsys < 0 || (nsys > 0 && !sys_ptr)) fail(HEC_ERR_INVALID_ARG, "bad system blocks");
         Csr a = csr_copy(n, rowptr, col, val, dt);
         const bool upper = uplo == HEC_UPPER, unit = unit_diag != 0;
         validate_triangle(a, upper, unit);
+        std::vector<int32_t> blocks;
+        if (nsys > 0) {
+            blocks.assign(sys_ptr, sys_ptr + nsys + 1);
+            if (blocks.front() != 0 || blocks.back() != n) fail(HEC_ERR_INVALID_ARG, "sys_ptr must run from 0 to n");
+            for (int32_t q = 0; q < nsys; ++q)
+                if (blocks[q + 1] < blocks[q]) fail(HEC_ERR_INVALID_ARG, "sys_ptr not monotone");
+        }
+        const std::vector<int32_t> *bp = blocks.empty() ? nullptr : &blocks;
+        // signature of the problem: sizes, type, right-hand sides, blocks and
+        // the level histogram (eq. (2)-(3)), FNV-1a hashed
+        const Levels lv = compute_levels(a, upper);
+        uint64_t h = 1469598103934665603ull;
+        auto mix = [&](int64_t v) {
+            for (int b = 0; b < 8; ++b) {
+                h ^= (uint64_t)((v >> (8 * b)) & 0xff);
+                h *= 1099511628211ull;
+            }
+        };
+        for (int64_t v : {(int64_t)n, (int64_t)a.nnz(), (int64_t)upper, (int64_t)unit, (int64_t)nrhs, (int64_t)dt,
+                          (int64_t)nsys})
+            mix(v);
+        for (int32_t k = 0; k < lv.nlev; ++k) mix(lv.levelptr[k + 1] - lv.levelptr[k]);
+        for (int32_t v : blocks) mix(v);
+        char sig[64];
+        std::snprintf(sig, sizeof sig, "%016llx", (unsigned long long)h);
+        static const char *kFields[] = {"ell_width", "schedule", "num_groups", "merge_rows", "group_lanes",
+                                        "long_row", "part_rows", "max_nrhs", "block_threads", "chunk_rows",
+                                        "partition", "kernel_variant"};
+        auto field = [](hec_tune_t &t, int i) -> int32_t & {
+            int32_t *f[] = {&t.ell_width, &t.schedule,  &t.num_groups,    &t.merge_rows,
+                            &t.group_lanes, &t.long_row, &t.part_rows,    &t.max_nrhs,
+                            &t.block_threads, &t.chunk_rows, &t.partition, &t.kernel_variant};
+            return *f[i];
+        };
+        // cache: one JSON object per line, {"sig": "...", "us": t, "tune": {...}}; the last line
+        // with a matching signature wins
+        if (cache_path && *cache_path) {
+            std::FILE *fp = std::fopen(cache_path, "r");
+            if (fp) {
+                char line[4096];
+                bool found = false;
+                hec_tune_t got;
+                double got_us = 0;
+                const std::string key = std::string("\"sig\": \"") + sig + "\"";
+                while (std::fgets(line, sizeof line, fp)) {
+                    const std::string ln(line);
+                    if (ln.find(key) == std::string::npos) continue;
+                    hec_tune_default(&got);
+                    bool ok = true;
+                    for (int i = 0; i < 12 && ok; ++i) {
+                        const std::string fk = std::string("\"") + kFields[i] + "\": ";
+                        const size_t pos = ln.find(fk);
+                        if (pos == std::string::npos) ok = false;
+                        else field(got, i) = (int32_t)std::strtol(ln.c_str() + pos + fk.size(), nullptr, 10);
+                    }
+                    const size_t pu = ln.find("\"us\": ");
+                    if (ok && pu != std::string::npos) {
+                        got_us = std::strtod(ln.c_str() + pu + 6, nullptr);
+                        found = true;
+                    }
+                }
+                std::fclose(fp);
+                if (found) {
+                    *best = got;
+                    if (best_us) *best_us = got_us;
+                    return;
+                }
+            }
+        }
         const int32_t w0 = auto_ell_width(a, upper);
-        // candidate grid: schedule x block size x level-merge threshold x ELL width
+        int32_t wmax = 0;
+        for (int32_t i = 0; i < a.n; ++i) wmax = std::max(wmax, a.rp[i + 1] - a.rp[i] - (unit ? 0 : 1));
+        // candidates, cheapest first: the automatic choice; the dataflow kernel
+        // with one part per workgroup (compute wavefronts x partition shape);
+        // the part queue (compute wavefronts x rows per part); the barrier-free
+        // kernel; one launch per level; the level-persistent schedule with
+        // level-merge thresholds; wider ELL parts when rows overflow
         std::vector<Tune> cands;
         Tune base = default_tune();
         base.max_nrhs = nrhs;
-        for (int32_t blk : {256, 384}) {  // dataflow owner kernel (64 * blk / 64 compute lanes)
-            Tune t = base;
-            t.block_threads = blk;
-            t.schedule = HEC_SCHED_OWNER_PERSISTENT;
-            t.variant = 4;
-            if (nrhs <= 64) cands.push_back(t);
+        cands.push_back(base);
+        if (nrhs <= 64) {
+            for (int32_t blk : {256, 128, 384})
+                for (int32_t part : {0, 1, 2}) {
+                    Tune t = base;
+                    t.schedule = HEC_SCHED_OWNER_PERSISTENT;
+                    t.variant = 4;
+                    t.block_threads = blk;
+                    t.partition = part;
+                    cands.push_back(t);
+                }
+            for (int32_t blk : {256, 384})
+                for (int32_t rows : {0, 1024, 4096}) {
+                    Tune t = base;
+                    t.schedule = HEC_SCHED_OWNER_PERSISTENT;
+                    t.variant = 6;
+                    t.block_threads = blk;
+                    t.part_rows = rows;
+                    cands.push_back(t);
+                }
+            if (wmax > w0 && wmax <= 16) {
+                Tune t = base;
+                t.schedule = HEC_SCHED_OWNER_PERSISTENT;
+                t.variant = 4;
+                t.ell_width = dataflow_width(std::max(1, (w0 + wmax) / 2));
+                cands.push_back(t);
+            }
         }
-        for (int32_t blk : {256, 512}) {
+        {
             Tune t = base;
-            t.block_threads = blk;
-            t.chunk_rows = std::max(256, blk);
-            t.schedule = HEC_SCHED_OWNER_PERSISTENT;
-            t.variant = 2;
+            t.schedule = HEC_SCHED_LEVEL_LAUNCH;
+            t.variant = 5;
             cands.push_back(t);
-            for (int32_t mul : {1, 2, 4}) {
-                Tune u = base;
-                u.block_threads = blk;
-                u.chunk_rows = std::max(256, blk);
-                u.schedule = HEC_SCHED_LEVEL_PERSISTENT;
-                u.merge_rows = std::max(1, mul * blk / nrhs);
-                cands.push_back(u);
-            }
+            Tune u = base;
+            u.schedule = HEC_SCHED_LEVEL_LAUNCH;
+            cands.push_back(u);
         }
-        bool tails = false;
-        for (int32_t i = 0; i < a.n && !tails; ++i) tails = (a.rp[i + 1] - a.rp[i] - (unit ? 0 : 1)) > w0;
-        if (tails) {
-            const size_t m = cands.size();
-            for (size_t q = 0; q < m; ++q) {
-                Tune t = cands[q];
-                const bool df = t.variant == 4;  // one lane per row, ELL width at most 16
-                t.ell_width = df ? dataflow_width(std::min(16, w0 + 2)) : std::min(64, w0 + 2);
-                if (t.ell_width > w0) cands.push_back(t);
-                if (df) continue;
-                Tune u = cands[q];
-                u.group_lanes = 4;
-                u.long_row = 8;
-                cands.push_back(u);
-            }
+        for (int32_t mul : {1, 4}) {
+            Tune u = base;
+            u.schedule = HEC_SCHED_LEVEL_PERSISTENT;
+            u.merge_rows = std::max(1, mul * u.block_threads / nrhs);
+            cands.push_back(u);
+        }
+        if (wmax > w0) {
+            Tune u = base;
+            u.schedule = HEC_SCHED_LEVEL_PERSISTENT;
+            u.group_lanes = 4;
+            u.long_row = 8;
+            cands.push_back(u);
         }
         const hec_dtype_t vdt = dt;
         const size_t bytes = ((size_t)std::max(1, n)) * nrhs * (vdt == HEC_F64 ? 8 : 4);
@@ -1086,12 +1190,25 @@ hec_status_t tri_autotune(int32_t n, const int32_t *rowptr, const int32_t *col, 
         hipEvent_t e0, e1;
         hip_check(hipEventCreate(&e0), "hipEventCreate");
         hip_check(hipEventCreate(&e1), "hipEventCreate");
+        struct EvFree {
+            hipEvent_t a, b;
+            ~EvFree()
+            {
+                (void)hipEventDestroy(a);
+                (void)hipEventDestroy(b);
+            }
+        } ev_free{e0, e1};
         double best_t = 1e300;
         Tune best_tune = cands.front();
-        for (const Tune &t : cands) {
+        const auto t_start = std::chrono::steady_clock::now();
+        for (size_t ci = 0; ci < cands.size(); ++ci) {
+            const Tune &t = cands[ci];
+            if (ci > 0 && max_seconds > 0 &&
+                std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count() > max_seconds)
+                break;
             tri_plan_s p;
             try {
-                build_plan(p, a, upper, unit, dt, t);
+                build_plan(p, a, upper, unit, dt, t, bp);
                 for (int rep = 0; rep < 2; ++rep) solve_one(&p, b.p, x.p, nrhs, vdt, st, upper);
                 hip_check(hipEventRecord(e0, st), "hipEventRecord");
                 const int reps = 5;
@@ -1108,15 +1225,12 @@ hec_status_t tri_autotune(int32_t n, const int32_t *rowptr, const int32_t *col, 
                     best_tune = t;
                 }
             } catch (const Error &e) {
-                if (e.code != HEC_ERR_CAPACITY && e.code != HEC_ERR_ALLOC && e.code != HEC_ERR_TIMEOUT) {
-                    (void)hipEventDestroy(e0);
-                    (void)hipEventDestroy(e1);
+                if (e.code != HEC_ERR_CAPACITY && e.code != HEC_ERR_ALLOC && e.code != HEC_ERR_TIMEOUT &&
+                    e.code != HEC_ERR_INVALID_ARG)
                     throw;
-                }
             }
         }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
+        if (best_t >= 1e300) fail(HEC_ERR_CAPACITY, "no candidate schedule could run this triangle");
         hec_tune_default(best);
         best->ell_width = best_tune.ell_width;
         best->schedule = best_tune.schedule;
@@ -1131,6 +1245,16 @@ hec_status_t tri_autotune(int32_t n, const int32_t *rowptr, const int32_t *col, 
         best->partition = best_tune.partition;
         best->kernel_variant = best_tune.variant;
         if (best_us) *best_us = best_t;
+        if (cache_path && *cache_path) {
+            std::FILE *fp = std::fopen(cache_path, "a");
+            if (!fp) fail(HEC_ERR_INVALID_ARG, std::string("cannot append to the tuning cache ") + cache_path);
+            std::fprintf(fp, "{\"sig\": \"%s\", \"n\": %d, \"nnz\": %lld, \"nlev\": %d, \"nrhs\": %d, \"dtype\": %d, "
+                             "\"us\": %.3f, \"tune\": {",
+                         sig, n, (long long)a.nnz(), lv.nlev, nrhs, (int)dt, best_t);
+            for (int i = 0; i < 12; ++i) std::fprintf(fp, "%s\"%s\": %d", i ? ", " : "", kFields[i], field(*best, i));
+            std::fprintf(fp, "}}\n");
+            std::fclose(fp);
+        }
     });
 }
 

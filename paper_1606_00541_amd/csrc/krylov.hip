@@ -498,10 +498,10 @@ void apply_M(const hec_precond_t &M, const double *r, double *z, int R, long n, 
 
 // Final outcome of every problem from its true residual norm^2 rr2[k]: a
 // finite relative residual at most rtol is a success (also after a lucky
-// breakdown); otherwise a problem keeps the error it stopped with
-// (INVALID_ARG: non-finite b; BREAKDOWN: zero or non-finite scalars) or is
-// NOT_CONVERGED.  A NaN never compares as converged.  The call returns the
-// first INVALID_ARG or BREAKDOWN, else the first NOT_CONVERGED, else OK.
+// breakdown); otherwise a problem keeps the BREAKDOWN it stopped with (a
+// non-finite b, a zero or non-finite scalar) or is NOT_CONVERGED.  A NaN
+// never compares as converged.  The call returns the first BREAKDOWN, else
+// the first NOT_CONVERGED, else OK.
 hec_status_t final_status(hec_krylov_info_t *info, const std::vector<double> &bnorm, const double *rr2, int P,
                           double rtol, hec_status_t hint)
 {
@@ -509,7 +509,7 @@ hec_status_t final_status(hec_krylov_info_t *info, const std::vector<double> &bn
     for (int k = 0; k < P; ++k) {
         const double rn = std::sqrt(rr2[k]);
         info[k].relres = !std::isfinite(bnorm[k]) ? std::nan("") : (bnorm[k] > 0 ? rn / bnorm[k] : rn);
-        if (info[k].status != HEC_ERR_INVALID_ARG && info[k].relres <= rtol) {
+        if (info[k].relres <= rtol) {
             info[k].status = HEC_OK;
             continue;
         }
@@ -581,7 +581,7 @@ hec_status_t gmres(const DevHec &A, const hec_precond_t &M, int m, const double 
         if (!std::isfinite(bnorm[k])) {
             // a NaN or infinity in b: this problem is not iterated
             done[k] = 1;
-            info[k].status = HEC_ERR_INVALID_ARG;
+            info[k].status = HEC_ERR_BREAKDOWN;
         } else if (bnorm[k] == 0.0) {
             done[k] = 1, zero_rhs = true;
         }
@@ -738,7 +738,7 @@ hec_status_t bicgstab(const DevHec &A, const hec_precond_t &M, const double *b, 
         if (!std::isfinite(bnorm[k])) {
             // a NaN or infinity in b: this problem is not iterated
             done[k] = 1;
-            info[k].status = HEC_ERR_INVALID_ARG;
+            info[k].status = HEC_ERR_BREAKDOWN;
         }
     }
     {

@@ -263,22 +263,21 @@ def test_auto_tuning_picks_the_dataflow_kernel_when_it_fits():
     L, _ = oracle.ilu0(A)
     st = H.tri_plan_stats(H.tri_analyze(L, unit_diag=True, tune=HOST))
     assert st["schedule"] == 3 and st["dataflow"] == 1
-    # one group cannot hold every row in LDS: the same kernel with more parts
-    # than workgroups, taken from a queue
+    # one group cannot hold every row in LDS: the level-ordered layout, run by
+    # the barrier-free kernel when levels are narrow ...
     A = synth.poisson2d(160)
     L, _ = oracle.ilu0(A)
     st = H.tri_plan_stats(H.tri_analyze(L, unit_diag=True, tune=H.tune_default(host_only=1, num_groups=1)))
-    assert st["schedule"] == 3 and st["dataflow"] == 1 and st["queue"] == 1 and st["num_groups"] > 1
-    # no dataflow kernel at all (more than 64 right-hand sides): the
-    # level-ordered layout, run by the barrier-free kernel when levels are
-    # narrow ...
-    st = H.tri_plan_stats(H.tri_analyze(L, unit_diag=True, tune=H.tune_default(host_only=1, max_nrhs=65)))
     assert st["schedule"] == 1 and st["dataflow"] == 0 and st["syncfree"] == 1
     # ... and by one launch per level when they are wide (2^17 items and more)
     n = (1 << 17) + 64
     D = CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.full(n, 2.0))
-    st = H.tri_plan_stats(H.tri_analyze(D, tune=H.tune_default(host_only=1, max_nrhs=65)))
+    st = H.tri_plan_stats(H.tri_analyze(D, tune=H.tune_default(host_only=1, num_groups=1)))
     assert st["schedule"] == 1 and st["nlev"] == 1 and st["syncfree"] == 0
+    # the part queue runs on request (kernel_variant 6)
+    st = H.tri_plan_stats(H.tri_analyze(L, unit_diag=True, tune=H.tune_default(
+        host_only=1, schedule="owner_persistent", kernel_variant=6)))
+    assert st["schedule"] == 3 and st["dataflow"] == 1 and st["queue"] == 1 and st["num_groups"] > 1
     # an explicit owner schedule falls back to the LDS-chunked owner kernel
     st = H.tri_plan_stats(H.tri_analyze(L, unit_diag=True, tune=H.tune_default(
         host_only=1, schedule="owner_persistent", num_groups=1)))

@@ -186,14 +186,45 @@ def test_owner_chunked_kernel_bit_identical_to_level_launch(block, chunk, nrhs, 
         assert np.array_equal(solve(pu, b, upper=True), solve(ref_plan_u, b, upper=True))
 
 
-def test_autotune_returns_a_working_tuning():
+def test_autotune_returns_a_working_tuning(tmp_path):
     A = synth.poisson3d(24)
     L, U = oracle.ilu0(A)
-    best, us = H.tri_autotune(U, "upper", nrhs=2)
-    assert us > 0 and best.schedule in (2, 3) and best.max_nrhs == 2
+    cache = str(tmp_path / "tune.jsonl")
+    best, us = H.tri_autotune(U, "upper", nrhs=2, cache=cache)
+    assert us > 0 and best.schedule in (0, 1, 2, 3) and best.max_nrhs == 2
     p = H.tri_analyze(U, "upper", tune=best)
     b = synth.rhs(A.n, 2, 3)
     assert relerr(solve(p, b, upper=True), oracle.upper_solve(U, b)) <= FP64_TOL
+    # the second call finds the problem's signature in the cache
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1 and '"nrhs": 2' in lines[0]
+    best2, us2 = H.tri_autotune(U, "upper", nrhs=2, cache=cache)
+    assert best2.as_dict() == best.as_dict() and abs(us2 - us) <= 1e-3 * us
+    assert len(open(cache).read().splitlines()) == 1
+    # another right-hand-side count is another problem
+    H.tri_autotune(U, "upper", nrhs=1, cache=cache, max_seconds=0.5)
+    assert len(open(cache).read().splitlines()) == 2
+
+
+def test_autotune_over_independent_systems():
+    mats = [synth.diffusion2d(30, 21, 1.0, seed=31), synth.diffusion3d(11, 10, 9, 1.0, seed=32),
+            synth.poisson2d(45, 7)]
+    import scipy.sparse as sp
+    m = sp.block_diag([Mi.to_scipy() for Mi in mats]).tocsr()
+    m.sort_indices()
+    A = CSR(m.shape[0], m.indptr.astype(np.int32), m.indices.astype(np.int32), m.data.copy())
+    sys_ptr = np.cumsum([0] + [Mi.n for Mi in mats]).astype(np.int32)
+    L, _ = oracle.iluk(A, 1)
+    best, us = H.tri_autotune(L, "lower", unit_diag=True, dtype="f32", nrhs=4, sys_ptr=sys_ptr)
+    assert us > 0
+    f = H.batch_setup(A, sys_ptr, "iluk", k=1, factor_dtype="f32", tune=best)
+    r = synth.rhs(A.n, 4, 33)
+    rt = dev(r)
+    zt = torch.empty_like(rt)
+    H.ilu_apply(f, rt, zt)
+    torch.cuda.synchronize()
+    L, U = oracle.iluk(A, 1)
+    assert relerr(zt.cpu().numpy(), oracle.ilu_apply_f32(oracle.to_f32(L), oracle.to_f32(U), r)) <= 1e-5
 
 
 def test_mailbox_recovers_across_rhs_widths():
