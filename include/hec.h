@@ -293,6 +293,23 @@ hec_status_t ilu_plans(ilu_t ilu, tri_plan_t *L, tri_plan_t *U);
  * vec_dt; r and z may alias. */
 hec_status_t ilu_apply(ilu_t ilu, const void *r, void *z, int32_t nrhs, hec_dtype_t vec_dt,
                        hipStream_t stream);
+/* ilu_apply for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same solves, with the intermediate vector and the U solve's workspace
+ * in a fixed 64 MiB device array of the library (one per GPU, held until the
+ * process ends) instead of the handle's workspace, and no hipMalloc, hipFree
+ * or other allocating call.  The handle's own per-plan state (mailboxes,
+ * counters) is used as sized at setup, so nrhs must not exceed the handle's
+ * max_nrhs.  Needs 2 * ceil256((n + 1) * nrhs * s) bytes of the array
+ * (s = 8 for FP64 factors, 4 for FP32): n * nrhs up to about 4.19 million
+ * with FP64 factors (one 128^3 right-hand side fits), 8.38 million with FP32.
+ * Nothing in the array needs to start at any value.  All calls on one GPU
+ * share the array: calls that overlap in time on one GPU (different streams
+ * or threads) race and must be ordered by the caller.
+ * Errors: INVALID_ARG (as ilu_apply, or nrhs above max_nrhs), CAPACITY
+ * (the sizes above exceed the array), NO_DEVICE, HIP, TIMEOUT. */
+hec_status_t ilu_apply_noalloc(ilu_t ilu, const void *r, void *z, int32_t nrhs, hec_dtype_t vec_dt,
+                               hipStream_t stream);
 void ilu_destroy(ilu_t ilu);
 /* Numeric refactorization on the device (Section 3's ILU(0) / ILU(k), computed
  * over the level sets of eq. (2): the rows of one level of L are independent).

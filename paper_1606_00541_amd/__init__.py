@@ -94,6 +94,7 @@ SIGNATURES = {
     "ilu_factor": (_i32, [_vp, _i32, _P(_i64), _vp, _vp, _vp]),
     "ilu_plans": (_i32, [_vp, _P(_vp), _P(_vp)]),
     "ilu_apply": (_i32, [_vp, _vp, _vp, _i32, _i32, _vp]),
+    "ilu_apply_noalloc": (_i32, [_vp, _vp, _vp, _i32, _i32, _vp]),
     "ilu_destroy": (None, [_vp]),
     "ilu_refactor": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "ras_setup": (_i32, [_i32, _vp, _vp, _vp, _i32, _vp, _i32, _i32, _P(Tune), _P(_vp)]),
@@ -447,6 +448,16 @@ def ilu_apply(f: Ilu, r, z, stream=None):
     if R != R2 or dr != dz:
         raise ValueError("r and z must have the same shape and dtype")
     _check(lib().ilu_apply(f.ptr, pr, pz, R, dr, _stream(stream)))
+
+
+def ilu_apply_noalloc(f: Ilu, r, z, stream=None):
+    """ilu_apply through the entry point that allocates nothing (the
+    library's fixed device scratch array; nrhs at most the handle's max_nrhs)."""
+    pr, R, dr = _vec(r, f.n)
+    pz, R2, dz = _vec(z, f.n)
+    if R != R2 or dr != dz:
+        raise ValueError("r and z must have the same shape and dtype")
+    _check(lib().ilu_apply_noalloc(f.ptr, pr, pz, R, dr, _stream(stream)))
 
 
 def ras_setup(A, nsub, owner, overlap=1, factor_dtype="f64", tune: Tune | None = None) -> Ras:

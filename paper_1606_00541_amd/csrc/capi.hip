@@ -11,7 +11,9 @@
 #include <cstdio>
 #include <chrono>
 #include <functional>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 
 #include "hec_dev.h"
@@ -737,6 +739,62 @@ hec_status_t ilu_plans(ilu_t f, tri_plan_t *L, tri_plan_t *U)
         if (!f) fail(HEC_ERR_INVALID_ARG, "ilu is NULL");
         if (L) *L = &f->L;
         if (U) *U = &f->U;
+    });
+}
+
+// Workspace of ilu_apply_noalloc: the intermediate y = L^{-1} r and the U
+// solve's own device-order workspace live in one file-scope device array,
+// so that the entry point never allocates.  Each GPU holds its own copy for
+// the life of the process; its address is taken once per device.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_ptr;  // device -> address of that device's scratch
+
+void *scratch_on_current_device()
+{
+    int dev = -1;
+    hip_check(hipGetDevice(&dev), "hipGetDevice");
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) return it->second;
+    void *ptr = nullptr;
+    hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!ptr) fail(HEC_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = ptr;
+    return ptr;
+}
+}  // namespace
+
+hec_status_t ilu_apply_noalloc(ilu_t f, const void *r, void *z, int32_t nrhs, hec_dtype_t vdt, hipStream_t st)
+{
+    return guard([&] {
+        if (!f) fail(HEC_ERR_INVALID_ARG, "ilu is NULL");
+        if (nrhs < 1) fail(HEC_ERR_INVALID_ARG, "nrhs must be >= 1");
+        check_vec(vdt);
+        require_device(f->L);
+        if (f->n > 0 && (!r || !z)) fail(HEC_ERR_INVALID_ARG, "vector pointer is NULL");
+        // the plans' mailboxes and counters were sized at setup; this entry
+        // point never grows them
+        if (nrhs > f->L.d.ws_R || nrhs > f->U.d.ws_R)
+            fail(HEC_ERR_INVALID_ARG, "nrhs " + std::to_string(nrhs) + " exceeds the handle's max_nrhs " +
+                                          std::to_string(std::min(f->L.d.ws_R, f->U.d.ws_R)) +
+                                          " (ilu_apply_noalloc never enlarges workspaces)");
+        const size_t ts = f->fdt == HEC_F64 ? 8 : 4;
+        const size_t part = (((size_t)f->n + 1) * (size_t)nrhs * ts + 255) & ~(size_t)255;
+        if (2 * part > kScratchBytes)
+            fail(HEC_ERR_CAPACITY, "ilu_apply_noalloc needs " + std::to_string(2 * part) + " bytes of scratch for n = " +
+                                       std::to_string(f->n) + " and nrhs = " + std::to_string(nrhs) +
+                                       "; its fixed scratch holds " + std::to_string(kScratchBytes) +
+                                       " (use ilu_apply)");
+        unsigned char *base = static_cast<unsigned char *>(scratch_on_current_device());
+        void *y = base;          // L's device-order output, U's input
+        void *uw = base + part;  // U's own workspace (kernels that keep the solution in global memory)
+        check_device_error(f->L.d, f->U.d);
+        launch_tri(f->L.d, r, vdt, f->L.d.orig.as<int32_t>(), y, nullptr, vdt, nullptr, nrhs, st);
+        launch_tri(f->U.d, y, f->fdt, f->qmap.as<int32_t>(), uw, z, vdt, f->U.d.orig.as<int32_t>(), nrhs, st);
     });
 }
 
