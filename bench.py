@@ -184,6 +184,8 @@ def _log(msg):
 
 def _tune(H, args, **kw):
     sched = 0 if args.schedule == "auto" else args.schedule
+    if args.block_threads:
+        kw.setdefault("block_threads", args.block_threads)
     return H.tune_default(schedule=sched, kernel_variant=args.kernel_variant, **kw)
 
 
@@ -606,6 +608,7 @@ def main(argv=None):
                     choices=["auto", "level_launch", "level_persistent", "owner_persistent"])
     ap.add_argument("--kernel-variant", type=int, default=0,
                     help="hec_tune_t.kernel_variant (0 = auto: the dataflow kernel when it fits)")
+    ap.add_argument("--block-threads", type=int, default=0, help="hec_tune_t.block_threads (0 = default)")
     ap.add_argument("--no-krylov", action="store_true")
     ap.add_argument("--timed-loop-only", action="store_true",
                     help="skip the device refactorization and the per-application (warm/cold) timings, so a "

@@ -120,7 +120,14 @@ typedef struct hec_tune {
                                order that fit the LDS (part_rows sets a first cut), systems
                                with the most levels first, and the workgroups take parts from
                                a queue in that order: a part reads only from earlier parts,
-                               so the solve needs no co-residency (on request only).
+                               so the solve needs no co-residency (on request only);
+                               7 = system queue (schedule AUTO or LEVEL_PERSISTENT): the
+                               workgroups take whole independent systems (batch_setup's
+                               systems, RAS subdomains, or the whole matrix), largest first,
+                               from a queue and solve each level by level with a workgroup
+                               barrier between levels, the last levels of the system held in
+                               an LDS ring (no co-residency needed; block_threads sets the
+                               workgroup).
                                Schedule AUTO picks the dataflow kernel when its LDS holds
                                every part, else 5 when the levels are narrow (fewer than 2^17
                                (row, rhs) items per level on average), else one launch per
@@ -153,6 +160,8 @@ typedef struct tri_stats {
     int32_t syncfree;        /* 1 when the plan runs on the barrier-free global-memory kernel */
     int32_t queue;           /* 1 when the dataflow kernel takes its parts from a queue
                                 (num_groups then counts parts, not workgroups) */
+    int32_t sysq;            /* 1 when the plan runs on the system-queue kernel (num_groups
+                                then counts independent systems) */
 } tri_stats_t;
 
 typedef struct hec_matrix_s *hec_matrix_t;
@@ -465,8 +474,9 @@ void hec_graph_destroy(hec_graph_t g);
  * one part per workgroup for 2, 4 and 6 compute wavefronts (the rows each
  * wavefront walks per level) and automatic, contiguous and bisection parts;
  * the part queue (kernel_variant 6) for 4 and 6 wavefronts and automatic,
- * 1024 and 4096 rows per part; the barrier-free kernel; one launch per
- * level; the level-persistent schedule at two level-merge thresholds; and
+ * 1024 and 4096 rows per part; the system queue with 512 and 1024 threads
+ * per workgroup; the barrier-free kernel; one launch per level; the
+ * level-persistent schedule at two level-merge thresholds; and
  * wider ELL parts when rows overflow the automatic width.  nsys > 0 with
  * sys_ptr[nsys+1] marks independent diagonal blocks (batch_setup's systems,
  * RAS subdomains), as the setups pass them.  max_seconds > 0 stops starting

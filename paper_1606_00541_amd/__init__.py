@@ -62,7 +62,7 @@ class TriStats(ctypes.Structure):
         ("nnz_offdiag", ctypes.c_int64), ("nnz_tail", ctypes.c_int64), ("lds_rows", ctypes.c_int64),
         ("nremote", ctypes.c_int64), ("unit_diag", ctypes.c_int32), ("dtype", ctypes.c_int32),
         ("crit_hops", ctypes.c_int32), ("dataflow", ctypes.c_int32), ("syncfree", ctypes.c_int32),
-        ("queue", ctypes.c_int32)]
+        ("queue", ctypes.c_int32), ("sysq", ctypes.c_int32)]
 
 
 class Precond(ctypes.Structure):

@@ -41,7 +41,7 @@ Tune tune_from(const hec_tune_t *t)
     u.chunk_rows = t->chunk_rows > 0 ? t->chunk_rows : std::max(256, u.block_threads);
     u.partition = t->partition;
     u.variant = t->kernel_variant;
-    if (u.variant < 0 || u.variant > 6) fail(HEC_ERR_INVALID_ARG, "tune.kernel_variant out of range");
+    if (u.variant < 0 || u.variant > 7) fail(HEC_ERR_INVALID_ARG, "tune.kernel_variant out of range");
     if (u.variant == 5 && u.schedule != HEC_SCHED_AUTO && u.schedule != HEC_SCHED_LEVEL_LAUNCH)
         fail(HEC_ERR_INVALID_ARG, "kernel_variant 5 runs the level-ordered layout (schedule AUTO or LEVEL_LAUNCH)");
     if (u.partition < 0 || u.partition > 3) fail(HEC_ERR_INVALID_ARG, "tune.partition out of range");
@@ -762,6 +762,85 @@ std::vector<int32_t> queue_parts(const Csr &a, bool upper, const Levels &lv, con
     return po;
 }
 
+// System queue: every column becomes a row of its system's LDS ring, which
+// holds the last D+1 levels of the system (D = the largest level distance of
+// a dependency in it) in D+1 slots of W rows (W = its widest level): a value
+// of local level l sits in slot l mod (D+1).  If the ring of a system does
+// not fit the LDS, D shrinks and the dependencies further back are read from
+// the global workspace instead (column -2 - device row).  ELL padding becomes
+// kSqPad, which the kernel maps to a zero row after the ring.
+constexpr int32_t kSqPad = INT32_MAX;
+
+void build_sysq(ExecHost &ex, const Levels &lv, const std::vector<int32_t> &sys, const std::vector<int32_t> &lvrow,
+                const std::vector<int32_t> &lvp, int32_t R, size_t ts, const DeviceShape &dev)
+{
+    (void)lv;
+    const int32_t n = ex.n, S = (int32_t)sys.size();
+    Schedule &s = ex.sched;
+    s.sysq = true;
+    s.groups = S;
+    s.sq_lvrow = lvrow;
+    s.sq_lvp = lvp;
+    s.sq_ring.assign(2 * (size_t)S, 0);
+    std::vector<int32_t> lev_of(n, 0), sys_of(n, 0);  // local level, queue position of each device row
+    for (int32_t k = 0; k < S; ++k)
+        for (int32_t l = lvp[k]; l < lvp[k + 1]; ++l)
+            for (int32_t x = lvrow[l]; x < lvrow[l + 1]; ++x) {
+                lev_of[x] = l - lvp[k];
+                sys_of[x] = k;
+            }
+    auto each_col = [&](int32_t x, const std::function<void(int32_t &)> &f) {
+        for (int32_t e = 0; e < ex.w; ++e) f(ex.ell_col[(size_t)e * ex.ld + x]);
+        if (!ex.tail_ptr.empty())
+            for (int32_t p = ex.tail_ptr[x]; p < ex.tail_ptr[x + 1]; ++p) f(ex.tail_col[p]);
+    };
+    const size_t cap = dev.lds > 0 ? (size_t)dev.lds : 163840;
+    std::vector<int32_t> D(S, 0), W(S, 1);
+    for (int32_t k = 0; k < S; ++k) {
+        for (int32_t l = lvp[k]; l < lvp[k + 1]; ++l) W[k] = std::max(W[k], lvrow[l + 1] - lvrow[l]);
+        for (int32_t l = lvp[k]; l < lvp[k + 1]; ++l)
+            for (int32_t x = lvrow[l]; x < lvrow[l + 1]; ++x)
+                each_col(x, [&](int32_t &c) {
+                    if (c < n) D[k] = std::max(D[k], lev_of[x] - lev_of[c]);
+                });
+        // shrink the ring until it fits (global reads beyond it)
+        while (D[k] > 0 && ((size_t)(D[k] + 1) * W[k] + 1) * R * ts > cap) --D[k];
+        if (((size_t)(D[k] + 1) * W[k] + 1) * R * ts > cap) D[k] = -1;  // not even one level: all global
+    }
+    s.sq_global = false;
+    int64_t lds_rows = 1;
+    for (int32_t k = 0; k < S; ++k) {
+        const int32_t slots = D[k] + 1;  // 0: no ring
+        s.sq_ring[2 * k] = slots;
+        s.sq_ring[2 * k + 1] = W[k];
+        lds_rows = std::max<int64_t>(lds_rows, (int64_t)slots * W[k] + 1);
+    }
+    for (int32_t x = 0; x < n; ++x) {
+        const int32_t k = sys_of[x];
+        each_col(x, [&](int32_t &c) {
+            if (c >= n) {
+                c = kSqPad;
+                return;
+            }
+            if (sys_of[c] != k) fail(HEC_ERR_INVALID_ARG, "internal: a dependency crosses two systems");
+            const int32_t dist = lev_of[x] - lev_of[c];
+            if (dist <= D[k]) {
+                const int32_t l = lvp[k] + lev_of[c];
+                c = (lev_of[c] % (D[k] + 1)) * W[k] + (c - lvrow[l]);
+            } else {
+                c = -2 - c;
+                s.sq_global = true;
+            }
+        });
+    }
+    s.sq_lds_rows = (int32_t)lds_rows;
+    s.window.assign(2 * (size_t)S, 0);
+    s.step_ptr.assign((size_t)S + 1, 0);
+    s.exp_ptr.assign((size_t)S + 1, 0);
+    s.exp_slot.assign(n, -1);
+    s.nexp = 0;
+}
+
 }  // namespace
 
 void build_exec(TriHost &t, const Csr &a, const Tune &tune, const DeviceShape &dev,
@@ -801,7 +880,56 @@ void build_exec(TriHost &t, const Csr &a, const Tune &tune, const DeviceShape &d
     ex.xord.resize(n);
     ex.owner.assign(n, 0);
     std::vector<std::vector<std::pair<int32_t, int32_t>>> runs;
-    if (kind == HEC_SCHED_LEVEL_LAUNCH || kind == HEC_SCHED_LEVEL_PERSISTENT) {
+    const bool sysq = tune.variant == 7;
+    std::vector<int32_t> sq_sys, sq_lvrow, sq_lvp;  // system queue: systems in queue order, level bounds
+    if (sysq) {
+        // one workgroup per independent system: device rows system by system
+        // in queue order (longest first), each system in level order
+        std::vector<int32_t> sp = sys_ptr && sys_ptr->size() >= 2 ? *sys_ptr : std::vector<int32_t>{0, n};
+        const int32_t S = (int32_t)sp.size() - 1;
+        const int32_t nt = std::max(64, tune.block_threads);
+        std::vector<std::vector<int32_t>> width(S);
+        for (int32_t q = 0; q < S; ++q)
+            for (int32_t i = sp[q]; i < sp[q + 1]; ++i) {
+                const int32_t l = lv.level[i] - 1;
+                if ((int32_t)width[q].size() <= l) width[q].resize(l + 1, 0);
+                width[q][l] += 1;
+            }
+        std::vector<int64_t> est(S, 0);
+        for (int32_t q = 0; q < S; ++q)
+            for (int32_t w2 : width[q]) est[q] += 1 + ((int64_t)w2 * R) / nt;
+        sq_sys.resize(S);
+        std::iota(sq_sys.begin(), sq_sys.end(), 0);
+        std::stable_sort(sq_sys.begin(), sq_sys.end(), [&](int32_t x, int32_t y) { return est[x] > est[y]; });
+        // rows of each system by (level, problem order): a stable sort of the
+        // level order (lv.perm lists rows by level, problem order inside)
+        std::vector<int32_t> sys_of(n);
+        for (int32_t q = 0; q < S; ++q)
+            for (int32_t i = sp[q]; i < sp[q + 1]; ++i) sys_of[i] = q;
+        std::vector<int32_t> rank(S);
+        for (int32_t k = 0; k < S; ++k) rank[sq_sys[k]] = k;
+        std::vector<int32_t> cnt(S + 1, 0);
+        for (int32_t i = 0; i < n; ++i) cnt[rank[sys_of[i]] + 1] += 1;
+        for (int32_t k = 0; k < S; ++k) cnt[k + 1] += cnt[k];
+        std::vector<int32_t> pos(cnt.begin(), cnt.end() - 1);
+        for (int32_t r = 0; r < n; ++r) {  // r: level-order row
+            const int32_t i = lv.perm[r];
+            ex.xord[pos[rank[sys_of[i]]]++] = r;
+        }
+        sq_lvp.assign(1, 0);
+        sq_lvrow.clear();
+        for (int32_t k = 0; k < S; ++k) {
+            const int32_t q = sq_sys[k];
+            int32_t row = cnt[k];
+            for (int32_t w2 : width[q]) {
+                sq_lvrow.push_back(row);
+                row += w2;
+            }
+            sq_lvp.push_back((int32_t)sq_lvrow.size());
+        }
+        sq_lvrow.push_back(n);
+        for (int32_t x = 0; x < n; ++x) ex.owner[x] = 0;
+    } else if (kind == HEC_SCHED_LEVEL_LAUNCH || kind == HEC_SCHED_LEVEL_PERSISTENT) {
         std::iota(ex.xord.begin(), ex.xord.end(), 0);
         ex.levelptr = lv.levelptr;
         if (kind == HEC_SCHED_LEVEL_PERSISTENT) {
@@ -958,6 +1086,10 @@ void build_exec(TriHost &t, const Csr &a, const Tune &tune, const DeviceShape &d
     // 3. schedule
     ex.sched = Schedule();
     ex.sched.kind = kind;
+    if (sysq) {
+        build_sysq(ex, lv, sq_sys, sq_lvrow, sq_lvp, R, t.dt == HEC_F64 ? 8 : 4, dev);
+        return;
+    }
     // the dataflow owner kernel runs each step as one wavefront's unit (at
     // most 64 (row, rhs) items); the other owner kernels cut steps to chunks
     if (want_df && dataflow_width(w) != w)
@@ -1049,6 +1181,12 @@ TriHost analyze(const Csr &a, bool upper, bool unit, hec_dtype_t dt, const Tune 
     }
     const bool auto_sched = tu.schedule == HEC_SCHED_AUTO;
     if (auto_sched) tu.schedule = HEC_SCHED_OWNER_PERSISTENT;
+    if (tu.variant == 7) {  // the system queue: one workgroup per independent system
+        if (tu.schedule != HEC_SCHED_LEVEL_PERSISTENT)
+            fail(HEC_ERR_INVALID_ARG, "kernel_variant 7 runs the level schedule (schedule AUTO or LEVEL_PERSISTENT)");
+        attempt(tu);
+        return t;
+    }
     if (tu.variant == 6) {
         if (tu.schedule != HEC_SCHED_OWNER_PERSISTENT)
             fail(HEC_ERR_INVALID_ARG, "kernel_variant 6 runs the owner schedule (schedule AUTO or OWNER_PERSISTENT)");

@@ -141,6 +141,14 @@ void upload_tri(DevTri &d, const TriHost &t, int32_t max_nrhs)
                 d.df_step_rows = std::max(d.df_step_rows, s.step_row[2 * q + 1] - s.step_row[2 * q]);
         }
         d.max_lanes_one = std::all_of(s.step_lanes.begin(), s.step_lanes.end(), [](int32_t v) { return v == 1; });
+        if (s.sysq) {
+            d.sysq = true;
+            d.sq_global = s.sq_global;
+            d.sq_lds_rows = s.sq_lds_rows;
+            upload(d.sq_lvp, s.sq_lvp);
+            upload(d.sq_lvrow, s.sq_lvrow);
+            upload(d.sq_ring, s.sq_ring);
+        }
     }
     // epoch, workgroups done, work counter (part queue / chunk batches)
     d.epoch.alloc(4 * sizeof(unsigned int));
@@ -612,6 +620,7 @@ hec_status_t tri_plan_stats(tri_plan_t p, tri_stats_t *s)
         s->dataflow = h.ex.sched.dataflow ? 1 : 0;
         s->syncfree = (h.ex.sched.kind == HEC_SCHED_LEVEL_LAUNCH && h.variant == 5) ? 1 : 0;
         s->queue = h.ex.sched.dataflow && h.ex.sched.queue ? 1 : 0;
+        s->sysq = h.ex.sched.sysq ? 1 : 0;
         s->unit_diag = h.unit ? 1 : 0;
         s->dtype = h.dt;
     });
@@ -1197,6 +1206,7 @@ hec_status_t tri_autotune(int32_t n, const int32_t *rowptr, const int32_t *col, 
                     t.schedule = HEC_SCHED_OWNER_PERSISTENT;
                     t.variant = 4;
                     t.block_threads = blk;
+                    t.chunk_rows = std::max(256, blk);  // a valid multiple of the block
                     t.partition = part;
                     cands.push_back(t);
                 }
@@ -1206,6 +1216,7 @@ hec_status_t tri_autotune(int32_t n, const int32_t *rowptr, const int32_t *col, 
                     t.schedule = HEC_SCHED_OWNER_PERSISTENT;
                     t.variant = 6;
                     t.block_threads = blk;
+                    t.chunk_rows = std::max(256, blk);
                     t.part_rows = rows;
                     cands.push_back(t);
                 }
@@ -1216,6 +1227,14 @@ hec_status_t tri_autotune(int32_t n, const int32_t *rowptr, const int32_t *col, 
                 t.ell_width = dataflow_width(std::max(1, (w0 + wmax) / 2));
                 cands.push_back(t);
             }
+        }
+        for (int32_t blk : {512, 1024}) {  // the system queue (one workgroup per system)
+            Tune t = base;
+            t.schedule = HEC_SCHED_LEVEL_PERSISTENT;
+            t.variant = 7;
+            t.block_threads = blk;
+            t.chunk_rows = blk;
+            cands.push_back(t);
         }
         {
             Tune t = base;

@@ -113,8 +113,9 @@ struct TriArgs {
     unsigned long long *trace;   // optional per-step clocks [groups][trace_stride][2]
     int32_t trace_stride;
     unsigned spin;               // polls before a bounded wait gives up
-    int32_t nparts;              // dataflow kernel: parts of the plan
+    int32_t nparts;              // dataflow kernel: parts of the plan; system queue: systems
     int32_t queue;               // dataflow kernel: workgroups take parts from a counter (epoch[2])
+    const int32_t *sq_lvp, *sq_lvrow, *sq_ring;  // system queue: levels per system, level rows, rings
 };
 
 // Polls of a bounded device-side wait before it is declared hung (a plan may
@@ -142,6 +143,9 @@ struct DevTri {
     int32_t df_rows = 0, df_ints = 0;
     int32_t df_step_rows = 0;      // longest step (one wavefront covers step rows x nrhs)
     bool queue = false;            // dataflow parts taken from a counter (more parts than workgroups)
+    bool sysq = false, sq_global = false;  // system queue kernel; some dependencies read from xw
+    int32_t sq_lds_rows = 0;
+    DevMem sq_lvp, sq_lvrow, sq_ring;
     int32_t chunk_rows = 0;
     bool max_lanes_one = true;     // every step runs one thread per (row, rhs)
     DevMem epoch, err, mbox;

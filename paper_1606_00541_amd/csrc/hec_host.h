@@ -95,6 +95,14 @@ struct Schedule {
     // queue mode: `groups` parts, more than the workgroups that run them; the
     // parts are numbered so that every part reads only lower-numbered ones
     bool queue = false;
+    // system queue (kernel variant 7): `groups` independent systems, taken
+    // whole by the workgroups; system k (queue order) has levels
+    // sq_lvp[k]..sq_lvp[k+1]-1, level l its device rows sq_lvrow[l]..sq_lvrow[l+1]-1;
+    // its LDS ring has sq_ring[2k] slots of sq_ring[2k+1] rows
+    bool sysq = false;
+    bool sq_global = false;          // some dependency is read from the global workspace
+    int32_t sq_lds_rows = 0;         // largest ring plus the zero row, in rows
+    std::vector<int32_t> sq_lvp, sq_lvrow, sq_ring;
     int32_t nsteps() const { return (int32_t)step_lanes.size(); }
 };
 

@@ -1330,6 +1330,88 @@ __global__ void __launch_bounds__(256) k_syncfree(TriArgs a)
     }
 }
 
+// System queue: every workgroup takes whole independent systems from a
+// counter (largest first) and solves one system's levels in order, all of a
+// level's (row, rhs) items spread over the workgroup, with a workgroup
+// barrier between levels.  The values of the system's last levels stay in an
+// LDS ring (slot = local level mod slots); a dependency further back is read
+// from the workspace, which this workgroup wrote before an earlier barrier.
+// A system is never shared between workgroups, so the solve needs no
+// co-residency.  Rows are computed exactly as in k_level (ELL slots in order,
+// then the CSR tail; ELL padding reads a zero row of the ring and subtracts
+// 0 * 0), so results are bit-identical to it.
+template <typename T, typename TIn, typename TOut>
+__global__ void __launch_bounds__(1024) k_sysq(TriArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_q;
+    __shared__ unsigned s_epoch;
+    T *ring = reinterpret_cast<T *>(smem);
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int R = a.R;
+    const T *ev = static_cast<const T *>(a.ell_val);
+    const T *tv = static_cast<const T *>(a.tail_val);
+    T *xw = static_cast<T *>(a.xw);
+    if (tid == 0) s_epoch = __hip_atomic_load(a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (;;) {
+        if (tid == 0)
+            s_q = (int)__hip_atomic_fetch_add(&a.epoch[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const int q = s_q;
+        if (q >= a.nparts) break;
+        const int slots = a.sq_ring[2 * q], W = a.sq_ring[2 * q + 1];
+        const int zrow = slots * W;
+        for (int t = tid; t < R; t += nt) ring[(size_t)zrow * R + t] = T(0);
+        __syncthreads();
+        const int l0 = a.sq_lvp[q], l1 = a.sq_lvp[q + 1];
+        for (int l = l0; l < l1; ++l) {
+            const int rb = a.sq_lvrow[l], re = a.sq_lvrow[l + 1];
+            const int base = slots ? ((l - l0) % slots) * W : 0;
+            const int items = (re - rb) * R;
+            for (int t = tid; t < items; t += nt) {
+                const int i = t / R, k = t - i * R;
+                const int x = rb + i;
+                T sv = canon(static_cast<T>(static_cast<const TIn *>(a.bin)[(size_t)a.gather[x] * R + k]));
+                if (a.dinv) sv = scale_rhs(sv, static_cast<const T *>(a.dinv)[x]);
+                for (int e = 0; e < a.w; ++e) {
+                    const int c = a.ell_col[(size_t)e * a.ld + x];
+                    const T v = ev[(size_t)e * a.ld + x];
+                    const T dep = c >= 0 ? ring[(size_t)min(c, zrow) * R + k]
+                                         : __hip_atomic_load(xw + (size_t)(-2 - c) * R + k, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_WORKGROUP);
+                    sv -= v * dep;
+                }
+                if (a.tail_ptr) {
+                    for (int p = a.tail_ptr[x]; p < a.tail_ptr[x + 1]; ++p) {
+                        const int c = a.tail_col[p];
+                        const T dep = c >= 0 ? ring[(size_t)min(c, zrow) * R + k]
+                                             : __hip_atomic_load(xw + (size_t)(-2 - c) * R + k, __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+                        sv -= tv[p] * dep;
+                    }
+                }
+                if (slots) ring[(size_t)(base + i) * R + k] = sv;
+                if (a.write_xw)
+                    __hip_atomic_store(xw + (size_t)x * R + k, sv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (a.xout) {
+                    const int d = a.scatter[x];
+                    if (d >= 0) static_cast<TOut *>(a.xout)[(size_t)d * R + k] = static_cast<TOut>(sv);
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (tid == 0) {
+        const unsigned done = __hip_atomic_fetch_add(&a.epoch[1], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (done == gridDim.x - 1) {
+            // last workgroup out: every claim is over; reset the queue
+            __hip_atomic_store(&a.epoch[2], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.epoch[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.epoch[0], s_epoch + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_fill_sentinel(T *p, size_t count, unsigned *counter)
 {
@@ -1356,6 +1438,19 @@ void launch_typed(DevTri &d, TriArgs a, hipStream_t st)
         const int grid = (int)std::max<long>(1, std::min<long>(lim, (chunks + 4 * kSfBatch - 1) / (4 * kSfBatch)));
         hipLaunchKernelGGL((k_syncfree<T, TIn, TOut>), dim3(grid), dim3(256), 0, st, a);
         hip_check(hipGetLastError(), "k_syncfree launch");
+        return;
+    }
+    if (d.sysq) {
+        const size_t lds = (size_t)std::max(1, d.sq_lds_rows) * a.R * sizeof(T);
+        if (lds > (size_t)device_max_lds())
+            fail(HEC_ERR_CAPACITY, "system queue: the LDS ring exceeds the device limit at this nrhs");
+        const int block = std::max(64, std::min(1024, d.block));
+        const int32_t cap = capacity_of((const void *)k_sysq<T, TIn, TOut>, block, lds);
+        a.nparts = d.groups;
+        if (d.sq_global) a.write_xw = 1;  // dependencies beyond the ring are read back from xw
+        const int grid = std::max(1, std::min(d.groups, cap));
+        hipLaunchKernelGGL((k_sysq<T, TIn, TOut>), dim3(grid), dim3(block), lds, st, a);
+        hip_check(hipGetLastError(), "k_sysq launch");
         return;
     }
     if (d.kind == HEC_SCHED_LEVEL_LAUNCH) {
@@ -1584,6 +1679,9 @@ void launch_tri(DevTri &d, const void *bin, hec_dtype_t in_dt, const int32_t *ga
     a.trace = d.trace;
     a.trace_stride = d.trace_stride;
     a.spin = d.spin;
+    a.sq_lvp = d.sq_lvp.as<int32_t>();
+    a.sq_lvrow = d.sq_lvrow.as<int32_t>();
+    a.sq_ring = d.sq_ring.as<int32_t>();
     a.in_f64 = in_dt == HEC_F64 ? 1 : 0;
     a.out_f64 = out_dt == HEC_F64 ? 1 : 0;
     if (d.dt == HEC_F64) launch_in<double>(d, a, in_dt, out_dt, st);

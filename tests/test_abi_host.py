@@ -371,3 +371,40 @@ def test_queue_parts_read_only_earlier_parts():
         first_part = [part[sys_ptr[s]:sys_ptr[s + 1]].min() for s in range(len(mats))]
         order = sorted(range(len(mats)), key=lambda s: first_part[s])
         assert [depth[s] for s in order] == sorted(depth, reverse=True)
+
+
+def test_system_queue_layout():
+    # kernel variant 7: whole independent systems per workgroup, each in level
+    # order, the longest first; every column is a ring row, a global read
+    # (-2 - device row) or padding
+    mats = [synth.poisson2d(7, 3), synth.diffusion2d(30, 21, 1.0, seed=1), synth.diffusion3d(9, 8, 7, 1.0, seed=2)]
+    import scipy.sparse as sp
+    m = sp.block_diag([M.to_scipy() for M in mats]).tocsr()
+    m.sort_indices()
+    A = CSR(m.shape[0], m.indptr.astype(np.int32), m.indices.astype(np.int32), m.data.copy())
+    sys_ptr = np.cumsum([0] + [M.n for M in mats]).astype(np.int32)
+    t = H.tune_default(host_only=1, max_nrhs=4, schedule="level_persistent", kernel_variant=7)
+    f = H.batch_setup(A, sys_ptr, "iluk", k=1, tune=t)
+    n = A.n
+    sysof = np.searchsorted(sys_ptr, np.arange(n), side="right") - 1
+    for which, plan in enumerate(H.ilu_plans(f)):
+        st = H.tri_plan_stats(plan)
+        assert st["sysq"] == 1 and st["num_groups"] == len(mats)
+        xperm, _ = H.tri_plan_layout(plan)
+        # device rows: one system after another, each in level order
+        s_dev = sysof[xperm]
+        runs = [s_dev[0]] + [s_dev[i] for i in range(1, n) if s_dev[i] != s_dev[i - 1]]
+        assert len(runs) == len(mats) and sorted(runs) == list(range(len(mats)))
+        nlev, lp, perm = H.tri_plan_info(plan)
+        level = np.empty(n, np.int64)
+        for k in range(nlev):
+            level[perm[lp[k]:lp[k + 1]]] = k
+        lev_dev = level[xperm]
+        for s_ in range(len(mats)):
+            idx = np.flatnonzero(s_dev == s_)
+            assert np.all(np.diff(lev_dev[idx]) >= 0)
+        # the system with the most work comes first (2D 30x21 ILU(1) or 3D 9x8x7)
+        assert runs[0] != 0
+    with pytest.raises(H.HecError):  # the system queue runs the level schedule only
+        H.tri_analyze(synth.random_lower(50, 0.05, seed=1), tune=H.tune_default(
+            host_only=1, schedule="owner_persistent", kernel_variant=7))

@@ -331,3 +331,44 @@ def test_batch_krylov_rejects_coupling():
     with pytest.raises(H.HecError) as e:
         H.krylov_solve_batch(M, None, np.array([0, 18, 36], np.int32), b, x)
     assert e.value.name == "INVALID_ARG"
+
+
+@pytest.mark.parametrize("fdt", ["f64", "f32"])
+@pytest.mark.parametrize("R", [1, 8])
+def test_system_queue_matches_level_launches(fdt, R):
+    # kernel variant 7 computes every row as the per-level launches do: the
+    # same bits, for batches (systems) and RAS (subdomains)
+    mats = [synth.diffusion2d(60, 41, 1.0, seed=41), synth.diffusion3d(13, 12, 11, 1.0, seed=42),
+            synth.poisson2d(5, 3), synth.diffusion3d(17, 16, 15, 1.0, seed=44), synth.poisson2d(90, 4)]
+    A, sys_ptr = _block_diag(mats)
+    tq = H.tune_default(schedule="level_persistent", kernel_variant=7, max_nrhs=R, block_threads=512)
+    tl = H.tune_default(schedule="level_launch", max_nrhs=R)
+    f = H.batch_setup(A, sys_ptr, "iluk", k=1, factor_dtype=fdt, tune=tq)
+    g = H.batch_setup(A, sys_ptr, "iluk", k=1, factor_dtype=fdt, tune=tl)
+    assert H.tri_plan_stats(H.ilu_plans(f)[0])["sysq"] == 1
+    r = synth.rhs(A.n, R, 45)
+    for rep in range(2):  # the queue counter resets between launches
+        assert np.array_equal(apply(f, r), apply(g, r))
+    B = synth.poisson3d(24)
+    owner, _ = synth.subdomain_cuts(B.n, 8, 1000, 2500, seed=46)
+    s1 = H.ras_setup(B, 8, owner, overlap=1, factor_dtype=fdt, tune=tq)
+    s2 = H.ras_setup(B, 8, owner, overlap=1, factor_dtype=fdt, tune=tl)
+    r = synth.rhs(B.n, R, 47)
+    assert np.array_equal(apply(s1, r), apply(s2, r))
+    doms = oracle.ras_setup(B, owner, 8, overlap=1)
+    ref = oracle.ras_apply(doms, r) if fdt == "f64" else oracle.ras_apply_f32(oracle.ras_to_f32(doms), r)
+    assert relerr(apply(s1, r), ref) <= (FP64_TOL if fdt == "f64" else 1e-5)
+
+
+def test_system_queue_reads_beyond_its_ring():
+    # 64 right-hand sides of a wide-level system: the ring holds one level at
+    # most, so every dependency is read back from the workspace
+    A = synth.poisson2d(300)
+    t = H.tune_default(schedule="level_persistent", kernel_variant=7, max_nrhs=64, block_threads=1024)
+    f = H.ilu_setup(A, "ilu0", tune=t)
+    g = H.ilu_setup(A, "ilu0", tune=H.tune_default(schedule="level_launch", max_nrhs=64))
+    r = synth.rhs(A.n, 64, 48)
+    z = apply(f, r)
+    assert np.array_equal(z, apply(g, r))
+    L, U = oracle.ilu0(A)
+    assert relerr(z, oracle.ilu_apply(L, U, r)) <= FP64_TOL
