@@ -107,8 +107,8 @@ typedef struct hec_tune {
                                2 = owner kernel with LDS-staged chunks, 3 = owner kernel with
                                separate compute and fetch waves (one RHS), 4 = dataflow owner
                                kernel: no per-level barrier, each row waits only for its own
-                               inputs; block_threads sets its compute wavefronts (at most 640,
-                               384 above ELL width 8); ELL width 1..8, 10, 12 or 16 (others round
+                               inputs; block_threads sets its compute wavefronts (at most 384;
+                               two more run beside them); ELL width 1..8, 10, 12 or 16 (others round
                                up; the automatic width covers the longest row, up to 16);
                                max_nrhs at most 64; 5 = barrier-free kernel over the
                                level-ordered layout in global memory (schedule AUTO or

@@ -576,7 +576,7 @@ int32_t dataflow_width(int32_t w)
     return -1;
 }
 
-int32_t dataflow_max_block(int32_t w) { return w > 8 ? 512 : 768; }
+int32_t dataflow_max_block(int32_t /*w*/) { return 512; }
 
 size_t dataflow_lds_bytes(int32_t rows, int32_t ints, int32_t R, size_t tsize)
 {
@@ -1095,6 +1095,8 @@ void build_exec(TriHost &t, const Csr &a, const Tune &tune, const DeviceShape &d
     if (want_df && dataflow_width(w) != w)
         fail(HEC_ERR_INVALID_ARG, "dataflow kernel: ELL width must be 1..8, 10, 12 or 16");
     if (want_df && R > 64) fail(HEC_ERR_INVALID_ARG, "dataflow kernel: max_nrhs above 64");
+    if (want_df && (size_t)w * ld * 8 > (size_t)INT32_MAX)
+        fail(HEC_ERR_CAPACITY, "dataflow kernel: ELL part beyond 2 GiB (32-bit buffer offsets)");
     if (want_df && tune.block_threads > dataflow_max_block(w) - 128)
         fail(HEC_ERR_CAPACITY, "dataflow kernel: block_threads above " + std::to_string(dataflow_max_block(w) - 128) +
                                    " for ELL width " + std::to_string(w) + " (two more wavefronts are added)");
@@ -1196,7 +1198,7 @@ TriHost analyze(const Csr &a, bool upper, bool unit, hec_dtype_t dt, const Tune 
     if (tu.schedule == HEC_SCHED_OWNER_PERSISTENT && tu.variant == 0) {
         Tune d = tu;
         d.variant = 4;
-        const bool df_ok = d.block_threads <= 640 && d.max_nrhs <= 64 && d.ell_width <= 16;
+        const bool df_ok = d.block_threads <= 384 && d.max_nrhs <= 64 && d.ell_width <= 16;
         if (df_ok) {
             try {
                 attempt(d);

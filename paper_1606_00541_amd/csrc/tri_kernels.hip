@@ -813,7 +813,7 @@ template <typename T, int W> struct DfRegs {
 };
 
 template <typename T, int W, bool UNIT, bool TAIL, bool R1>
-__global__ void __launch_bounds__(W > 8 ? 512 : 768) k_dataflow(TriArgs a)
+__global__ void __launch_bounds__(512) k_dataflow(TriArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ unsigned s_epoch;
@@ -923,6 +923,15 @@ __global__ void __launch_bounds__(W > 8 ? 512 : 768) k_dataflow(TriArgs a)
         // Lanes past the step's items repeat its last item, so loads and
         // their uses are unconditional and the compiler's load waits stay
         // exact (DEPTH steps' loads stay in flight while one is solved).
+        // The ELL slots of a step's rows are contiguous per slot: buffer
+        // loads with one per-lane byte offset and a per-slot scalar offset
+        // (no 64-bit address arithmetic per load).
+        const int nb_col = (int)min((size_t)0x7fffffff, (size_t)a.w * a.ld * sizeof(int32_t));
+        const int nb_val = (int)min((size_t)0x7fffffff, (size_t)a.w * a.ld * sizeof(T));
+        const __amdgpu_buffer_rsrc_t rcol =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<int32_t *>(a.ell_col), 0, nb_col, 0x00020000);
+        const __amdgpu_buffer_rsrc_t rval =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(ev), 0, nb_val, 0x00020000);
         auto load = [&](DfRegs<T, W> &u, int rb, int re) {
             u.rb = rb;
             u.re = re;
@@ -930,8 +939,12 @@ __global__ void __launch_bounds__(W > 8 ? 512 : 768) k_dataflow(TriArgs a)
             const int x = lo + rb + (R1 ? it : it / R);
 #pragma unroll
             for (int e = 0; e < W; ++e) {
-                u.c[e] = a.ell_col[(size_t)e * a.ld + x];
-                u.v[e] = ev[(size_t)e * a.ld + x];
+                u.c[e] = (int)__builtin_amdgcn_raw_buffer_load_b32(rcol, x * (int)sizeof(int32_t),
+                                                                   e * a.ld * (int)sizeof(int32_t), 0);
+                if constexpr (sizeof(T) == 8)
+                    u.v[e] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rval, x * 8, e * a.ld * 8, 0));
+                else
+                    u.v[e] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rval, x * 4, e * a.ld * 4, 0));
             }
         };
         const int ntr = a.trace ? min(ns, a.trace_stride - 1) : 0;
@@ -1014,20 +1027,22 @@ __global__ void __launch_bounds__(W > 8 ? 512 : 768) k_dataflow(TriArgs a)
             lds_put(xl + r * R + k, sv);
             if (j < ntr && lane == 0) ltr[2 * j + 1] = __builtin_amdgcn_s_memrealtime();
         };
-        // The wave walks its own steps [j, jend) in order.  Four register
-        // sets rotate: while step j is solved from one, steps j+1 and j+2 have
-        // their loads in flight and step j+3's loads are issued into the
-        // fourth (three sets and two steps ahead for rows wider than 8).  Loads past the last step repeat it, so every path issues
+        // The wave walks its own steps [j, jend) in order.  K register sets
+        // rotate: while step j is solved from one, the next K-2 steps have
+        // their matrix loads in flight and step j+K-1's loads are issued into
+        // the set just freed.  K is as large as the vector-memory counter
+        // allows (it holds 63 outstanding loads; a step issues 2W), so a step
+        // finds its data loaded although the memory latency spans several
+        // steps.  Loads past the last step repeat it, so every path issues
         // the same loads; the loop runs whole rotations with a single exit at
         // the bottom and no register moves, so the compiler's load waits are
         // exact.
         int j = a.wave_ptr[g * nwc + wv] - s0;
         const int jend = a.wave_ptr[g * nwc + wv + 1] - s0;
         const int last = jend - 1;
-        // Rows wider than 8 slots keep one step fewer in flight (three sets):
-        // the vector-memory counter holds at most 63 outstanding loads.
-        constexpr int kAhead = W > 8 ? 2 : 3;
-        DfRegs<T, W> A, B, C, D;
+        constexpr int K = W <= 3 ? 8 : (W <= 5 ? 6 : (W <= 8 ? 4 : 3));
+        constexpr int kAhead = K - 1;
+        DfRegs<T, W> S[K];
         auto first = [&](DfRegs<T, W> &u, int q) {
             q = min(q, last);
             load(u, stl[2 * q], stl[2 * q + 1]);
@@ -1038,34 +1053,19 @@ __global__ void __launch_bounds__(W > 8 ? 512 : 768) k_dataflow(TriArgs a)
             j += 1;
         };
         if (j < jend) {
-            first(A, j);
-            first(B, j + 1);
-            if (kAhead == 3) first(C, j + 2);
+#pragma unroll
+            for (int p = 0; p < K - 1; ++p) first(S[p], j + p);
             fb = stl[2 * min(j + kAhead, last)];
             fe = stl[2 * min(j + kAhead, last) + 1];
-            if (kAhead == 3) {
-                const int quads = (jend - j) / 4, rest = (jend - j) - 4 * quads;
-                for (int q4 = 0; q4 < quads; ++q4) {
-                    run(A, D);
-                    run(B, A);
-                    run(C, B);
-                    run(D, C);
-                    if (__ballot(aborted) != 0) break;
-                }
-                if (rest > 0 && __ballot(aborted) == 0) run(A, D);
-                if (rest > 1 && __ballot(aborted) == 0) run(B, A);
-                if (rest > 2 && __ballot(aborted) == 0) run(C, B);
-            } else {
-                const int triples = (jend - j) / 3, rest = (jend - j) - 3 * triples;
-                for (int q3 = 0; q3 < triples; ++q3) {
-                    run(A, C);
-                    run(B, A);
-                    run(C, B);
-                    if (__ballot(aborted) != 0) break;
-                }
-                if (rest > 0 && __ballot(aborted) == 0) run(A, C);
-                if (rest > 1 && __ballot(aborted) == 0) run(B, A);
+            const int rounds = (jend - j) / K, rest = (jend - j) - K * rounds;
+            for (int q = 0; q < rounds; ++q) {
+#pragma unroll
+                for (int p = 0; p < K; ++p) run(S[p], S[(p + K - 1) % K]);
+                if (__ballot(aborted) != 0) break;
             }
+#pragma unroll
+            for (int p = 0; p < K - 1; ++p)
+                if (rest > p && __ballot(aborted) == 0) run(S[p], S[(p + K - 1) % K]);
         }
     } else if (wv == nwc) {
         // import wave: lane l owns items l, l+64, l+128, ... (level order).
@@ -1119,25 +1119,38 @@ __global__ void __launch_bounds__(W > 8 ? 512 : 768) k_dataflow(TriArgs a)
             if (lds_get(&s_abort)) break;
         }
     } else {
-        // export wave
+        // export wave: each lane watches its next exported item; a round in
+        // which no lane found a new value sleeps briefly, so the wave does
+        // not take issue slots and LDS bandwidth from the compute waves
         const int items = nex * R;
         int it = lane;
-        unsigned idle = 0;
+        unsigned idle = 0, rounds = 0;
+        int q = it / R, k = it - q * R;
+        int row = it < items ? erl[q] : 0;
         while (__ballot(it < items) != 0) {
+            bool moved = false;
             if (it < items) {
-                const int q = it / R, k = it - q * R;
-                const T v = lds_get(xl + erl[q] * R + k);
+                const T v = lds_get(xl + row * R + k);
                 if (!is_sentinel(v)) {
                     __hip_atomic_store(mrd + (size_t)(e0 + q) * a.mbox_stride + k, v, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
                     it += 64;
                     idle = 0;
+                    moved = true;
+                    if (it < items) {
+                        q = it / R;
+                        k = it - q * R;
+                        row = erl[q];
+                    }
                 } else if (++idle > (a.spin << 4)) {
                     lds_put(&s_abort, 2);
                     it = items;
                 }
             }
-            if (lds_get(&s_abort)) break;
+            if (__ballot(moved) == 0) {
+                __builtin_amdgcn_s_sleep(1);
+                if ((++rounds & 15u) == 0 && lds_get(&s_abort)) break;
+            }
         }
     }
     __syncthreads();
