@@ -97,7 +97,8 @@ typedef struct hec_tune {
                                plans run by the dataflow kernel accept at most this many */
     int32_t block_threads;  /* threads per workgroup (64..1024, multiple of 64) */
     int32_t chunk_rows;     /* owner schedule: rows of matrix data staged in LDS per chunk
-                               (1, 2 or 4 times block_threads; 0 = max(256, block_threads)) */
+                               (1, 2 or 4 times block_threads; 0 = the smallest of
+                               those that is at least 256) */
     int32_t partition;      /* owner schedule parts: 0 = auto (blocks of a detected
                                structured grid, else contiguous), 1 = contiguous ranges of the
                                problem order, 2 = recursive graph bisection, 3 = grid blocks */

@@ -38,7 +38,9 @@ Tune tune_from(const hec_tune_t *t)
     u.host_only = t->host_only;
     u.max_nrhs = t->max_nrhs > 0 ? t->max_nrhs : 1;
     u.block_threads = t->block_threads > 0 ? t->block_threads : 256;
-    u.chunk_rows = t->chunk_rows > 0 ? t->chunk_rows : std::max(256, u.block_threads);
+    // Default chunk: the smallest of 1, 2 or 4 blocks that holds at least 256 rows.
+    u.chunk_rows = t->chunk_rows > 0 ? t->chunk_rows
+                 : u.block_threads * (u.block_threads >= 256 ? 1 : (u.block_threads >= 128 ? 2 : 4));
     u.partition = t->partition;
     u.variant = t->kernel_variant;
     if (u.variant < 0 || u.variant > 7) fail(HEC_ERR_INVALID_ARG, "tune.kernel_variant out of range");

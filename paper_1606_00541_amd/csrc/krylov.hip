@@ -1,7 +1,8 @@
 // Outer Krylov loop of the preconditioned solve (Section 4 uses restarted
 // GMRES): general HEC matrices for the residual b - A x, deterministic
 // multi-RHS inner products, vector updates, restarted (F)GMRES(m) with
-// classical Gram-Schmidt plus one re-orthogonalization, and BiCGSTAB.  All
+// classical Gram-Schmidt plus one re-orthogonalization (fused into three
+// passes over the basis), and BiCGSTAB.  All
 // vectors are FP64 [n][R] on the device; only the small per-RHS scalars
 // (Hessenberg columns, inner products) travel to the host.  The autotuner for
 // the triangular plans lives here as well.
@@ -205,6 +206,108 @@ __global__ void __launch_bounds__(256) k_basis_update(double *x, const double *Z
     x[t] += s;
 }
 
+// One fused pass of the Gram-Schmidt process over a block's rows (blocks as
+// in k_dot_partial; R a power of two up to kGsMaxR, threads as rows x R).
+// MODE 0: the inner products V_i . w (i < nv) followed by w . w; MODE 1:
+// w' = w - sum_{i<nv} h[i][c] V_i written to out, then V_i . w' and w' . w';
+// MODE 2: the same update, then only w' . w'.  The products go to
+// partial[blk][np][R] (np = nv + 1, or 1 in MODE 2).  Each basis element is
+// loaded once for both the update and the inner products, and a thread loads
+// U rows (U nv <= kMaxPairs values) before it computes on them, so that
+// enough loads are in flight however short the basis.  Rows of problems that
+// are no longer active are neither read nor written.  Lanes of a wavefront
+// that share k are folded with cross-lane exchanges, then the four
+// wavefronts through LDS (a fixed order: deterministic).  The streams are
+// read and written non-temporally, which measured faster for the whole
+// solve (they are not reused before the next pass, while the factors of the
+// preconditioner are).
+constexpr int kGsMaxR = 16;
+struct GsArgs {
+    const double *V;  // basis vector i at V + i * stride
+    long stride;
+    int nv;
+    const double *h;  // [i][P] coefficients of the update (MODE 1, 2)
+    const double *w;
+    double *out;      // the updated vector (MODE 1, 2)
+};
+
+template <int MODE, int U, bool R1>
+__global__ void __launch_bounds__(256) k_gs_pass(GsArgs a, int R_, int rows_per_iter, int P, const int32_t *brow,
+                                                const int32_t *bsys, const int8_t *act, double *partial)
+{
+    // one right-hand side: the coefficients are uniform across the block
+    // and stay in scalar registers
+    const int R = R1 ? 1 : R_;
+    constexpr int NV = kMaxPairs / U;          // basis vectors a row may hold
+    constexpr int NA = MODE == 2 ? 0 : NV;      // basis-product accumulators
+    __shared__ double red[4 * (NA + 1) * kGsMaxR];  // [wave][pair][k]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int k = tid & (R - 1), r0 = tid / R;
+    const int c = bsys[blockIdx.x] * R + k;
+    const long row0 = brow[2 * blockIdx.x], row1 = brow[2 * blockIdx.x + 1];
+    const bool live = act == nullptr || act[c];
+    const int nv = a.nv;
+    double hc[NV], acc[NA + 1];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) hc[i] = (MODE != 0 && i < nv) ? a.h[i * P + c] : 0.0;
+#pragma unroll
+    for (int i = 0; i <= NA; ++i) acc[i] = 0.0;
+    double nrm = 0.0;
+    if (live) {
+        const long step = (long)rows_per_iter * U;
+        for (long row = row0 + r0; row < row1; row += step) {
+            double vv[U][NV], wv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                long ru = row + (long)u * rows_per_iter;
+                ru = ru < row1 ? ru : row;  // past the block's rows: load a valid row, skip it below
+                const long t = ru * R + k;
+#pragma unroll
+                for (int i = 0; i < NV; ++i)
+                    if (i < nv) vv[u][i] = __builtin_nontemporal_load(a.V + i * a.stride + t);
+                wv[u] = __builtin_nontemporal_load(a.w + t);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const long ru = row + (long)u * rows_per_iter;
+                if (ru >= row1) break;
+                double x = wv[u];
+                if (MODE != 0) {
+#pragma unroll
+                    for (int i = 0; i < NV; ++i)
+                        if (i < nv) x -= hc[i] * vv[u][i];
+                    __builtin_nontemporal_store(x, a.out + ru * R + k);
+                }
+                if (MODE != 2) {
+#pragma unroll
+                    for (int i = 0; i < NV; ++i)
+                        if (i < nv) acc[i] += vv[u][i] * x;
+                }
+                nrm += x * x;
+            }
+        }
+    }
+    // slots 0..nb-1: the basis products, slot nb: w' . w'
+    const int nb = MODE == 2 ? 0 : nv, np = nb + 1;
+#pragma unroll
+    for (int i = 0; i <= NA; ++i) {
+        if (i <= nb) {  // uniform across the block
+            double v = i == nb ? nrm : acc[i];
+            for (int off = R; off < 64; off <<= 1) v += __shfl_xor(v, off);
+            if (lane < R) red[(wave * (NA + 1) + i) * R + lane] = v;
+        }
+    }
+    __syncthreads();
+    for (int o = tid; o < np * R; o += 256) {
+        const int p = o / R, kk = o - p * R;
+        double sum = red[(0 * (NA + 1) + p) * R + kk];
+        sum += red[(1 * (NA + 1) + p) * R + kk];
+        sum += red[(2 * (NA + 1) + p) * R + kk];
+        sum += red[(3 * (NA + 1) + p) * R + kk];
+        partial[((size_t)blockIdx.x * np + p) * R + kk] = sum;
+    }
+}
+
 // v[:,c] = w[:,c] / ||w[:,c]|| for active problems (norm^2 in d[c]), else 0
 __global__ void __launch_bounds__(256) k_normalize(double *v, const double *w, const double *d, const int8_t *act,
                                                   long total, int R, const int32_t *seg)
@@ -230,42 +333,48 @@ __global__ void __launch_bounds__(256) k_fill_i32(int32_t *p, long count, int32_
     if (t < count) p[t] = v;
 }
 
-// One Arnoldi step's small work, one thread per problem c still active:
+// One Arnoldi step's small work, one wavefront per problem c still active:
 // the new Hessenberg column h_{0..j+1, j} (the two Gram-Schmidt passes'
 // coefficients summed, and ||w||), the earlier Givens rotations applied to
 // it, a new rotation annihilating h_{j+1,j}, the rotated right-hand side g,
-// and the stopping test |g_{j+1}| / ||b|| <= rtol.  A zero or non-finite
-// column stops the problem with BREAKDOWN and leaves its basis at j
-// vectors.  H holds the rotated upper triangle, column j at H[(j*m + i)*P + c].
-__global__ void __launch_bounds__(256) k_arnoldi(int j, int m, int P, const double *d1, const double *d2,
-                                                 const double *dn, double *H, double *cs, double *sn, double *g,
-                                                 const double *bnorm, double rtol, int maxit, int8_t *act,
-                                                 int32_t *kdim, int32_t *iters, int32_t *status, int32_t *flag)
+// and the stopping test |g_{j+1}| / ||b|| <= rtol.  The lanes fetch the
+// column and the rotations together; lane 0 applies the rotations in order.
+// A zero or non-finite column stops the problem with BREAKDOWN and leaves
+// its basis at j vectors.  H holds the rotated upper triangle, column j at
+// H[(j*m + i)*P + c].
+__global__ void __launch_bounds__(64) k_arnoldi(int j, int m, int P, const double *d1, const double *d2,
+                                                const double *dn, double *H, double *cs, double *sn, double *g,
+                                                const double *bnorm, double rtol, int maxit, int8_t *act,
+                                                int32_t *kdim, int32_t *iters, int32_t *status, int32_t *flag)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= P || !act[c]) return;
-    double h[kMaxPairs + 1];
-    for (int i = 0; i <= j; ++i) h[i] = d1[i * P + c] + d2[i * P + c];
+    __shared__ double sh[kMaxPairs + 1], scs[kMaxPairs], ssn[kMaxPairs];
+    const int c = blockIdx.x, lane = threadIdx.x;
+    if (!act[c]) return;  // uniform across the wavefront
+    if (lane <= j) sh[lane] = d1[lane * P + c] + d2[lane * P + c];
+    if (lane < j) {
+        scs[lane] = cs[lane * P + c];
+        ssn[lane] = sn[lane * P + c];
+    }
+    __syncthreads();
+    if (lane != 0) return;
     const double hn = sqrt(fmax(0.0, dn[c]));
-    h[j + 1] = hn;
+    double t = sh[0];  // h_i after the rotations before i
     for (int i = 0; i < j; ++i) {
-        const double ci = cs[i * P + c], si = sn[i * P + c];
-        const double t = ci * h[i] + si * h[i + 1];
-        h[i + 1] = -si * h[i] + ci * h[i + 1];
-        h[i] = t;
+        const double nx = sh[i + 1], ci = scs[i], si = ssn[i];
+        H[((size_t)j * m + i) * P + c] = ci * t + si * nx;
+        t = -si * t + ci * nx;
     }
     const int it = iters[c] + 1;
     iters[c] = it;
-    const double den = hypot(h[j], h[j + 1]);
+    const double den = hypot(t, hn);
     if (!(den > 0.0) || !isfinite(den)) {
         status[c] = HEC_ERR_BREAKDOWN;
         act[c] = 0;
         return;
     }
-    const double cj = h[j] / den, sj = h[j + 1] / den;
+    const double cj = t / den, sj = hn / den;
     cs[j * P + c] = cj;
     sn[j * P + c] = sj;
-    for (int i = 0; i < j; ++i) H[((size_t)j * m + i) * P + c] = h[i];
     H[((size_t)j * m + j) * P + c] = den;
     const double gj = g[j * P + c];
     g[(j + 1) * P + c] = -sj * gj;
@@ -276,20 +385,31 @@ __global__ void __launch_bounds__(256) k_arnoldi(int j, int m, int P, const doub
 }
 
 // y = R^{-1} g per problem over its kdim[c] columns (back substitution on the
-// rotated Hessenberg triangle); counts a completed cycle for every problem
-// that extended its basis.
-__global__ void __launch_bounds__(256) k_hess_solve(int m, int P, const double *H, const double *g,
-                                                    const int32_t *kdim, double *y, int32_t *restarts)
+// rotated Hessenberg triangle), one wavefront per problem: the triangle is
+// staged in LDS, lane i holds g_i and finally y_i, and each solved y_i is
+// subtracted from the lanes above it (column order).  Counts a completed
+// cycle for every problem that extended its basis.
+__global__ void __launch_bounds__(64) k_hess_solve(int m, int P, const double *H, const double *g,
+                                                   const int32_t *kdim, double *y, int32_t *restarts)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= P) return;
+    __shared__ double T[kMaxPairs][kMaxPairs];  // T[l][i] = H_{i,l}
+    const int c = blockIdx.x, lane = threadIdx.x;
     const int kk = kdim[c];
-    for (int i = kk - 1; i >= 0; --i) {
-        double s = g[i * P + c];
-        for (int l = i + 1; l < kk; ++l) s -= H[((size_t)l * m + i) * P + c] * y[l * P + c];
-        y[i * P + c] = s / H[((size_t)i * m + i) * P + c];
+    if (kk == 0) return;  // uniform across the wavefront
+#pragma unroll 4
+    for (int e = lane; e < kk * kk; e += 64) {
+        const int l = e / kk, i = e - l * kk;
+        if (i <= l) T[l][i] = H[((size_t)l * m + i) * P + c];
     }
-    if (kk > 0) restarts[c] += 1;
+    double s = lane < kk ? g[lane * P + c] : 0.0;
+    __syncthreads();
+    for (int i = kk - 1; i >= 0; --i) {
+        const double yi = __shfl(s, i) / T[i][i];
+        if (lane == i) s = yi;
+        else if (lane < i) s -= T[i][lane] * yi;
+    }
+    if (lane < kk) y[lane * P + c] = s;
+    if (lane == 0) restarts[c] += 1;
 }
 
 inline int blocks_for(long total) { return (int)std::max<long>(1, (total + 255) / 256); }
@@ -353,9 +473,11 @@ struct Ctx {
     const int32_t *seg = nullptr;  // row -> system (batches only)
     double *hbuf = nullptr;        // pinned host scalars
     int nblk, rows_per_iter;
+    bool fused_gs;  // R is a power of two up to kGsMaxR: k_gs_pass applies
     Ctx(long n_, int R_, hipStream_t s, int nsys = 1, const int32_t *sys_ptr = nullptr) : st(s), n(n_), R(R_)
     {
         P = nsys * R;
+        fused_gs = R >= 1 && R <= kGsMaxR && (R & (R - 1)) == 0;
         rows_per_iter = std::max(1, 256 / R);
         // reduction blocks: each covers rows of one system only
         const long chunk = std::max<long>((long)rows_per_iter * 4, (n + 1023) / 1024);
@@ -415,6 +537,37 @@ struct Ctx {
         hipLaunchKernelGGL(k_dot_final, dim3(np * P), dim3(256), 0, st, partial.as<double>(), bptrm.as<int32_t>(),
                            np, R, P, out);
         hip_check(hipGetLastError(), "dot launch");
+    }
+    // one fused Gram-Schmidt pass (k_gs_pass), its inner products finished
+    // per problem into out[p*P + c]
+    template <int MODE>
+    void gs_pass(const GsArgs &a, double *out, const int8_t *act)
+    {
+        const int np = MODE == 2 ? 1 : a.nv + 1;
+        const dim3 g(nblk), b(256);
+        const int32_t *br = browm.as<int32_t>(), *bs = bsysm.as<int32_t>();
+        double *pt = partial.as<double>();
+        if (R == 1) {
+            if (a.nv <= kMaxPairs / 8)
+                hipLaunchKernelGGL((k_gs_pass<MODE, 8, true>), g, b, 0, st, a, R, rows_per_iter, P, br, bs, act, pt);
+            else if (a.nv <= kMaxPairs / 4)
+                hipLaunchKernelGGL((k_gs_pass<MODE, 4, true>), g, b, 0, st, a, R, rows_per_iter, P, br, bs, act, pt);
+            else if (a.nv <= kMaxPairs / 2)
+                hipLaunchKernelGGL((k_gs_pass<MODE, 2, true>), g, b, 0, st, a, R, rows_per_iter, P, br, bs, act, pt);
+            else
+                hipLaunchKernelGGL((k_gs_pass<MODE, 1, true>), g, b, 0, st, a, R, rows_per_iter, P, br, bs, act, pt);
+        } else {
+            if (a.nv <= kMaxPairs / 8)
+                hipLaunchKernelGGL((k_gs_pass<MODE, 8, false>), g, b, 0, st, a, R, rows_per_iter, P, br, bs, act, pt);
+            else if (a.nv <= kMaxPairs / 4)
+                hipLaunchKernelGGL((k_gs_pass<MODE, 4, false>), g, b, 0, st, a, R, rows_per_iter, P, br, bs, act, pt);
+            else if (a.nv <= kMaxPairs / 2)
+                hipLaunchKernelGGL((k_gs_pass<MODE, 2, false>), g, b, 0, st, a, R, rows_per_iter, P, br, bs, act, pt);
+            else
+                hipLaunchKernelGGL((k_gs_pass<MODE, 1, false>), g, b, 0, st, a, R, rows_per_iter, P, br, bs, act, pt);
+        }
+        hipLaunchKernelGGL(k_dot_final, dim3(np * P), dim3(256), 0, st, pt, bptrm.as<int32_t>(), np, R, P, out);
+        hip_check(hipGetLastError(), "k_gs_pass launch");
     }
     // stream-ordered upload of the active mask; the host rewrites the staging
     // area only after the next synchronization, when the copy has landed
@@ -660,25 +813,33 @@ hec_status_t gmres(const DevHec &A, const hec_precond_t &M, int m, const double 
             // problems already finished are skipped (their basis stops growing)
             apply_M(M, Vi(j), Zi(j), R, n, st, c.actm.as<int8_t>());
             spmv(A, Zi(j), w, R, st);
-            for (int i = 0; i <= j; ++i) {
-                pa[i] = Vi(i);
-                pb[i] = w;
-            }
-            for (int pass = 0; pass < 2; ++pass) {
-                double *dp = pass == 0 ? c.d1m.as<double>() : c.d2m.as<double>();
-                c.dots_dev(pa.data(), pb.data(), j + 1, dp, c.actm.as<int8_t>());
-                hipLaunchKernelGGL(k_gs_update, dim3(blocks_for(nR)), dim3(256), 0, st, w, V, nR, dp, j + 1, nR, R,
-                                   P, c.seg, c.actm.as<int8_t>());
-                hip_check(hipGetLastError(), "k_gs_update");
-            }
-            {
+            const int8_t *act = c.actm.as<int8_t>();
+            if (c.fused_gs) {
+                // h1 = V^T w; w' = w - V h1 with h2 = V^T w'; v = w' - V h2
+                // with ||v||^2: three passes over the basis
+                c.gs_pass<0>(GsArgs{V, nR, j + 1, nullptr, w, nullptr}, c.d1m.as<double>(), act);
+                c.gs_pass<1>(GsArgs{V, nR, j + 1, c.d1m.as<double>(), w, w}, c.d2m.as<double>(), act);
+                c.gs_pass<2>(GsArgs{V, nR, j + 1, c.d2m.as<double>(), w, Vi(j + 1)}, c.dnm.as<double>(), act);
+            } else {
+                for (int i = 0; i <= j; ++i) {
+                    pa[i] = Vi(i);
+                    pb[i] = w;
+                }
+                for (int pass = 0; pass < 2; ++pass) {
+                    double *dp = pass == 0 ? c.d1m.as<double>() : c.d2m.as<double>();
+                    c.dots_dev(pa.data(), pb.data(), j + 1, dp, act);
+                    hipLaunchKernelGGL(k_gs_update, dim3(blocks_for(nR)), dim3(256), 0, st, w, V, nR, dp, j + 1, nR,
+                                       R, P, c.seg, act);
+                    hip_check(hipGetLastError(), "k_gs_update");
+                }
                 const double *a[1] = {w};
-                c.dots_dev(a, a, 1, c.dnm.as<double>(), c.actm.as<int8_t>());
+                c.dots_dev(a, a, 1, c.dnm.as<double>(), act);
             }
             // v_{j+1} = w / h_{j+1,j} for the problems still active at step j
-            hipLaunchKernelGGL(k_normalize, dim3(blocks_for(nR)), dim3(256), 0, st, Vi(j + 1), w, c.dnm.as<double>(),
-                               c.actm.as<int8_t>(), nR, R, c.seg);
-            hipLaunchKernelGGL(k_arnoldi, dim3(blocks_for(P)), dim3(256), 0, st, j, m, P, c.d1m.as<double>(),
+            // (in place when the last pass wrote w - V h2 there)
+            hipLaunchKernelGGL(k_normalize, dim3(blocks_for(nR)), dim3(256), 0, st, Vi(j + 1),
+                               c.fused_gs ? Vi(j + 1) : w, c.dnm.as<double>(), act, nR, R, c.seg);
+            hipLaunchKernelGGL(k_arnoldi, dim3(P), dim3(64), 0, st, j, m, P, c.d1m.as<double>(),
                                c.d2m.as<double>(), c.dnm.as<double>(), Hm.as<double>(), csm.as<double>(),
                                snm.as<double>(), gm.as<double>(), bnm.as<double>(), rtol, maxit, c.actm.as<int8_t>(),
                                c.kdm.as<int32_t>(), d_iters, d_stat, flg.as<int32_t>());
@@ -690,7 +851,7 @@ hec_status_t gmres(const DevHec &A, const hec_precond_t &M, int m, const double 
         }
         // y = H^{-1} g per problem, x += Z y (each problem over its own basis)
         if (steps > 0) {
-            hipLaunchKernelGGL(k_hess_solve, dim3(blocks_for(P)), dim3(256), 0, st, m, P, Hm.as<double>(),
+            hipLaunchKernelGGL(k_hess_solve, dim3(P), dim3(64), 0, st, m, P, Hm.as<double>(),
                                gm.as<double>(), c.kdm.as<int32_t>(), c.coef.as<double>(), d_rest);
             hipLaunchKernelGGL(k_basis_update, dim3(blocks_for(nR)), dim3(256), 0, st, x, Z, nR, c.coef.as<double>(),
                                c.kdm.as<int32_t>(), nR, R, P, c.seg);
