@@ -143,7 +143,8 @@ typedef struct hec_krylov_info {
                                 infinity is not iterated at all) */
     int32_t iters;           /* Krylov iterations (Arnoldi steps / BiCGSTAB steps) */
     int32_t restarts;        /* completed restart cycles */
-    int32_t precond_applies; /* preconditioner applications */
+    int32_t precond_applies; /* preconditioner applications (GMRES with delayed
+                                re-orthogonalization: iters or iters + 1) */
     double relres;           /* final true ||b - A x||_2 / ||b||_2, computed in FP64 (||b - A x||_2
                                 for b = 0; NaN when b is not finite) */
 } hec_krylov_info_t;
@@ -430,6 +431,11 @@ void sor_destroy(sor_t sor);
  * device; with an FP32 preconditioner the outer loop is iterative refinement
  * (use HEC_FGMRES).  GMRES/FGMRES(m): classical Gram-Schmidt with one
  * re-orthogonalization, Givens rotations, x updated at the end of each cycle.
+ * For nrhs a power of two up to 16 the re-orthogonalization of each basis
+ * vector is delayed into the next step (the preconditioner is applied to the
+ * once-projected vector and the Hessenberg column is finished one step
+ * later), so the last step before convergence applies M once more than the
+ * iteration count.
  * BiCGSTAB: van der Vorst's right-preconditioned recurrence.  Convergence is
  * declared on the true residual ||b - A x|| / ||b|| <= rtol.  b, x: device FP64
  * [n][nrhs]; x holds x0 on entry.  info: host array of nrhs entries.

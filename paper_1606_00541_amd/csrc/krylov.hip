@@ -1,8 +1,8 @@
 // Outer Krylov loop of the preconditioned solve (Section 4 uses restarted
 // GMRES): general HEC matrices for the residual b - A x, deterministic
 // multi-RHS inner products, vector updates, restarted (F)GMRES(m) with
-// classical Gram-Schmidt plus one re-orthogonalization (fused into three
-// passes over the basis), and BiCGSTAB.  All
+// classical Gram-Schmidt with one re-orthogonalization (delayed by one step,
+// two passes over the basis per step), and BiCGSTAB.  All
 // vectors are FP64 [n][R] on the device; only the small per-RHS scalars
 // (Hessenberg columns, inner products) travel to the host.  The autotuner for
 // the triangular plans lives here as well.
@@ -206,105 +206,221 @@ __global__ void __launch_bounds__(256) k_basis_update(double *x, const double *Z
     x[t] += s;
 }
 
-// One fused pass of the Gram-Schmidt process over a block's rows (blocks as
-// in k_dot_partial; R a power of two up to kGsMaxR, threads as rows x R).
-// MODE 0: the inner products V_i . w (i < nv) followed by w . w; MODE 1:
-// w' = w - sum_{i<nv} h[i][c] V_i written to out, then V_i . w' and w' . w';
-// MODE 2: the same update, then only w' . w'.  The products go to
-// partial[blk][np][R] (np = nv + 1, or 1 in MODE 2).  Each basis element is
-// loaded once for both the update and the inner products, and a thread loads
-// U rows (U nv <= kMaxPairs values) before it computes on them, so that
-// enough loads are in flight however short the basis.  Rows of problems that
-// are no longer active are neither read nor written.  Lanes of a wavefront
-// that share k are folded with cross-lane exchanges, then the four
-// wavefronts through LDS (a fixed order: deterministic).  The streams are
-// read and written non-temporally, which measured faster for the whole
-// solve (they are not reused before the next pass, while the factors of the
-// preconditioner are).
+// Largest RHS count of the delayed-re-orthogonalization kernels (R a power
+// of two up to it); other counts take the two-pass classical path.
 constexpr int kGsMaxR = 16;
-struct GsArgs {
-    const double *V;  // basis vector i at V + i * stride
-    long stride;
-    int nv;
-    const double *h;  // [i][P] coefficients of the update (MODE 1, 2)
-    const double *w;
-    double *out;      // the updated vector (MODE 1, 2)
-};
 
-template <int MODE, int U, bool R1>
-__global__ void __launch_bounds__(256) k_gs_pass(GsArgs a, int R_, int rows_per_iter, int P, const int32_t *brow,
-                                                const int32_t *bsys, const int8_t *act, double *partial)
+// ---- Gram-Schmidt with delayed re-orthogonalization -----------------------
+// Arnoldi step j holds the final orthonormal q_0..q_{j-1} in V slots 0..j-1
+// and in slot j a candidate c_j: the previous Krylov vector projected once
+// against the basis and scaled to about unit length, not yet final.  The
+// step applies the preconditioner to the candidate itself (z_j = M^{-1} c_j,
+// w = A z_j), then one pass of inner products gives s = Q^T c_j, t = Q^T w,
+// c_j.c_j, c_j.w and w.w.  From them alpha = ||c_j - Q s|| makes
+// q_j = (c_j - Q s)/alpha (the second projection of c_j), and w is
+// projected once against [Q, q_j]: c_{j+1} = (w - Q t - tau q_j)/beta with
+// tau = q_j.w = (c_j.w - s.t)/alpha and beta its length, both written in a
+// second pass.  Since w = Q t + tau q_j + beta c_{j+1} and c_{j+1} =
+// alpha' q_{j+1} + [Q, q_j] s' one step later, the Hessenberg column j is
+// [t; tau] + beta [s'; alpha'], finished at step j+1 (z_j, as stored, is
+// exactly the vector with A z_j = w, so x += Z y needs no correction).  Two
+// passes over the basis per step instead of three; the last column of a
+// cycle takes one more inner-product pass without a new vector.
+
+// s_i = Q_i . c and t_i = Q_i . w (i < nq), then c.c, c.w and w.w (w set), or
+// s_i and c.c (w null), per block into partial[blk][np][R]: slot i for s_i,
+// nq + i for t_i, then 2nq, 2nq+1, 2nq+2 (np = 2nq + 3); without w slot nq
+// holds c.c (np = nq + 1).  Blocks as in k_dot_partial; R a power of two up
+// to kGsMaxR.  Wavefront q of the block takes the basis vectors q, q+4, ...
+// over all of the block's rows (each basis element is read once) and every
+// wavefront reads c and w; each product is summed by one wavefront only, so
+// no cross-wavefront step is needed (deterministic).  A thread loads U rows
+// before it computes on them.
+template <int U, bool R1>
+__global__ void __launch_bounds__(256) k_dcgs_dots(const double *Q, long stride, int nq, const double *cv,
+                                                  const double *w, int R_, int P, const int32_t *brow,
+                                                  const int32_t *bsys, const int8_t *act, double *partial)
 {
-    // one right-hand side: the coefficients are uniform across the block
-    // and stay in scalar registers
+    constexpr int NQ = 16 / U;  // basis vectors per wavefront
     const int R = R1 ? 1 : R_;
-    constexpr int NV = kMaxPairs / U;          // basis vectors a row may hold
-    constexpr int NA = MODE == 2 ? 0 : NV;      // basis-product accumulators
-    __shared__ double red[4 * (NA + 1) * kGsMaxR];  // [wave][pair][k]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int k = tid & (R - 1), r0 = tid / R;
+    const int k = lane & (R - 1), r0 = lane / R, rpw = 64 / R;
     const int c = bsys[blockIdx.x] * R + k;
     const long row0 = brow[2 * blockIdx.x], row1 = brow[2 * blockIdx.x + 1];
     const bool live = act == nullptr || act[c];
-    const int nv = a.nv;
-    double hc[NV], acc[NA + 1];
+    const bool hw = w != nullptr;
+    const int mine = nq > wave ? (nq - wave + 3) / 4 : 0;
+    double as[NQ], at[NQ], sc = 0.0;
 #pragma unroll
-    for (int i = 0; i < NV; ++i) hc[i] = (MODE != 0 && i < nv) ? a.h[i * P + c] : 0.0;
-#pragma unroll
-    for (int i = 0; i <= NA; ++i) acc[i] = 0.0;
-    double nrm = 0.0;
+    for (int q = 0; q < NQ; ++q) as[q] = at[q] = 0.0;
     if (live) {
-        const long step = (long)rows_per_iter * U;
-        for (long row = row0 + r0; row < row1; row += step) {
-            double vv[U][NV], wv[U];
+        for (long row = row0 + r0; row < row1; row += (long)rpw * U) {
+            double vq[U][NQ], cu[U], wu[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                long ru = row + (long)u * rows_per_iter;
+                long ru = row + (long)u * rpw;
                 ru = ru < row1 ? ru : row;  // past the block's rows: load a valid row, skip it below
                 const long t = ru * R + k;
 #pragma unroll
-                for (int i = 0; i < NV; ++i)
-                    if (i < nv) vv[u][i] = __builtin_nontemporal_load(a.V + i * a.stride + t);
-                wv[u] = __builtin_nontemporal_load(a.w + t);
+                for (int q = 0; q < NQ; ++q)
+                    if (q < mine) vq[u][q] = __builtin_nontemporal_load(Q + (wave + 4 * q) * stride + t);
+                cu[u] = cv[t];
+                wu[u] = hw ? w[t] : 0.0;
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const long ru = row + (long)u * rows_per_iter;
-                if (ru >= row1) break;
-                double x = wv[u];
-                if (MODE != 0) {
+                if (row + (long)u * rpw >= row1) break;
 #pragma unroll
-                    for (int i = 0; i < NV; ++i)
-                        if (i < nv) x -= hc[i] * vv[u][i];
-                    __builtin_nontemporal_store(x, a.out + ru * R + k);
-                }
-                if (MODE != 2) {
-#pragma unroll
-                    for (int i = 0; i < NV; ++i)
-                        if (i < nv) acc[i] += vv[u][i] * x;
-                }
-                nrm += x * x;
+                for (int q = 0; q < NQ; ++q)
+                    if (q < mine) {
+                        as[q] += vq[u][q] * cu[u];
+                        at[q] += vq[u][q] * wu[u];
+                    }
+                sc += wave == 0 ? cu[u] * cu[u] : (wave == 1 ? cu[u] * wu[u] : wu[u] * wu[u]);
             }
         }
     }
-    // slots 0..nb-1: the basis products, slot nb: w' . w'
-    const int nb = MODE == 2 ? 0 : nv, np = nb + 1;
+    const int np = hw ? 2 * nq + 3 : nq + 1;
+    double *out = partial + (size_t)blockIdx.x * np * R;
 #pragma unroll
-    for (int i = 0; i <= NA; ++i) {
-        if (i <= nb) {  // uniform across the block
-            double v = i == nb ? nrm : acc[i];
-            for (int off = R; off < 64; off <<= 1) v += __shfl_xor(v, off);
-            if (lane < R) red[(wave * (NA + 1) + i) * R + lane] = v;
+    for (int q = 0; q < NQ; ++q) {
+        if (q < mine) {  // uniform across the wavefront
+            double a = as[q], b = at[q];
+            for (int off = R; off < 64; off <<= 1) {
+                a += __shfl_xor(a, off);
+                b += __shfl_xor(b, off);
+            }
+            if (lane < R) {
+                out[(wave + 4 * q) * R + lane] = a;
+                if (hw) out[(nq + wave + 4 * q) * R + lane] = b;
+            }
         }
     }
-    __syncthreads();
-    for (int o = tid; o < np * R; o += 256) {
-        const int p = o / R, kk = o - p * R;
-        double sum = red[(0 * (NA + 1) + p) * R + kk];
-        sum += red[(1 * (NA + 1) + p) * R + kk];
-        sum += red[(2 * (NA + 1) + p) * R + kk];
-        sum += red[(3 * (NA + 1) + p) * R + kk];
-        partial[((size_t)blockIdx.x * np + p) * R + kk] = sum;
+    if (wave < (hw ? 3 : 1)) {
+        for (int off = R; off < 64; off <<= 1) sc += __shfl_xor(sc, off);
+        if (lane < R) out[((hw ? 2 * nq : nq) + wave) * R + lane] = sc;
+    }
+}
+
+// The second pass of a step, one element per thread: q = (c - sum_{i<nq}
+// s_i Q_i) / alpha written over c, and the next candidate c' = (w -
+// sum_{i<nq} t_i Q_i - tau q) / beta.  s and t come from the step's inner
+// products (red[i][P], red[nq+i][P]), alpha, tau and beta from k_dcgs_step
+// (sc[0..2][P]).  Problems that are no longer active are left as they are.
+// With one problem (UNI) every coefficient is uniform and read once per
+// wavefront.
+template <bool UNI>
+__global__ void __launch_bounds__(256) k_dcgs_update(const double *__restrict__ Q, long stride, int nq,
+                                                    double *__restrict__ cv, const double *__restrict__ w,
+                                                    double *__restrict__ cnext, const double *__restrict__ red,
+                                                    const double *__restrict__ sc, long total, int R, int P,
+                                                    const int32_t *seg, const int8_t *act)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const int c = UNI ? 0 : col_of(t, R, seg);
+    if (act && !act[c]) return;
+    double ss = 0.0, tt = 0.0;
+#pragma unroll 8
+    for (int i = 0; i < nq; ++i) {
+        const double qv = __builtin_nontemporal_load(Q + i * stride + t);
+        ss += red[i * P + c] * qv;
+        tt += red[(nq + i) * P + c] * qv;
+    }
+    const double q = (cv[t] - ss) / sc[c];
+    cv[t] = q;
+    __builtin_nontemporal_store((w[t] - tt - sc[P + c] * q) / sc[2 * P + c], cnext + t);
+}
+
+// The small work of step j for each problem still active, one wavefront per
+// problem.  For j >= 1 it first finishes Hessenberg column j-1 from the
+// previous step's [t; tau] and beta (tprev, sc[2][P]) and this step's s and
+// alpha = sqrt(c.c - s.s): the earlier Givens rotations, a new one, the
+// rotated right-hand side g and the stopping test |g_j| / ||b|| <= rtol (a
+// zero or non-finite column stops the problem with BREAKDOWN).  Unless the
+// problem stops or this is the cycle's closing pass (fin), it then sets
+// alpha, tau and beta for k_dcgs_update and keeps [t; tau] for the next
+// step.  H holds the rotated upper triangle, column l at H[(l*m + i)*P + c].
+__global__ void __launch_bounds__(64) k_dcgs_step(int j, int m, int P, int fin, const double *red, double *tprev,
+                                                  double *sc, double *H, double *cs, double *sn, double *g,
+                                                  const double *bnorm, double rtol, int maxit, int8_t *act,
+                                                  int32_t *kdim, int32_t *iters, int32_t *applies, int32_t *status,
+                                                  int32_t *flag)
+{
+    __shared__ double sh[kMaxPairs + 1];
+    __shared__ int s_stop;
+    const int c = blockIdx.x, lane = threadIdx.x;
+    if (!act[c]) return;  // uniform across the wavefront
+    const int nq = j;
+    const double s = lane < nq ? red[lane * P + c] : 0.0;
+    const double t = (!fin && lane < nq) ? red[(nq + lane) * P + c] : 0.0;
+    const double tp = lane < nq ? tprev[lane * P + c] : 0.0;
+    double ss = s * s, tt = t * t, st = s * t;
+    for (int off = 32; off > 0; off >>= 1) {
+        ss += __shfl_xor(ss, off);
+        tt += __shfl_xor(tt, off);
+        st += __shfl_xor(st, off);
+    }
+    const double cc = red[(fin ? nq : 2 * nq) * P + c];
+    const double bprev = sc[2 * P + c];
+    double alpha = 1.0;
+    if (lane == 0) s_stop = 0;
+    if (j >= 1) {
+        alpha = sqrt(fmax(0.0, cc - ss));
+        if (lane < nq) sh[lane] = tp + bprev * s;
+        __syncthreads();
+        if (lane == 0) {
+            const int col = j - 1;
+            const double hn = bprev * alpha;
+            double h = sh[0];  // h_i after the rotations before i
+            for (int i = 0; i < col; ++i) {
+                const double nx = sh[i + 1], ci = cs[i * P + c], si = sn[i * P + c];
+                H[((size_t)col * m + i) * P + c] = ci * h + si * nx;
+                h = -si * h + ci * nx;
+            }
+            const int it = iters[c] + 1;
+            iters[c] = it;
+            const double den = hypot(h, hn);
+            if (!(den > 0.0) || !isfinite(den)) {
+                status[c] = HEC_ERR_BREAKDOWN;
+                act[c] = 0;
+                s_stop = 1;
+            } else {
+                const double cj = h / den, sj = hn / den;
+                cs[col * P + c] = cj;
+                sn[col * P + c] = sj;
+                H[((size_t)col * m + col) * P + c] = den;
+                const double gj = g[col * P + c];
+                g[(col + 1) * P + c] = -sj * gj;
+                g[col * P + c] = cj * gj;
+                kdim[c] = col + 1;
+                if (fin || fabs(g[(col + 1) * P + c]) / bnorm[c] <= rtol || hn == 0.0 || it >= maxit) {
+                    act[c] = 0;
+                    s_stop = 1;
+                }
+            }
+        }
+        __syncthreads();
+        if (s_stop) return;
+    }
+    if (fin) return;
+    const double cw = red[(2 * nq + 1) * P + c], ww = red[(2 * nq + 2) * P + c];
+    const double tau = (cw - st) / alpha;
+    const double est = ww - tt - tau * tau;
+    const double beta = est > 0.0 ? sqrt(est) : (ww > 0.0 ? sqrt(ww) : 1.0);
+    if (lane < nq) tprev[lane * P + c] = t;
+    if (lane == 0) {
+        tprev[nq * P + c] = tau;
+        applies[c] += 1;
+        if (!isfinite(tau) || !isfinite(beta)) {
+            status[c] = HEC_ERR_BREAKDOWN;
+            act[c] = 0;
+            return;
+        }
+        sc[c] = alpha;
+        sc[P + c] = tau;
+        sc[2 * P + c] = beta;
+        atomicOr(flag + j, 1);
     }
 }
 
@@ -473,11 +589,11 @@ struct Ctx {
     const int32_t *seg = nullptr;  // row -> system (batches only)
     double *hbuf = nullptr;        // pinned host scalars
     int nblk, rows_per_iter;
-    bool fused_gs;  // R is a power of two up to kGsMaxR: k_gs_pass applies
+    bool dcgs_ok;  // R is a power of two up to kGsMaxR: the delayed re-orthogonalization applies
     Ctx(long n_, int R_, hipStream_t s, int nsys = 1, const int32_t *sys_ptr = nullptr) : st(s), n(n_), R(R_)
     {
         P = nsys * R;
-        fused_gs = R >= 1 && R <= kGsMaxR && (R & (R - 1)) == 0;
+        dcgs_ok = R >= 1 && R <= kGsMaxR && (R & (R - 1)) == 0;
         rows_per_iter = std::max(1, 256 / R);
         // reduction blocks: each covers rows of one system only
         const long chunk = std::max<long>((long)rows_per_iter * 4, (n + 1023) / 1024);
@@ -506,7 +622,7 @@ struct Ctx {
             upload(segm, sg);
             seg = segm.as<int32_t>();
         }
-        partial.alloc(sizeof(double) * (size_t)nblk * kMaxPairs * R);
+        partial.alloc(sizeof(double) * (size_t)nblk * (2 * kMaxPairs + 4) * R);
         dots.alloc(sizeof(double) * kMaxPairs * P);
         coef.alloc(sizeof(double) * (size_t)std::max(kMaxPairs, kMaxTerms) * P);
         hip_check(hipHostMalloc((void **)&hbuf, sizeof(double) * (size_t)std::max(kMaxPairs, kMaxTerms) * P, 0),
@@ -538,36 +654,29 @@ struct Ctx {
                            np, R, P, out);
         hip_check(hipGetLastError(), "dot launch");
     }
-    // one fused Gram-Schmidt pass (k_gs_pass), its inner products finished
-    // per problem into out[p*P + c]
-    template <int MODE>
-    void gs_pass(const GsArgs &a, double *out, const int8_t *act)
+    // the inner products of one delayed-re-orthogonalization step
+    // (k_dcgs_dots), finished per problem into out[p*P + c]
+    void dcgs_dots(const double *Q, long stride, int nq, const double *cv, const double *w, double *out,
+                   const int8_t *act)
     {
-        const int np = MODE == 2 ? 1 : a.nv + 1;
+        const int np = w ? 2 * nq + 3 : nq + 1;
         const dim3 g(nblk), b(256);
         const int32_t *br = browm.as<int32_t>(), *bs = bsysm.as<int32_t>();
         double *pt = partial.as<double>();
+#define HEC_DCGS_DOTS(U, R1)                                                                                   \
+    hipLaunchKernelGGL((k_dcgs_dots<U, R1>), g, b, 0, st, Q, stride, nq, cv, w, R, P, br, bs, act, pt)
         if (R == 1) {
-            if (a.nv <= kMaxPairs / 8)
-                hipLaunchKernelGGL((k_gs_pass<MODE, 8, true>), g, b, 0, st, a, R, rows_per_iter, P, br, bs, act, pt);
-            else if (a.nv <= kMaxPairs / 4)
-                hipLaunchKernelGGL((k_gs_pass<MODE, 4, true>), g, b, 0, st, a, R, rows_per_iter, P, br, bs, act, pt);
-            else if (a.nv <= kMaxPairs / 2)
-                hipLaunchKernelGGL((k_gs_pass<MODE, 2, true>), g, b, 0, st, a, R, rows_per_iter, P, br, bs, act, pt);
-            else
-                hipLaunchKernelGGL((k_gs_pass<MODE, 1, true>), g, b, 0, st, a, R, rows_per_iter, P, br, bs, act, pt);
+            if (nq <= 8) HEC_DCGS_DOTS(8, true);
+            else if (nq <= 16) HEC_DCGS_DOTS(4, true);
+            else HEC_DCGS_DOTS(2, true);
         } else {
-            if (a.nv <= kMaxPairs / 8)
-                hipLaunchKernelGGL((k_gs_pass<MODE, 8, false>), g, b, 0, st, a, R, rows_per_iter, P, br, bs, act, pt);
-            else if (a.nv <= kMaxPairs / 4)
-                hipLaunchKernelGGL((k_gs_pass<MODE, 4, false>), g, b, 0, st, a, R, rows_per_iter, P, br, bs, act, pt);
-            else if (a.nv <= kMaxPairs / 2)
-                hipLaunchKernelGGL((k_gs_pass<MODE, 2, false>), g, b, 0, st, a, R, rows_per_iter, P, br, bs, act, pt);
-            else
-                hipLaunchKernelGGL((k_gs_pass<MODE, 1, false>), g, b, 0, st, a, R, rows_per_iter, P, br, bs, act, pt);
+            if (nq <= 8) HEC_DCGS_DOTS(8, false);
+            else if (nq <= 16) HEC_DCGS_DOTS(4, false);
+            else HEC_DCGS_DOTS(2, false);
         }
+#undef HEC_DCGS_DOTS
         hipLaunchKernelGGL(k_dot_final, dim3(np * P), dim3(256), 0, st, pt, bptrm.as<int32_t>(), np, R, P, out);
-        hip_check(hipGetLastError(), "k_gs_pass launch");
+        hip_check(hipGetLastError(), "k_dcgs_dots launch");
     }
     // stream-ordered upload of the active mask; the host rewrites the staging
     // area only after the next synchronization, when the copy has landed
@@ -675,10 +784,12 @@ hec_status_t final_status(hec_krylov_info_t *info, const std::vector<double> &bn
 }
 
 // Restarted (F)GMRES(m): right preconditioning with the preconditioned basis
-// Z stored (flexible form), CGS with one re-orthogonalization.  Every
+// Z stored (flexible form), CGS with one re-orthogonalization: delayed by
+// one step (k_dcgs_*: two passes over the basis per step) when R is a power
+// of two up to kGsMaxR, else two classical passes per step.  Every
 // problem runs its own Arnoldi process in lockstep with the others; the
 // Hessenberg columns, Givens rotations, rotated residual and each problem's
-// stopping test live on the device (k_arnoldi), so the host does not wait
+// stopping test live on the device (k_dcgs_step, k_arnoldi), so the host does not wait
 // for a step to finish before issuing the next: it keeps two steps in
 // flight and reads back one "any problem still active" flag per step, then
 // synchronizes once per restart cycle for the true residual.  A problem whose
@@ -690,8 +801,14 @@ hec_status_t gmres(const DevHec &A, const hec_precond_t &M, int m, const double 
     const long nR = n * R;
     Ctx c(n, R, st, nsys, sys_ptr);
     const int P = c.P;
-    DevMem Vm, Zm, wm, rm, Hm, csm, snm, gm, bnm, cnt, flg;
+    DevMem Vm, Zm, wm, rm, Hm, csm, snm, gm, bnm, cnt, flg, redm, tpm, scm;
     Vm.alloc(sizeof(double) * (size_t)(m + 1) * nR);
+    const bool dcgs = c.dcgs_ok;
+    if (dcgs) {
+        redm.alloc(sizeof(double) * (size_t)(2 * m + 3) * P);  // one step's inner products
+        tpm.alloc(sizeof(double) * (size_t)(m + 1) * P);       // [t; tau] of the previous step
+        scm.alloc(sizeof(double) * 3 * (size_t)P);             // alpha, tau, beta
+    }
     Zm.alloc(sizeof(double) * (size_t)m * nR);
     wm.alloc(sizeof(double) * (size_t)nR);
     rm.alloc(sizeof(double) * (size_t)nR);
@@ -755,6 +872,13 @@ hec_status_t gmres(const DevHec &A, const hec_precond_t &M, int m, const double 
     hip_check(hipGetLastError(), "k_fill_i32");
     std::vector<int32_t> hcnt(4 * (size_t)P, 0);
     std::vector<const double *> pa(kMaxPairs), pb(kMaxPairs);
+    auto launch_dcgs_step = [&](int j, int fin) {
+        hipLaunchKernelGGL(k_dcgs_step, dim3(P), dim3(64), 0, st, j, m, P, fin, redm.as<double>(), tpm.as<double>(),
+                           scm.as<double>(), Hm.as<double>(), csm.as<double>(), snm.as<double>(), gm.as<double>(),
+                           bnm.as<double>(), rtol, maxit, c.actm.as<int8_t>(), c.kdm.as<int32_t>(), d_iters,
+                           d_iters + 3 * P, d_stat, flg.as<int32_t>());
+        hip_check(hipGetLastError(), "k_dcgs_step");
+    };
     for (;;) {
         // true residual and convergence test (the one full synchronization
         // of a restart cycle)
@@ -814,31 +938,44 @@ hec_status_t gmres(const DevHec &A, const hec_precond_t &M, int m, const double 
             apply_M(M, Vi(j), Zi(j), R, n, st, c.actm.as<int8_t>());
             spmv(A, Zi(j), w, R, st);
             const int8_t *act = c.actm.as<int8_t>();
-            if (c.fused_gs) {
-                // h1 = V^T w; w' = w - V h1 with h2 = V^T w'; v = w' - V h2
-                // with ||v||^2: three passes over the basis
-                c.gs_pass<0>(GsArgs{V, nR, j + 1, nullptr, w, nullptr}, c.d1m.as<double>(), act);
-                c.gs_pass<1>(GsArgs{V, nR, j + 1, c.d1m.as<double>(), w, w}, c.d2m.as<double>(), act);
-                c.gs_pass<2>(GsArgs{V, nR, j + 1, c.d2m.as<double>(), w, Vi(j + 1)}, c.dnm.as<double>(), act);
-            } else {
-                for (int i = 0; i <= j; ++i) {
-                    pa[i] = Vi(i);
-                    pb[i] = w;
-                }
-                for (int pass = 0; pass < 2; ++pass) {
-                    double *dp = pass == 0 ? c.d1m.as<double>() : c.d2m.as<double>();
-                    c.dots_dev(pa.data(), pb.data(), j + 1, dp, act);
-                    hipLaunchKernelGGL(k_gs_update, dim3(blocks_for(nR)), dim3(256), 0, st, w, V, nR, dp, j + 1, nR,
-                                       R, P, c.seg, act);
-                    hip_check(hipGetLastError(), "k_gs_update");
-                }
+            if (dcgs) {
+                // slot j holds the candidate: inner products, column j-1 and
+                // the coefficients, then q_j over the candidate and the next
+                // candidate into slot j+1
+                c.dcgs_dots(V, nR, j, Vi(j), w, redm.as<double>(), act);
+                launch_dcgs_step(j, 0);
+                if (P == 1)
+                    hipLaunchKernelGGL(k_dcgs_update<true>, dim3(blocks_for(nR)), dim3(256), 0, st, V, nR, j, Vi(j), w,
+                                       Vi(j + 1), redm.as<double>(), scm.as<double>(), nR, R, P, c.seg, act);
+                else
+                    hipLaunchKernelGGL(k_dcgs_update<false>, dim3(blocks_for(nR)), dim3(256), 0, st, V, nR, j, Vi(j),
+                                       w, Vi(j + 1), redm.as<double>(), scm.as<double>(), nR, R, P, c.seg, act);
+                hip_check(hipGetLastError(), "k_dcgs_update");
+                hip_check(hipMemcpyAsync(hflag + j, flg.as<int32_t>() + j, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                         st), "D2H");
+                hip_check(hipEventRecord(ev[j], st), "hipEventRecord");
+                ++steps;
+                continue;
+            }
+            // classical Gram-Schmidt, two passes
+            for (int i = 0; i <= j; ++i) {
+                pa[i] = Vi(i);
+                pb[i] = w;
+            }
+            for (int pass = 0; pass < 2; ++pass) {
+                double *dp = pass == 0 ? c.d1m.as<double>() : c.d2m.as<double>();
+                c.dots_dev(pa.data(), pb.data(), j + 1, dp, act);
+                hipLaunchKernelGGL(k_gs_update, dim3(blocks_for(nR)), dim3(256), 0, st, w, V, nR, dp, j + 1, nR, R,
+                                   P, c.seg, act);
+                hip_check(hipGetLastError(), "k_gs_update");
+            }
+            {
                 const double *a[1] = {w};
                 c.dots_dev(a, a, 1, c.dnm.as<double>(), act);
             }
             // v_{j+1} = w / h_{j+1,j} for the problems still active at step j
-            // (in place when the last pass wrote w - V h2 there)
-            hipLaunchKernelGGL(k_normalize, dim3(blocks_for(nR)), dim3(256), 0, st, Vi(j + 1),
-                               c.fused_gs ? Vi(j + 1) : w, c.dnm.as<double>(), act, nR, R, c.seg);
+            hipLaunchKernelGGL(k_normalize, dim3(blocks_for(nR)), dim3(256), 0, st, Vi(j + 1), w, c.dnm.as<double>(),
+                               act, nR, R, c.seg);
             hipLaunchKernelGGL(k_arnoldi, dim3(P), dim3(64), 0, st, j, m, P, c.d1m.as<double>(),
                                c.d2m.as<double>(), c.dnm.as<double>(), Hm.as<double>(), csm.as<double>(),
                                snm.as<double>(), gm.as<double>(), bnm.as<double>(), rtol, maxit, c.actm.as<int8_t>(),
@@ -848,6 +985,12 @@ hec_status_t gmres(const DevHec &A, const hec_precond_t &M, int m, const double 
                       "D2H");
             hip_check(hipEventRecord(ev[j], st), "hipEventRecord");
             ++steps;
+        }
+        if (dcgs && steps == m) {
+            // close the cycle: the last candidate's inner products finish
+            // column m-1 of the problems still active
+            c.dcgs_dots(V, nR, m, Vi(m), nullptr, redm.as<double>(), c.actm.as<int8_t>());
+            launch_dcgs_step(m, 1);
         }
         // y = H^{-1} g per problem, x += Z y (each problem over its own basis)
         if (steps > 0) {
@@ -866,7 +1009,7 @@ hec_status_t gmres(const DevHec &A, const hec_precond_t &M, int m, const double 
     }
     for (int k = 0; k < P; ++k) {
         info[k].iters = hcnt[k];
-        info[k].precond_applies = hcnt[k];
+        info[k].precond_applies = dcgs ? hcnt[3 * P + k] : hcnt[k];
         info[k].restarts = hcnt[P + k];
         if (info[k].status == HEC_OK && hcnt[2 * P + k] == HEC_ERR_BREAKDOWN) info[k].status = HEC_ERR_BREAKDOWN;
     }

@@ -372,3 +372,28 @@ def test_system_queue_reads_beyond_its_ring():
     assert np.array_equal(z, apply(g, r))
     L, U = oracle.ilu0(A)
     assert relerr(z, oracle.ilu_apply(L, U, r)) <= FP64_TOL
+
+
+@pytest.mark.parametrize("R", [1, 3, 4])
+def test_gmres_both_orthogonalizations_match_oracle(R):
+    # R = 1, 4: the re-orthogonalization delayed into the next step; R = 3:
+    # two classical passes per step.  A short restart length takes several
+    # cycles, each closed by the extra inner-product pass of the delayed form.
+    A = synth.poisson3d(14)
+    f = H.ilu_setup(A, "ilu0", tune=H.tune_default(max_nrhs=R))
+    M = H.hec_from_csr(A)
+    b = synth.rhs(A.n, R, 21)
+    xt = torch.zeros(A.n, R, dtype=torch.float64, device="cuda")
+    st, info = H.krylov_solve(M, f, dev(b), xt, method="gmres", m=4, rtol=1e-10)
+    assert st == 0
+    x = xt.cpu().numpy()
+    L, U = oracle.ilu0(A)
+    for k in range(R):
+        xo, io = oracle.fgmres(A, b[:, k], lambda v: oracle.ilu_apply(L, U, v), m=4, rtol=1e-10)
+        assert relerr(x[:, k], xo) <= 1e-7
+        assert abs(info[k].iters - io.iters) <= 2 and info[k].restarts >= 2
+        assert info[k].precond_applies in (info[k].iters, info[k].iters + 1)
+    # the iteration limit reached in the middle of a cycle
+    xt.zero_()
+    st, info = H.krylov_solve(M, f, dev(b), xt, method="gmres", m=4, rtol=1e-14, maxit=6)
+    assert st == 8 and all(q.status == 8 and q.iters == 6 for q in info)
