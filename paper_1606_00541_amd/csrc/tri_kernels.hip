@@ -1251,40 +1251,30 @@ OwnerKernel split_kernel(int w, bool unit, size_t &lds, int rows, int CH)
 
 // Barrier-free solve of a level-ordered plan through global memory, for
 // solutions too large for LDS (the alternative to one launch per level).  The
-// (row, rhs) items in level order are cut into chunks of 64; every wavefront
-// takes kSfBatch consecutive chunks at a time from a counter (epoch[2], reset
-// by the fill kernel that precedes the launch) and solves them in order.  A
-// chunk depends only on earlier chunks, all of which have been taken by
-// wavefronts that are running; the earliest unfinished chunk belongs to a
-// wavefront that has finished its batch's earlier chunks, so the solve
-// progresses whatever the number of resident wavefronts (taking batches
-// rather than single chunks keeps the counter off the critical path).
-// xw starts as the sentinel; an item reads its inputs with
+// (row, rhs) items in level order are cut into chunks of 64, dealt
+// round-robin to the wavefronts of the grid.  A chunk depends only on earlier
+// chunks, and the earliest unfinished chunk belongs to a wavefront that has
+// finished all its earlier ones, so the solve progresses when every
+// wavefront is resident: the kernel is launched cooperatively, so that the
+// runtime either makes the whole grid co-resident or refuses the launch.
+// (Taking chunks from one shared counter instead needs no co-residency, but
+// the counter serializes: with batches of 8 chunks per claim, 288K claims on
+// one address made an application of the batched 256-system workload 3.7x
+// slower.)  xw starts as the sentinel; an item reads its inputs with
 // agent-scope loads and, once none holds the sentinel, computes exactly as
 // solve_item does and publishes its value with an agent-scope store.  Lanes
 // whose inputs are ready finish inside the wait loop, so a wavefront never
 // waits on one of its own lanes.
-constexpr int kSfBatch = 8;
-
 template <typename T, typename TIn, typename TOut>
-__global__ void __launch_bounds__(256) k_syncfree(TriArgs a)
+__global__ void __launch_bounds__(256) k_syncfree(TriArgs a, int waves)
 {
     const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const long items = (long)a.n * a.R;
     const long nch = (items + 63) >> 6;
     const T *ev = static_cast<const T *>(a.ell_val);
     T *xw = static_cast<T *>(a.xw);
-    long ch = 0, bend = 0;
-    for (;;) {
-        if (ch == bend) {
-            unsigned first = 0;
-            if (lane == 0)
-                first = __hip_atomic_fetch_add(&a.epoch[2], (unsigned)kSfBatch, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-            ch = (long)__shfl(first, 0);
-            bend = ch + kSfBatch;
-        }
-        if (ch >= nch) break;
+    for (long ch = wave; ch < nch; ch += waves) {
         const long t = (ch << 6) + lane;
         bool todo = t < items;
         const int x = todo ? (int)(t / a.R) : 0;
@@ -1339,7 +1329,6 @@ __global__ void __launch_bounds__(256) k_syncfree(TriArgs a)
                 }
             }
         }
-        ++ch;
     }
 }
 
@@ -1440,17 +1429,21 @@ void launch_typed(DevTri &d, TriArgs a, hipStream_t st)
     if (d.kind == HEC_SCHED_LEVEL_LAUNCH && d.variant == 5) {
         const size_t cnt = ((size_t)d.n + 1) * a.R;
         hipLaunchKernelGGL(k_fill_sentinel<T>, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st,
-                           static_cast<T *>(a.xw), cnt, a.epoch + 2);
+                           static_cast<T *>(a.xw), cnt, (unsigned *)nullptr);
         // about one wavefront per chunk of an average level (at least two
-        // workgroups per compute unit), within the occupancy; progress does
-        // not depend on how many are resident
+        // workgroups per compute unit), within half the occupancy; the
+        // cooperative launch guarantees co-residency (it costs tens of
+        // microseconds, small beside this kernel's milliseconds)
         const long chunks = ((long)d.n * a.R + 63) / 64;
         const int cap = capacity_of((const void *)k_syncfree<T, TIn, TOut>, 256, 0);
         const long per_level = chunks / std::max(1, d.nlev);
-        const long lim = std::min<long>(std::max(1, cap), std::max<long>(2L * device_cus(), per_level / 4));
-        const int grid = (int)std::max<long>(1, std::min<long>(lim, (chunks + 4 * kSfBatch - 1) / (4 * kSfBatch)));
-        hipLaunchKernelGGL((k_syncfree<T, TIn, TOut>), dim3(grid), dim3(256), 0, st, a);
-        hip_check(hipGetLastError(), "k_syncfree launch");
+        const long lim = std::min<long>(std::max(1, cap / 2), std::max<long>(2L * device_cus(), per_level / 4));
+        const int grid = (int)std::max<long>(1, std::min<long>(lim, (chunks + 3) / 4));
+        int waves = grid * 4;
+        void *args[] = {(void *)&a, (void *)&waves};
+        hip_check(hipLaunchCooperativeKernel((const void *)k_syncfree<T, TIn, TOut>, dim3(grid), dim3(256), args, 0,
+                                             st),
+                  "k_syncfree cooperative launch");
         return;
     }
     if (d.sysq) {
