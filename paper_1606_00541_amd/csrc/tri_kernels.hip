@@ -807,12 +807,17 @@ template <typename T> __device__ __forceinline__ void lds_put(T *p, T v)
 }
 
 template <typename T, int W> struct DfRegs {
-    int rb, re;
-    int c[W];
+    int c[W];  // columns as loaded, then LDS byte offsets
     T v[W];
+    T b;       // right-hand side of the lane's item
+    int r, k;  // the lane's item: window row, right-hand side
+    int xo;    // LDS byte offset of the item's value
 };
 
-template <typename T, int W, bool UNIT, bool TAIL, bool R1>
+// TRACE: per-step clocks (tri_plan_trace).  Untraced instances read no clock
+// in the step loop: the clock is a scalar-memory read, and with one possibly
+// outstanding the compiler must drain every LDS access before the next step.
+template <typename T, int W, bool UNIT, bool TAIL, bool R1, bool TRACE>
 __global__ void __launch_bounds__(512) k_dataflow(TriArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -915,28 +920,33 @@ __global__ void __launch_bounds__(512) k_dataflow(TriArgs a)
     copy_ints(erl, a.exp_row + e0, nex, -lo);
     copy_ints(stl, a.step_row + 2 * s0, 2 * ns, -lo);
     __syncthreads();
-    const unsigned long long t_fill = a.trace ? __builtin_amdgcn_s_memrealtime() : 0ull;
+    const unsigned long long t_fill = TRACE ? __builtin_amdgcn_s_memrealtime() : 0ull;
 
     if (wv < nwc) {
         const T *ev = static_cast<const T *>(a.ell_val);
         const T *tv = static_cast<const T *>(a.tail_val);
         // Lanes past the step's items repeat its last item, so loads and
         // their uses are unconditional and the compiler's load waits stay
-        // exact (DEPTH steps' loads stay in flight while one is solved).
-        // The ELL slots of a step's rows are contiguous per slot: buffer
-        // loads with one per-lane byte offset and a per-slot scalar offset
-        // (no 64-bit address arithmetic per load).
+        // exact.  The ELL slots of a step's rows are contiguous per slot:
+        // buffer loads with one per-lane byte offset and a per-slot scalar
+        // offset (no 64-bit address arithmetic per load).
         const int nb_col = (int)min((size_t)0x7fffffff, (size_t)a.w * a.ld * sizeof(int32_t));
         const int nb_val = (int)min((size_t)0x7fffffff, (size_t)a.w * a.ld * sizeof(T));
         const __amdgpu_buffer_rsrc_t rcol =
             __builtin_amdgcn_make_buffer_rsrc(const_cast<int32_t *>(a.ell_col), 0, nb_col, 0x00020000);
         const __amdgpu_buffer_rsrc_t rval =
             __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(ev), 0, nb_val, 0x00020000);
+        unsigned char *xb = reinterpret_cast<unsigned char *>(xl);
+        // Everything a step needs besides its inputs is prepared when its
+        // register set is filled, steps ahead: the matrix loads, the lane's
+        // item (row r, right-hand side k), its right-hand-side value from LDS
+        // and the LDS byte offset its result goes to.
         auto load = [&](DfRegs<T, W> &u, int rb, int re) {
-            u.rb = rb;
-            u.re = re;
             const int it = min(lane, (re - rb) * R - 1);
-            const int x = lo + rb + (R1 ? it : it / R);
+            const int q = R1 ? it : it / R;
+            u.k = R1 ? 0 : it - q * R;
+            u.r = rb + q;
+            const int x = lo + u.r;
 #pragma unroll
             for (int e = 0; e < W; ++e) {
                 u.c[e] = (int)__builtin_amdgcn_raw_buffer_load_b32(rcol, x * (int)sizeof(int32_t),
@@ -946,64 +956,73 @@ __global__ void __launch_bounds__(512) k_dataflow(TriArgs a)
                 else
                     u.v[e] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rval, x * 4, e * a.ld * 4, 0));
             }
+            u.xo = (u.r * R + u.k) * (int)sizeof(T);
+            u.b = bl[u.r * R + u.k];
         };
-        const int ntr = a.trace ? min(ns, a.trace_stride - 1) : 0;
-        bool aborted = false;
-        // solve step j from registers u; `nj` is the step whose bounds are
-        // read (returned in nb, ne) while this one waits for LDS
-        // Solve step j from registers u.  The matrix loads of step j+3 (bounds
-        // fb, fe, read one step earlier) go into `fill` right after this
-        // step's input reads are issued, and the bounds of step j+4 are read
-        // behind them, so neither waits on the other.
-        auto process = [&](const DfRegs<T, W> &u, DfRegs<T, W> &fill, int j, int &fb, int &fe, int nq) {
-            if (j < ntr && lane == 0) ltr[2 * j] = __builtin_amdgcn_s_memrealtime();
-            const int items = (u.re - u.rb) * R;
-            const int it = min(lane, items - 1);
-            const int q = R1 ? it : it / R, k = it - q * R;
-            const int r = u.rb + q;  // window offset of the row
-            T sv = bl[r * R + k];
-            // columns are LDS value rows (ELL padding names the zero row)
-            T dep[W];
-            int off[W];
+        // columns (LDS value rows; ELL padding names the zero row) become
+        // LDS byte offsets one step before their use
+        auto to_offsets = [&](DfRegs<T, W> &u) {
 #pragma unroll
-            for (int e = 0; e < W; ++e) {
-                off[e] = u.c[e] * R + k;
-                dep[e] = lds_get(xl + off[e]);
-            }
+            for (int e = 0; e < W; ++e) u.c[e] = (R1 ? u.c[e] : u.c[e] * R + u.k) * (int)sizeof(T);
+        };
+        const int ntr = TRACE ? min(ns, a.trace_stride - 1) : 0;
+        bool aborted = false;
+        // Solve step j from registers u.  Its inputs are read first; while
+        // they are in flight the loads of step j+K-1 (bounds fb, fe, read one
+        // step earlier) go into `fill` and the bounds of step j+K are read;
+        // after the result is stored the next step's columns become offsets.  Padding subtracts 0 * 0,
+        // which leaves the value unchanged bit for bit.  An input not solved
+        // yet holds the sentinel (a NaN), so a lane that read one ends with a
+        // NaN: one test of the result covers every input.  Only then are the
+        // inputs checked one by one (the result may be a NaN of the data,
+        // which passes) and re-read until none holds the sentinel, and the
+        // value is recomputed in the same order.
+        auto process = [&](const DfRegs<T, W> &u, DfRegs<T, W> &fill, DfRegs<T, W> &next, int j, int &fb, int &fe,
+                           int nq) {
+            if (TRACE && j < ntr && lane == 0) ltr[2 * j] = __builtin_amdgcn_s_memrealtime();
+            T dep[W];
+#pragma unroll
+            for (int e = 0; e < W; ++e) dep[e] = lds_get(reinterpret_cast<const T *>(xb + u.c[e]));
+            __builtin_amdgcn_sched_barrier(0);  // the reads go first
             load(fill, fb, fe);
             fb = stl[2 * nq];
             fe = stl[2 * nq + 1];
-            bool pend = false;
+            T acc = u.b;
 #pragma unroll
-            for (int e = 0; e < W; ++e) pend |= is_sentinel(dep[e]);
-            unsigned spins = 0;
-            while (pend) {
-                // re-read every input (one LDS round trip per poll; inputs
-                // already present do not change)
-#pragma unroll
-                for (int e = 0; e < W; ++e) dep[e] = lds_get(xl + off[e]);
-                pend = false;
+            for (int e = 0; e < W; ++e) acc -= u.v[e] * dep[e];
+            if (__ballot(acc != acc) != 0) {
+                bool pend = false;
 #pragma unroll
                 for (int e = 0; e < W; ++e) pend |= is_sentinel(dep[e]);
-                if (pend && (++spins & 63u) == 0) {
-                    if (lds_get(&s_abort)) {
-                        aborted = true;
-                        break;
-                    }
-                    if (spins > (a.spin << 4)) {
-                        lds_put(&s_abort, 2);
-                        aborted = true;
-                        break;
+                unsigned spins = 0;
+                while (pend) {
+                    // re-read every input (one LDS round trip per poll; inputs
+                    // already present do not change)
+#pragma unroll
+                    for (int e = 0; e < W; ++e) dep[e] = lds_get(reinterpret_cast<const T *>(xb + u.c[e]));
+                    pend = false;
+#pragma unroll
+                    for (int e = 0; e < W; ++e) pend |= is_sentinel(dep[e]);
+                    if (pend && (++spins & 63u) == 0) {
+                        if (lds_get(&s_abort)) {
+                            aborted = true;
+                            break;
+                        }
+                        if (spins > (a.spin << 4)) {
+                            lds_put(&s_abort, 2);
+                            aborted = true;
+                            break;
+                        }
                     }
                 }
-            }
-            // padding subtracts 0 * 0, which leaves sv unchanged bit for bit
+                acc = u.b;
 #pragma unroll
-            for (int e = 0; e < W; ++e) sv -= u.v[e] * dep[e];
+                for (int e = 0; e < W; ++e) acc -= u.v[e] * dep[e];
+            }
             if (TAIL) {
-                const int x = lo + r;
+                const int x = lo + u.r;
                 for (int p = a.tail_ptr[x]; p < a.tail_ptr[x + 1]; ++p) {
-                    const int o = a.tail_col[p] * R + k;
+                    const int o = a.tail_col[p] * R + u.k;
                     T dd = lds_get(xl + o);
                     unsigned sp = 0;
                     while (is_sentinel(dd)) {
@@ -1020,12 +1039,17 @@ __global__ void __launch_bounds__(512) k_dataflow(TriArgs a)
                             }
                         }
                     }
-                    sv -= tv[p] * dd;
+                    acc -= tv[p] * dd;
                 }
             }
-            // lanes past the items store the same value as the last item's lane
-            lds_put(xl + r * R + k, sv);
-            if (j < ntr && lane == 0) ltr[2 * j + 1] = __builtin_amdgcn_s_memrealtime();
+            // lanes past the items store the same value as the last item's lane;
+            // the store is the end of the dependency chain, so nothing of the
+            // next step (which waits for this step's bounds read) is
+            // scheduled above it
+            lds_put(reinterpret_cast<T *>(xb + u.xo), acc);
+            __builtin_amdgcn_sched_barrier(0);
+            to_offsets(next);
+            if (TRACE && j < ntr && lane == 0) ltr[2 * j + 1] = __builtin_amdgcn_s_memrealtime();
         };
         // The wave walks its own steps [j, jend) in order.  K register sets
         // rotate: while step j is solved from one, the next K-2 steps have
@@ -1040,7 +1064,7 @@ __global__ void __launch_bounds__(512) k_dataflow(TriArgs a)
         int j = a.wave_ptr[g * nwc + wv] - s0;
         const int jend = a.wave_ptr[g * nwc + wv + 1] - s0;
         const int last = jend - 1;
-        constexpr int K = W <= 3 ? 8 : (W <= 5 ? 6 : (W <= 8 ? 4 : 3));
+        constexpr int K = W == 1 ? 12 : (W == 2 ? 10 : (W == 3 ? (R1 ? 9 : 8) : (W <= 5 ? 6 : (W <= 8 ? 4 : 3))));
         constexpr int kAhead = K - 1;
         DfRegs<T, W> S[K];
         auto first = [&](DfRegs<T, W> &u, int q) {
@@ -1048,24 +1072,25 @@ __global__ void __launch_bounds__(512) k_dataflow(TriArgs a)
             load(u, stl[2 * q], stl[2 * q + 1]);
         };
         int fb = 0, fe = 0;
-        auto run = [&](const DfRegs<T, W> &u, DfRegs<T, W> &fill) {
-            process(u, fill, j, fb, fe, min(j + kAhead + 1, last));
+        auto run = [&](const DfRegs<T, W> &u, DfRegs<T, W> &fill, DfRegs<T, W> &next) {
+            process(u, fill, next, j, fb, fe, min(j + kAhead + 1, last));
             j += 1;
         };
         if (j < jend) {
 #pragma unroll
             for (int p = 0; p < K - 1; ++p) first(S[p], j + p);
+            to_offsets(S[0]);
             fb = stl[2 * min(j + kAhead, last)];
             fe = stl[2 * min(j + kAhead, last) + 1];
             const int rounds = (jend - j) / K, rest = (jend - j) - K * rounds;
             for (int q = 0; q < rounds; ++q) {
 #pragma unroll
-                for (int p = 0; p < K; ++p) run(S[p], S[(p + K - 1) % K]);
+                for (int p = 0; p < K; ++p) run(S[p], S[(p + K - 1) % K], S[(p + 1) % K]);
                 if (__ballot(aborted) != 0) break;
             }
 #pragma unroll
             for (int p = 0; p < K - 1; ++p)
-                if (rest > p && __ballot(aborted) == 0) run(S[p], S[(p + K - 1) % K]);
+                if (rest > p && __ballot(aborted) == 0) run(S[p], S[(p + K - 1) % K], S[(p + 1) % K]);
         }
     } else if (wv == nwc) {
         // import wave: lane l owns items l, l+64, l+128, ... (level order).
@@ -1154,13 +1179,13 @@ __global__ void __launch_bounds__(512) k_dataflow(TriArgs a)
         }
     }
     __syncthreads();
-    const unsigned long long t_done = a.trace ? __builtin_amdgcn_s_memrealtime() : 0ull;
+    const unsigned long long t_done = TRACE ? __builtin_amdgcn_s_memrealtime() : 0ull;
     if (tid == 0 && s_abort == 2) {
         __hip_atomic_store(a.err_dev, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(a.err_host, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         s_abort = 1;
     }
-    if (a.trace) {
+    if (TRACE) {
         const int ntr = min(ns, a.trace_stride - 1);
         for (int t = tid; t < 2 * ntr; t += nt) a.trace[2 * (size_t)g * a.trace_stride + t] = ltr[t];
         if (tid == 0) {
@@ -1198,36 +1223,39 @@ __global__ void __launch_bounds__(512) k_dataflow(TriArgs a)
     }
 }
 
-template <typename T, bool UNIT, bool TAIL, bool R1>
+template <typename T, bool UNIT, bool TAIL, bool R1, bool TRACE>
 OwnerKernel dataflow_kernel_w(int w)
 {
     switch (w) {
-    case 1: return k_dataflow<T, 1, UNIT, TAIL, R1>;
-    case 2: return k_dataflow<T, 2, UNIT, TAIL, R1>;
-    case 3: return k_dataflow<T, 3, UNIT, TAIL, R1>;
-    case 4: return k_dataflow<T, 4, UNIT, TAIL, R1>;
-    case 5: return k_dataflow<T, 5, UNIT, TAIL, R1>;
-    case 6: return k_dataflow<T, 6, UNIT, TAIL, R1>;
-    case 7: return k_dataflow<T, 7, UNIT, TAIL, R1>;
-    case 8: return k_dataflow<T, 8, UNIT, TAIL, R1>;
-    case 10: return k_dataflow<T, 10, UNIT, TAIL, R1>;
-    case 12: return k_dataflow<T, 12, UNIT, TAIL, R1>;
-    case 16: return k_dataflow<T, 16, UNIT, TAIL, R1>;
+    case 1: return k_dataflow<T, 1, UNIT, TAIL, R1, TRACE>;
+    case 2: return k_dataflow<T, 2, UNIT, TAIL, R1, TRACE>;
+    case 3: return k_dataflow<T, 3, UNIT, TAIL, R1, TRACE>;
+    case 4: return k_dataflow<T, 4, UNIT, TAIL, R1, TRACE>;
+    case 5: return k_dataflow<T, 5, UNIT, TAIL, R1, TRACE>;
+    case 6: return k_dataflow<T, 6, UNIT, TAIL, R1, TRACE>;
+    case 7: return k_dataflow<T, 7, UNIT, TAIL, R1, TRACE>;
+    case 8: return k_dataflow<T, 8, UNIT, TAIL, R1, TRACE>;
+    case 10: return k_dataflow<T, 10, UNIT, TAIL, R1, TRACE>;
+    case 12: return k_dataflow<T, 12, UNIT, TAIL, R1, TRACE>;
+    case 16: return k_dataflow<T, 16, UNIT, TAIL, R1, TRACE>;
     default: return nullptr;
     }
 }
 
-template <typename T, bool R1>
+template <typename T, bool R1, bool TRACE>
 OwnerKernel dataflow_kernel_r(int w, bool unit, bool tail)
 {
-    if (unit) return tail ? dataflow_kernel_w<T, true, true, R1>(w) : dataflow_kernel_w<T, true, false, R1>(w);
-    return tail ? dataflow_kernel_w<T, false, true, R1>(w) : dataflow_kernel_w<T, false, false, R1>(w);
+    if (unit)
+        return tail ? dataflow_kernel_w<T, true, true, R1, TRACE>(w) : dataflow_kernel_w<T, true, false, R1, TRACE>(w);
+    return tail ? dataflow_kernel_w<T, false, true, R1, TRACE>(w) : dataflow_kernel_w<T, false, false, R1, TRACE>(w);
 }
 
 template <typename T>
-OwnerKernel dataflow_kernel(int w, bool unit, bool tail, int R)
+OwnerKernel dataflow_kernel(int w, bool unit, bool tail, int R, bool trace)
 {
-    return R == 1 ? dataflow_kernel_r<T, true>(w, unit, tail) : dataflow_kernel_r<T, false>(w, unit, tail);
+    if (trace)
+        return R == 1 ? dataflow_kernel_r<T, true, true>(w, unit, tail) : dataflow_kernel_r<T, false, true>(w, unit, tail);
+    return R == 1 ? dataflow_kernel_r<T, true, false>(w, unit, tail) : dataflow_kernel_r<T, false, false>(w, unit, tail);
 }
 
 template <typename T>
@@ -1472,7 +1500,7 @@ void launch_typed(DevTri &d, TriArgs a, hipStream_t st)
     }
     if (d.dataflow) {
         // the plan's columns name group-local imports: only this kernel reads them
-        OwnerKernel k = dataflow_kernel<T>(d.w, d.unit, d.has_tail, a.R);
+        OwnerKernel k = dataflow_kernel<T>(d.w, d.unit, d.has_tail, a.R, a.trace != nullptr);
         if (!k) fail(HEC_ERR_INVALID_ARG, "internal: dataflow plan with an unsupported ELL width");
         if ((int64_t)d.df_step_rows * a.R > 64)
             fail(HEC_ERR_INVALID_ARG, "dataflow plan: nrhs exceeds the plan's max_nrhs (steps are sized for it)");
