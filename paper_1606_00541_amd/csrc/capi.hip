@@ -442,6 +442,38 @@ void build_refactor(ilu_s &f, const int32_t *rowptr, const int32_t *col)
             u_diag.push_back(fdpos[i]);
         }
     }
+    // sources of the row-per-lane elimination, in the order the host
+    // factorization uses them: pivots ascending, each pivot's diagonal, then
+    // the pivot row's later entries that the row holds
+    std::vector<int32_t> sptr((size_t)n + 1, 0), spos, sdst;
+    int32_t maxsrc = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const int32_t b = frp[i], e = frp[i + 1];
+        for (int32_t p = b; p < fdpos[i]; ++p) {
+            const int32_t k = fci[p], pk = fdpos[k];
+            spos.push_back(pk);
+            sdst.push_back(-1);
+            for (int32_t pp = pk + 1; pp < frp[k + 1]; ++pp) {
+                auto it = std::lower_bound(fci.begin() + p + 1, fci.begin() + e, fci[pp]);
+                if (it != fci.begin() + e && *it == fci[pp]) {
+                    spos.push_back(pp);
+                    sdst.push_back((int32_t)(it - fci.begin()) - b);
+                }
+            }
+        }
+        sptr[i + 1] = (int32_t)spos.size();
+        maxsrc = std::max(maxsrc, sptr[i + 1] - sptr[i]);
+    }
+    r->flow_row = maxrow <= 8 && maxsrc <= 16 ? 8 : (maxrow <= 16 && maxsrc <= 32 ? 16 : 0);
+    if (r->flow_row > 0) {
+        if (spos.empty()) {
+            spos.assign(1, 0);
+            sdst.assign(1, 0);
+        }
+        upload(r->sptr, sptr);
+        upload(r->spos, spos);
+        upload(r->sdst, sdst);
+    }
     const Levels &lv = f.L.h.lev;
     r->max_row = std::max(1, maxrow);
     r->levelptr = lv.levelptr;

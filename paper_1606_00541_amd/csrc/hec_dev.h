@@ -173,6 +173,14 @@ struct DevRefactor {
     DevMem a2f, frp, fci, fdpos, fval, rows, err;
     DevMem fwork;                         // elimination target; swapped with fval on success
     DevMem l_src, l_dst, u_src, u_dst, u_diag, d_src;
+    // row-per-lane elimination in one launch (0: rows too long, one launch
+    // per level instead): the rows' longest length it is built for, and per
+    // row (original index) the factor positions it reads from its pivot
+    // rows in pivot order, each pivot's diagonal followed by the entries
+    // that update the row (sdst: -1 for a pivot, else the updated entry's
+    // index in the row)
+    int32_t flow_row = 0;
+    DevMem sptr, spos, sdst, fflow;
 };
 // Scatter A's device values into F and eliminate level by level; synchronizes
 // `st` and throws ZERO_PIVOT on a zero or non-finite pivot.  The elimination

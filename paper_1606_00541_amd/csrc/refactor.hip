@@ -5,7 +5,9 @@
 // is fixed at setup; new values of A are scattered into it (zero at fill
 // positions) and eliminated row by row.  Row i needs the finished rows k < i
 // with f_ik stored, which are exactly its dependencies in L, so the rows of
-// one level of L are independent and each level is one launch.  Inside a row
+// one level of L are independent.  Short rows are eliminated in one launch,
+// a lane per row waiting on the rows it needs (k_ilu_flow); longer ones take
+// one launch per level (k_ilu_row).  Inside a row
 // the pivots are taken in ascending order, l_ik = f_ik / u_kk and then
 // f_ij -= l_ik u_kj for every j > k of row k that row i holds, with separate
 // roundings (no fused multiply-add), so the factors equal the host
@@ -14,6 +16,7 @@
 // U's scaled by the reciprocal diagonal, which itself fills U's diagonal array.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <utility>
 
 #include "hec_dev.h"
@@ -111,6 +114,102 @@ __global__ void __launch_bounds__(kRowThreads) k_ilu_row(const int32_t *rows, in
     }
 }
 
+// The elimination in one launch, one lane per row.  Rows in level order are
+// cut into chunks of 64, dealt round-robin to the wavefronts of a
+// cooperative launch (every wavefront is resident).  A lane copies its row
+// of A (zero at fill positions) into LDS, reads the entries of its pivot
+// rows it needs from the output, which starts as the sentinel and receives
+// every row's final values, re-reading until none holds the sentinel (they
+// come from earlier chunks, held by running wavefronts, so the solve always
+// progresses), then eliminates in the host factorization's order with
+// separate roundings and writes its row.  A copied entry whose bits equal the
+// sentinel is written as the canonical quiet NaN, so no value can look
+// unwritten.  err: 1 for a zero or non-finite pivot, 2 when a wait gave up
+// after `spin` polls (every wavefront then stops).
+__device__ __forceinline__ bool rf_unset(double v) { return __double_as_longlong(v) == (long long)kSentinel64; }
+
+__global__ void __launch_bounds__(256) k_fill_unset(double *p, long n)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = __longlong_as_double((long long)kSentinel64);
+}
+
+template <int MAXR, int MAXS>
+__global__ void __launch_bounds__(64) k_ilu_flow(const int32_t *rows, int n, const int32_t *rp, const int32_t *dpos,
+                                                 const int32_t *sptr, const int32_t *spos, const int32_t *sdst,
+                                                 const double *init, double *f, int *err, unsigned spin)
+{
+#pragma clang fp contract(off)
+    __shared__ double buf[MAXR][64];
+    const int lane = threadIdx.x;
+    const long nch = ((long)n + 63) / 64;
+    for (long ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+        const long t = ch * 64 + lane;
+        const bool live = t < n;
+        const int i = live ? rows[t] : 0;
+        const int b = live ? rp[i] : 0, len = live ? rp[i + 1] - b : 0, d = live ? dpos[i] - b : 0;
+        const int s0 = live ? sptr[i] : 0, ns = live ? sptr[i + 1] - s0 : 0;
+        int pos[MAXS], dq[MAXS];
+#pragma unroll
+        for (int s = 0; s < MAXS; ++s) {
+            pos[s] = s < ns ? spos[s0 + s] : 0;
+            dq[s] = s < ns ? sdst[s0 + s] : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < MAXR; ++q)
+            if (q < len) {
+                const double v = init[b + q];
+                buf[q][lane] = rf_unset(v) ? __builtin_nan("") : v;
+            }
+        double v[MAXS];
+        unsigned long long need = ns >= 64 ? ~0ull : ((1ull << ns) - 1ull);
+        bool todo = live;
+        unsigned spins = 0;
+        // a lane finishes its row inside the loop as soon as its own inputs
+        // are there, so a wavefront never waits on one of its own lanes (a
+        // chunk can hold the end of one level and the start of the next)
+        while (__ballot(todo) != 0) {
+            if (todo) {
+#pragma unroll
+                for (int s = 0; s < MAXS; ++s)
+                    if ((need >> s) & 1ull) {
+                        const double x = __hip_atomic_load(f + pos[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if (!rf_unset(x)) {
+                            v[s] = x;
+                            need &= ~(1ull << s);
+                        }
+                    }
+                if (need == 0ull) {
+                    int piv = -1;
+                    double lik = 0.0;
+#pragma unroll
+                    for (int s = 0; s < MAXS; ++s)
+                        if (s < ns) {
+                            if (dq[s] < 0) {
+                                ++piv;
+                                lik = buf[piv][lane] / v[s];
+                                buf[piv][lane] = lik;
+                            } else {
+                                buf[dq[s]][lane] = buf[dq[s]][lane] - lik * v[s];
+                            }
+                        }
+#pragma unroll
+                    for (int q = 0; q < MAXR; ++q)
+                        if (q < len)
+                            __hip_atomic_store(f + b + q, buf[q][lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const double dd = buf[d][lane];
+                    if (dd == 0.0 || !isfinite(dd)) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    todo = false;
+                }
+            }
+            if (__ballot(todo) != 0 && (++spins & 255u) == 0) {
+                if (spins > spin) __hip_atomic_store(err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 2) return;
+            }
+        }
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_refill_l(const double *f, const int32_t *src, const int32_t *dst, long cnt,
                                                   T *ell, T *tail)
@@ -169,9 +268,30 @@ void refill_typed(const DevRefactor &r, DevTri &L, DevTri &U, hipStream_t st)
 
 }  // namespace
 
+template <int MAXR, int MAXS>
+void launch_flow(DevRefactor &r, const double *init, double *f, int *err, hipStream_t st)
+{
+    const void *kern = (const void *)k_ilu_flow<MAXR, MAXS>;
+    int per_cu = 0;
+    hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, 0), "occupancy query");
+    // at most half the co-resident wavefronts (the cooperative launch refuses
+    // more than can be resident), and no more than there are chunks
+    const long chunks = ((long)r.n + 63) / 64;
+    const int grid = (int)std::max<long>(1, std::min<long>(chunks, std::max(1, per_cu * device_cus() / 2)));
+    const int32_t *rows = r.rows.as<int32_t>(), *rp = r.frp.as<int32_t>(), *dpos = r.fdpos.as<int32_t>();
+    const int32_t *sp = r.sptr.as<int32_t>(), *so = r.spos.as<int32_t>(), *sd = r.sdst.as<int32_t>();
+    int n = r.n;
+    unsigned spin = kDefaultSpin;
+    void *args[] = {(void *)&rows, (void *)&n, (void *)&rp, (void *)&dpos, (void *)&sp, (void *)&so, (void *)&sd,
+                    (void *)&init, (void *)&f, (void *)&err, (void *)&spin};
+    hip_check(hipLaunchCooperativeKernel(kern, dim3(grid), dim3(64), args, 0, st), "refactor cooperative launch");
+}
+
 void refactor_numeric(DevRefactor &r, const double *aval, hipStream_t st)
 {
     if (r.fwork.bytes < r.fval.bytes) r.fwork.alloc(r.fval.bytes);
+    const bool flow = r.flow_row > 0 && r.n > 0;
+    if (flow && r.fflow.bytes < r.fval.bytes) r.fflow.alloc(r.fval.bytes);
     double *f = r.fwork.as<double>();
     int *err = r.err.as<int>();
     if (r.nnz_f > 0)
@@ -180,20 +300,33 @@ void refactor_numeric(DevRefactor &r, const double *aval, hipStream_t st)
     if (r.nnz_a > 0)
         hipLaunchKernelGGL(k_scatter_a, dim3(grid_for(r.nnz_a)), dim3(256), 0, st, aval, r.a2f.as<int32_t>(),
                            (long)r.nnz_a, f);
-    const int32_t *rows = r.rows.as<int32_t>();
-    for (size_t k = 0; k + 1 < r.levelptr.size(); ++k) {
-        const int nr = r.levelptr[k + 1] - r.levelptr[k];
-        if (nr == 0) continue;
-        hipLaunchKernelGGL(k_ilu_row, dim3(nr), dim3(kRowThreads), ilu_row_lds(r.max_row), st, rows + r.levelptr[k],
-                           nr, r.frp.as<int32_t>(), r.fci.as<int32_t>(), r.fdpos.as<int32_t>(), f, err, r.max_row);
+    DevMem *out = &r.fwork;
+    if (flow) {
+        // one launch: rows read the finished rows they need from fflow
+        double *g = r.fflow.as<double>();
+        if (r.nnz_f > 0)
+            hipLaunchKernelGGL(k_fill_unset, dim3(grid_for(r.nnz_f)), dim3(256), 0, st, g, (long)r.nnz_f);
+        if (r.flow_row == 8) launch_flow<8, 16>(r, f, g, err, st);
+        else launch_flow<16, 32>(r, f, g, err, st);
+        out = &r.fflow;
+    } else {
+        const int32_t *rows = r.rows.as<int32_t>();
+        for (size_t k = 0; k + 1 < r.levelptr.size(); ++k) {
+            const int nr = r.levelptr[k + 1] - r.levelptr[k];
+            if (nr == 0) continue;
+            hipLaunchKernelGGL(k_ilu_row, dim3(nr), dim3(kRowThreads), ilu_row_lds(r.max_row), st,
+                               rows + r.levelptr[k], nr, r.frp.as<int32_t>(), r.fci.as<int32_t>(),
+                               r.fdpos.as<int32_t>(), f, err, r.max_row);
+        }
     }
     hip_check(hipGetLastError(), "refactor launch");
     int flag = 0;
     hip_check(hipMemcpyAsync(&flag, err, sizeof(int), hipMemcpyDeviceToHost, st), "refactor flag copy");
     hip_check(hipStreamSynchronize(st), "refactor synchronize");
+    if (flag == 2) fail(HEC_ERR_TIMEOUT, "the device refactorization gave up waiting for a pivot row");
     if (flag) fail(HEC_ERR_ZERO_PIVOT, "zero or non-finite pivot in the device refactorization");
-    std::swap(r.fval.p, r.fwork.p);
-    std::swap(r.fval.bytes, r.fwork.bytes);
+    std::swap(r.fval.p, out->p);
+    std::swap(r.fval.bytes, out->bytes);
 }
 
 void gather_f64(const double *src, const int32_t *idx, int64_t cnt, double *dst, hipStream_t st)
