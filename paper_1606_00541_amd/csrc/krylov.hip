@@ -364,7 +364,10 @@ __global__ void __launch_bounds__(64) k_dcgs_step(int j, int m, int P, int fin, 
     const double cc = red[(fin ? nq : 2 * nq) * P + c];
     const double bprev = sc[2 * P + c];
     double alpha = 1.0;
-    if (lane == 0) s_stop = 0;
+    if (lane == 0) {
+        s_stop = 0;
+        if (!fin) applies[c] += 1;  // M was applied to this step's candidate
+    }
     if (j >= 1) {
         alpha = sqrt(fmax(0.0, cc - ss));
         if (lane < nq) sh[lane] = tp + bprev * s;
@@ -411,7 +414,6 @@ __global__ void __launch_bounds__(64) k_dcgs_step(int j, int m, int P, int fin, 
     if (lane < nq) tprev[lane * P + c] = t;
     if (lane == 0) {
         tprev[nq * P + c] = tau;
-        applies[c] += 1;
         if (!isfinite(tau) || !isfinite(beta)) {
             status[c] = HEC_ERR_BREAKDOWN;
             act[c] = 0;
