@@ -388,10 +388,12 @@ def _cfg5(H, torch, np, synth, args):
     Aop = H.hec_from_csr(A)
     res = {}
     z32 = None
+    tuned = None
     for fdt in ("f64", "f32"):
         _log("config 5: batch ILU(1) setup, %s factors" % fdt)
         t0 = time.time()
-        f = H.batch_setup(A, sys_ptr, "iluk", k=1, factor_dtype=fdt, tune=_tune(H, args, max_nrhs=R))
+        tune = _tune(H, args, max_nrhs=R) if tuned is None else tuned
+        f = H.batch_setup(A, sys_ptr, "iluk", k=1, factor_dtype=fdt, tune=tune)
         setup = time.time() - t0
         pl, pu = H.ilu_plans(f)
         stl, stu = H.tri_plan_stats(pl), H.tri_plan_stats(pu)
@@ -414,9 +416,27 @@ def _cfg5(H, torch, np, synth, args):
             _, kr = _krylov_batch(H, torch, f, Aop, sys_ptr, b, "fgmres")
             row["fgmres"] = kr
             row["systems_per_s"] = round(len(mats) * R / kr["seconds"], 3)
+        if fdt == "f32" and tuned is not None:
+            row["autotune"] = tune_info
         res[fdt] = row
         if fdt == "f32":
             z32 = z.cpu().numpy()
+        if fdt == "f64" and not args.no_autotune:
+            # the FP32 plans take the tuner's choice for this batch (kernel,
+            # wavefronts, parts, ELL width), searched on L's pattern within a
+            # time budget; results are cached by a signature of the problem
+            import tempfile
+
+            _log("config 5: autotuning the FP32 triangular plans")
+            Lf = synth.CSR(n, *H.ilu_factor(f, 0))
+            t0 = time.time()
+            tuned, us = H.tri_autotune(Lf, "lower", unit_diag=True, dtype="f32", nrhs=R, sys_ptr=sys_ptr,
+                                       cache=os.path.join(tempfile.gettempdir(), "hec_tune_cache.jsonl"),
+                                       max_seconds=40.0)
+            tune_info = {"seconds": round(time.time() - t0, 2), "best_L_solve_us": round(us, 1),
+                         "schedule": int(tuned.schedule), "kernel_variant": int(tuned.kernel_variant),
+                         "block_threads": int(tuned.block_threads), "ell_width": int(tuned.ell_width),
+                         "part_rows": int(tuned.part_rows), "partition": int(tuned.partition)}
     out = {"workload": "256 independent systems (log-uniform 1e3..2e5 rows, 2D/3D lognormal sigma=1, n=%d), ILU(1), "
                        "8 RHS each; batched FGMRES(30), each (system, rhs) to 1e-10" % n,
            "systems": len(mats), "fp64": res["f64"], "fp32_refined": res["f32"]}
@@ -610,6 +630,7 @@ def main(argv=None):
                     help="hec_tune_t.kernel_variant (0 = auto: the dataflow kernel when it fits)")
     ap.add_argument("--block-threads", type=int, default=0, help="hec_tune_t.block_threads (0 = default)")
     ap.add_argument("--no-krylov", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="config 5: default tuning instead of the autotuner")
     ap.add_argument("--timed-loop-only", action="store_true",
                     help="skip the device refactorization and the per-application (warm/cold) timings, so a "
                          "profiler sees only the warmup and timed applications")

@@ -1231,7 +1231,12 @@ hec_status_t tri_autotune(int32_t n, const int32_t *rowptr, const int32_t *col, 
         Tune base = default_tune();
         base.max_nrhs = nrhs;
         cands.push_back(base);
-        if (nrhs <= 64) {
+        // one part per workgroup holds about n / CUs rows of solution and
+        // right-hand side in LDS: skip those candidates when that cannot fit
+        const size_t part_lds = 2 * (size_t)((n + device_cus() - 1) / std::max(1, device_cus())) * (size_t)nrhs *
+                                (dt == HEC_F64 ? 8 : 4);
+        const bool parts_fit = part_lds <= (size_t)device_max_lds();
+        if (nrhs <= 64 && parts_fit) {
             for (int32_t blk : {256, 128, 384})
                 for (int32_t part : {0, 1, 2}) {
                     Tune t = base;
@@ -1242,6 +1247,8 @@ hec_status_t tri_autotune(int32_t n, const int32_t *rowptr, const int32_t *col, 
                     t.partition = part;
                     cands.push_back(t);
                 }
+        }
+        if (nrhs <= 64) {
             for (int32_t blk : {256, 384})
                 for (int32_t rows : {0, 1024, 4096}) {
                     Tune t = base;
@@ -1252,7 +1259,7 @@ hec_status_t tri_autotune(int32_t n, const int32_t *rowptr, const int32_t *col, 
                     t.part_rows = rows;
                     cands.push_back(t);
                 }
-            if (wmax > w0 && wmax <= 16) {
+            if (wmax > w0 && wmax <= 16 && parts_fit) {
                 Tune t = base;
                 t.schedule = HEC_SCHED_OWNER_PERSISTENT;
                 t.variant = 4;
