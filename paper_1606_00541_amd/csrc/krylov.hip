@@ -43,9 +43,11 @@ __global__ void __launch_bounds__(256) k_spmv(int n, int w, int ld, const int32_
     if (t >= (long)n * R) return;
     const int i = (int)(t / R), k = (int)(t - (long)i * R);
     double s = 0.0;
+    // the matrix streams through non-temporally: inside a Krylov solve the
+    // preconditioner's factors are the data worth keeping in the caches
     for (int e = 0; e < w; ++e) {
-        const int c = ell_col[(size_t)e * ld + i];
-        if (c < n) s += (double)ell_val[(size_t)e * ld + i] * x[(size_t)c * R + k];
+        const int c = __builtin_nontemporal_load(ell_col + (size_t)e * ld + i);
+        if (c < n) s += (double)__builtin_nontemporal_load(ell_val + (size_t)e * ld + i) * x[(size_t)c * R + k];
     }
     if (tail_ptr)
         for (int p = tail_ptr[i]; p < tail_ptr[i + 1]; ++p) s += (double)tail_val[p] * x[(size_t)tail_col[p] * R + k];
