@@ -1293,7 +1293,10 @@ OwnerKernel split_kernel(int w, bool unit, size_t &lds, int rows, int CH)
 // solve_item does and publishes its value with an agent-scope store.  Lanes
 // whose inputs are ready finish inside the wait loop, so a wavefront never
 // waits on one of its own lanes.
-template <typename T, typename TIn, typename TOut>
+// MAXW > 0: rows of at most MAXW ELL slots keep their columns and values in
+// registers, loaded once, and every poll issues all input loads together (one
+// memory round trip per poll); MAXW = 0: any width, columns re-read per poll.
+template <typename T, typename TIn, typename TOut, int MAXW>
 __global__ void __launch_bounds__(256) k_syncfree(TriArgs a, int waves)
 {
     const int lane = threadIdx.x & 63;
@@ -1302,6 +1305,7 @@ __global__ void __launch_bounds__(256) k_syncfree(TriArgs a, int waves)
     const long nch = (items + 63) >> 6;
     const T *ev = static_cast<const T *>(a.ell_val);
     T *xw = static_cast<T *>(a.xw);
+    constexpr int NW = MAXW > 0 ? MAXW : 1;
     for (long ch = wave; ch < nch; ch += waves) {
         const long t = (ch << 6) + lane;
         bool todo = t < items;
@@ -1314,18 +1318,44 @@ __global__ void __launch_bounds__(256) k_syncfree(TriArgs a, int waves)
             b = canon(static_cast<T>(static_cast<const TIn *>(a.bin)[(size_t)a.gather[x] * a.R + k]));
             if (a.dinv) b = scale_rhs(b, static_cast<const T *>(a.dinv)[x]);
         }
+        int cr[NW];
+        T vr[NW];
+        if (MAXW > 0) {
+#pragma unroll
+            for (int e = 0; e < NW; ++e) {
+                cr[e] = e < a.w ? a.ell_col[(size_t)e * a.ld + x] : a.n;
+                vr[e] = e < a.w ? ev[(size_t)e * a.ld + x] : T(0);
+            }
+        }
         unsigned spins = 0;
         while (__ballot(todo)) {
             if (todo) {
                 T s = b;
                 bool ready = true;
-                for (int e = 0; e < a.w && ready; ++e) {
-                    const int c = a.ell_col[(size_t)e * a.ld + x];
-                    if (c != a.n) {
-                        const T v = __hip_atomic_load(xw + (size_t)c * a.R + k, __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT);
-                        if (is_sentinel(v)) ready = false;
-                        else s -= ev[(size_t)e * a.ld + x] * v;
+                if (MAXW > 0) {
+                    T dv[NW];
+#pragma unroll
+                    for (int e = 0; e < NW; ++e)
+                        dv[e] = cr[e] != a.n ? __hip_atomic_load(xw + (size_t)cr[e] * a.R + k, __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_AGENT)
+                                             : T(0);
+#pragma unroll
+                    for (int e = 0; e < NW; ++e)
+                        if (cr[e] != a.n && is_sentinel(dv[e])) ready = false;
+                    if (ready) {
+#pragma unroll
+                        for (int e = 0; e < NW; ++e)
+                            if (cr[e] != a.n) s -= vr[e] * dv[e];
+                    }
+                } else {
+                    for (int e = 0; e < a.w && ready; ++e) {
+                        const int c = a.ell_col[(size_t)e * a.ld + x];
+                        if (c != a.n) {
+                            const T v = __hip_atomic_load(xw + (size_t)c * a.R + k, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
+                            if (is_sentinel(v)) ready = false;
+                            else s -= ev[(size_t)e * a.ld + x] * v;
+                        }
                     }
                 }
                 if (ready && a.tail_ptr) {
@@ -1463,15 +1493,16 @@ void launch_typed(DevTri &d, TriArgs a, hipStream_t st)
         // cooperative launch guarantees co-residency (it costs tens of
         // microseconds, small beside this kernel's milliseconds)
         const long chunks = ((long)d.n * a.R + 63) / 64;
-        const int cap = capacity_of((const void *)k_syncfree<T, TIn, TOut>, 256, 0);
+        // rows of at most 8 (or 16) ELL slots keep them in registers
+        const void *kern = d.w <= 8 ? (const void *)k_syncfree<T, TIn, TOut, 8>
+                         : (d.w <= 16 ? (const void *)k_syncfree<T, TIn, TOut, 16> : (const void *)k_syncfree<T, TIn, TOut, 0>);
+        const int cap = capacity_of(kern, 256, 0);
         const long per_level = chunks / std::max(1, d.nlev);
         const long lim = std::min<long>(std::max(1, cap / 2), std::max<long>(2L * device_cus(), per_level / 4));
         const int grid = (int)std::max<long>(1, std::min<long>(lim, (chunks + 3) / 4));
         int waves = grid * 4;
         void *args[] = {(void *)&a, (void *)&waves};
-        hip_check(hipLaunchCooperativeKernel((const void *)k_syncfree<T, TIn, TOut>, dim3(grid), dim3(256), args, 0,
-                                             st),
-                  "k_syncfree cooperative launch");
+        hip_check(hipLaunchCooperativeKernel(kern, dim3(grid), dim3(256), args, 0, st), "k_syncfree cooperative launch");
         return;
     }
     if (d.sysq) {
