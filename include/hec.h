@@ -130,9 +130,9 @@ typedef struct hec_tune {
                                an LDS ring (no co-residency needed; block_threads sets the
                                workgroup).
                                Schedule AUTO picks the dataflow kernel when its LDS holds
-                               every part, else 5 when the levels are narrow (fewer than 2^17
-                               (row, rhs) items per level on average), else one launch per
-                               level */
+                               every part, else 5 unless the levels are very wide (2^20
+                               (row, rhs) items per level on average or more), else one
+                               launch per level */
 } hec_tune_t;
 
 /* Per-RHS outcome of krylov_solve. */

@@ -1210,12 +1210,13 @@ TriHost analyze(const Csr &a, bool upper, bool unit, hec_dtype_t dt, const Tune 
             }
         }
         if (auto_sched) {
-            // too large for LDS: the barrier-free kernel when levels are
-            // narrow (its per-level cost is one memory round trip), one
-            // launch per level when they are wide (cached gathers)
+            // too large for LDS: the barrier-free kernel (its per-level cost
+            // is one memory round trip; measured faster than one launch per
+            // level up to 256k (row, rhs) items per level), one launch per
+            // level only when levels average above 2^20 items
             tu.schedule = HEC_SCHED_LEVEL_LAUNCH;
             const double items = (double)a.n * std::max(1, tu.max_nrhs);
-            if (items < (double)(1 << 17) * std::max(1, t.lev.nlev)) t.variant = tu.variant = 5;
+            if (items < (double)(1 << 20) * std::max(1, t.lev.nlev)) t.variant = tu.variant = 5;
         } else {
             tu.variant = 2;
         }

@@ -269,8 +269,8 @@ def test_auto_tuning_picks_the_dataflow_kernel_when_it_fits():
     L, _ = oracle.ilu0(A)
     st = H.tri_plan_stats(H.tri_analyze(L, unit_diag=True, tune=H.tune_default(host_only=1, num_groups=1)))
     assert st["schedule"] == 1 and st["dataflow"] == 0 and st["syncfree"] == 1
-    # ... and by one launch per level when they are wide (2^17 items and more)
-    n = (1 << 17) + 64
+    # ... and by one launch per level when they are wide (2^20 items and more)
+    n = (1 << 20) + 64
     D = CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.full(n, 2.0))
     st = H.tri_plan_stats(H.tri_analyze(D, tune=H.tune_default(host_only=1, num_groups=1)))
     assert st["schedule"] == 1 and st["nlev"] == 1 and st["syncfree"] == 0

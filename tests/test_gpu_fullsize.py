@@ -105,10 +105,11 @@ def config4():
     return A, owner, doms, r, ref
 
 
-@pytest.mark.parametrize("kernel", ["auto", "syncfree"])
+@pytest.mark.parametrize("kernel", ["auto", "syncfree", "level_launch"])
 def test_config4_ras64_16rhs_fp32_full_size(config4, kernel):
     A, owner, doms, r, ref = config4
-    kw = {"schedule": "level_launch", "kernel_variant": 5} if kernel == "syncfree" else {}
+    kw = {"syncfree": {"schedule": "level_launch", "kernel_variant": 5},
+          "level_launch": {"schedule": "level_launch"}}.get(kernel, {})
     s = H.ras_setup(A, 64, owner, overlap=1, factor_dtype="f32", tune=H.tune_default(max_nrhs=16, **kw))
     assert list(H.ras_info(s)[2]) == [len(d.ext) for d in doms]
     z = apply(s, r, ras=True)
