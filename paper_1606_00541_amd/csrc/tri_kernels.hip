@@ -1339,6 +1339,7 @@ __global__ void __launch_bounds__(256) k_syncfree(TriArgs a, int waves)
                         dv[e] = cr[e] != a.n ? __hip_atomic_load(xw + (size_t)cr[e] * a.R + k, __ATOMIC_RELAXED,
                                                                  __HIP_MEMORY_SCOPE_AGENT)
                                              : T(0);
+                    __builtin_amdgcn_sched_barrier(0);  // all loads out before the first test
 #pragma unroll
                     for (int e = 0; e < NW; ++e)
                         if (cr[e] != a.n && is_sentinel(dv[e])) ready = false;
