@@ -233,15 +233,15 @@ constexpr int kGsMaxR = 16;
 // s_i and c.c (w null), per block into partial[blk][np][R]: slot i for s_i,
 // nq + i for t_i, then 2nq, 2nq+1, 2nq+2 (np = 2nq + 3); without w slot nq
 // holds c.c (np = nq + 1).  Blocks as in k_dot_partial; R a power of two up
-// to kGsMaxR.  Wavefront q of the block takes the basis vectors q, q+4, ...
-// over all of the block's rows (each basis element is read once) and every
-// wavefront reads c and w; each product is summed by one wavefront only, so
-// no cross-wavefront step is needed (deterministic).  A thread loads U rows
+// to kGsMaxR.  Wavefront q of the block's WV takes the basis vectors q,
+// q+WV, ... over all of the block's rows (each basis element is read once) and
+// every wavefront reads c and w; each product is summed by one wavefront only,
+// so no cross-wavefront step is needed (deterministic).  A thread loads U rows
 // before it computes on them.
-template <int U, bool R1>
-__global__ void __launch_bounds__(256) k_dcgs_dots(const double *Q, long stride, int nq, const double *cv,
-                                                  const double *w, int R_, int P, const int32_t *brow,
-                                                  const int32_t *bsys, const int8_t *act, double *partial)
+template <int U, bool R1, int WV>
+__global__ void __launch_bounds__(WV * 64) k_dcgs_dots(const double *Q, long stride, int nq, const double *cv,
+                                                      const double *w, int R_, int P, const int32_t *brow,
+                                                      const int32_t *bsys, const int8_t *act, double *partial)
 {
     constexpr int NQ = 16 / U;  // basis vectors per wavefront
     const int R = R1 ? 1 : R_;
@@ -251,8 +251,8 @@ __global__ void __launch_bounds__(256) k_dcgs_dots(const double *Q, long stride,
     const long row0 = brow[2 * blockIdx.x], row1 = brow[2 * blockIdx.x + 1];
     const bool live = act == nullptr || act[c];
     const bool hw = w != nullptr;
-    const int mine = nq > wave ? (nq - wave + 3) / 4 : 0;
-    double as[NQ], at[NQ], sc = 0.0;
+    const int mine = nq > wave ? (nq - wave + WV - 1) / WV : 0;
+    double as[NQ], at[NQ], s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) as[q] = at[q] = 0.0;
     if (live) {
@@ -265,7 +265,7 @@ __global__ void __launch_bounds__(256) k_dcgs_dots(const double *Q, long stride,
                 const long t = ru * R + k;
 #pragma unroll
                 for (int q = 0; q < NQ; ++q)
-                    if (q < mine) vq[u][q] = __builtin_nontemporal_load(Q + (wave + 4 * q) * stride + t);
+                    if (q < mine) vq[u][q] = __builtin_nontemporal_load(Q + (wave + WV * q) * stride + t);
                 cu[u] = cv[t];
                 wu[u] = hw ? w[t] : 0.0;
             }
@@ -278,7 +278,9 @@ __global__ void __launch_bounds__(256) k_dcgs_dots(const double *Q, long stride,
                         as[q] += vq[u][q] * cu[u];
                         at[q] += vq[u][q] * wu[u];
                     }
-                sc += wave == 0 ? cu[u] * cu[u] : (wave == 1 ? cu[u] * wu[u] : wu[u] * wu[u]);
+                if (wave == 0) s0 += cu[u] * cu[u];
+                if (wave == 1 % WV) s1 += cu[u] * wu[u];
+                if (wave == 2 % WV) s2 += wu[u] * wu[u];
             }
         }
     }
@@ -293,14 +295,21 @@ __global__ void __launch_bounds__(256) k_dcgs_dots(const double *Q, long stride,
                 b += __shfl_xor(b, off);
             }
             if (lane < R) {
-                out[(wave + 4 * q) * R + lane] = a;
-                if (hw) out[(nq + wave + 4 * q) * R + lane] = b;
+                out[(wave + WV * q) * R + lane] = a;
+                if (hw) out[(nq + wave + WV * q) * R + lane] = b;
             }
         }
     }
-    if (wave < (hw ? 3 : 1)) {
-        for (int off = R; off < 64; off <<= 1) sc += __shfl_xor(sc, off);
-        if (lane < R) out[((hw ? 2 * nq : nq) + wave) * R + lane] = sc;
+    // c.c, c.w and w.w, each summed by one wavefront (wave j takes product
+    // j mod WV)
+    const int base = hw ? 2 * nq : nq;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        if (j > 0 && !hw) break;
+        if (wave != j % WV) continue;
+        double v = j == 0 ? s0 : (j == 1 ? s1 : s2);
+        for (int off = R; off < 64; off <<= 1) v += __shfl_xor(v, off);
+        if (lane < R) out[(base + j) * R + lane] = v;
     }
 }
 
@@ -667,16 +676,19 @@ struct Ctx {
         const dim3 g(nblk), b(256);
         const int32_t *br = browm.as<int32_t>(), *bs = bsysm.as<int32_t>();
         double *pt = partial.as<double>();
+        // two wavefronts per workgroup, each over half the basis (both read
+        // the candidate and the new vector; four wavefronts measured 1.6%
+        // slower for the whole solve)
 #define HEC_DCGS_DOTS(U, R1)                                                                                   \
-    hipLaunchKernelGGL((k_dcgs_dots<U, R1>), g, b, 0, st, Q, stride, nq, cv, w, R, P, br, bs, act, pt)
+    hipLaunchKernelGGL((k_dcgs_dots<U, R1, 2>), g, dim3(128), 0, st, Q, stride, nq, cv, w, R, P, br, bs, act, pt)
         if (R == 1) {
-            if (nq <= 8) HEC_DCGS_DOTS(8, true);
-            else if (nq <= 16) HEC_DCGS_DOTS(4, true);
-            else HEC_DCGS_DOTS(2, true);
+            if (nq <= 8) HEC_DCGS_DOTS(4, true);
+            else if (nq <= 16) HEC_DCGS_DOTS(2, true);
+            else HEC_DCGS_DOTS(1, true);
         } else {
-            if (nq <= 8) HEC_DCGS_DOTS(8, false);
-            else if (nq <= 16) HEC_DCGS_DOTS(4, false);
-            else HEC_DCGS_DOTS(2, false);
+            if (nq <= 8) HEC_DCGS_DOTS(4, false);
+            else if (nq <= 16) HEC_DCGS_DOTS(2, false);
+            else HEC_DCGS_DOTS(1, false);
         }
 #undef HEC_DCGS_DOTS
         hipLaunchKernelGGL(k_dot_final, dim3(np * P), dim3(256), 0, st, pt, bptrm.as<int32_t>(), np, R, P, out);
