@@ -466,10 +466,10 @@ void build_refactor(ilu_s &f, const int32_t *rowptr, const int32_t *col)
     }
     r->flow_row = maxrow <= 8 && maxsrc <= 16 ? 8 : (maxrow <= 16 && maxsrc <= 32 ? 16 : 0);
     if (r->flow_row > 0) {
-        if (spos.empty()) {
-            spos.assign(1, 0);
-            sdst.assign(1, 0);
-        }
+        // one padding entry: a row without sources starts at the lists' end,
+        // and the kernel's clamped (unconditional) loads read that position
+        spos.push_back(0);
+        sdst.push_back(0);
         upload(r->sptr, sptr);
         upload(r->spos, spos);
         upload(r->sdst, sdst);
