@@ -145,3 +145,28 @@ def test_ras_refactor_equals_new_setup(kind, overlap, fdt):
     H.ras_refactor(s, None, val=torch.from_numpy(A1.val.copy()).cuda())
     H.ras_refactor(s, None, val=torch.from_numpy(A2.val.copy()).cuda())
     assert np.array_equal(ras(s), ras(g))
+
+
+@pytest.mark.parametrize("tail", ["single_row", "diagonal"])
+def test_refactor_rows_without_sources(tail):
+    # rows with no pivots (a decoupled last row; a diagonal matrix, where no
+    # row has one) start their source lists at the lists' end
+    import scipy.sparse as sp
+
+    def build(scale, seed):
+        if tail == "diagonal":
+            d = 2.0 + np.random.default_rng(seed).random(97)
+            m = sp.diags(d * scale).tocsr()
+        else:
+            P = synth.poisson2d(7)
+            m = sp.block_diag([P.to_scipy() * scale, sp.csr_matrix(np.array([[3.0 * scale]]))]).tocsr()
+        m.sort_indices()
+        return CSR(m.shape[0], m.indptr.astype(np.int32), m.indices.astype(np.int32), m.data.astype(np.float64))
+
+    A1, A2 = build(1.0, 90), build(2.0, 91)
+    f = H.ilu_setup(A1, "ilu0")
+    g = H.ilu_setup(A2, "ilu0")
+    H.ilu_refactor(f, A2)
+    same_factors(factors(f), oracle.ilu0(A2))
+    r = synth.rhs(A2.n, 1, 92)
+    assert np.array_equal(apply(f, r), apply(g, r))
