@@ -817,6 +817,7 @@ void build_sysq(ExecHost &ex, const Levels &lv, const std::vector<int32_t> &sys,
         s.sq_ring[2 * k + 1] = W[k];
         lds_rows = std::max<int64_t>(lds_rows, (int64_t)slots * W[k] + 1);
     }
+    s.sq_keep.assign(n, 0);
     for (int32_t x = 0; x < n; ++x) {
         const int32_t k = sys_of[x];
         each_col(x, [&](int32_t &c) {
@@ -830,6 +831,7 @@ void build_sysq(ExecHost &ex, const Levels &lv, const std::vector<int32_t> &sys,
                 const int32_t l = lvp[k] + lev_of[c];
                 c = (lev_of[c] % (D[k] + 1)) * W[k] + (c - lvrow[l]);
             } else {
+                s.sq_keep[c] = 1;
                 c = -2 - c;
                 s.sq_global = true;
             }
@@ -1168,6 +1170,14 @@ TriHost analyze(const Csr &a, bool upper, bool unit, hec_dtype_t dt, const Tune 
             }
             w = dataflow_width(std::min(std::max(w, 1), 16));
         }
+        // The pipelined system queue holds a row's ELL slots in registers and
+        // reads no CSR tail: the automatic width covers the longest row when
+        // it has at most 8 off-diagonals.
+        if (u.variant == 7 && u.ell_width < 0) {
+            int32_t wmax = 0;
+            for (int32_t i = 0; i < a.n; ++i) wmax = std::max(wmax, offdiag_count(a, i));
+            if (wmax <= 8) w = std::max(w, std::max(wmax, 1));
+        }
         t.hec = build_hec(a, upper, unit, t.lev, w);
         build_exec(t, a, u, dev, sys_ptr);
     };
@@ -1208,6 +1218,21 @@ TriHost analyze(const Csr &a, bool upper, bool unit, hec_dtype_t dt, const Tune 
             } catch (const Error &e) {
                 if (e.code != HEC_ERR_CAPACITY) throw;
             }
+        }
+        // too large for LDS with enough independent systems to give every
+        // other compute unit one (a batch, RAS subdomains): the system
+        // queue, whose levels are separated by workgroup barriers with the
+        // last levels' values in LDS (256 systems of ILU(1), 8 RHS: 4.2 ms
+        // FP32 against 7.4 ms for the barrier-free kernel; 64 subdomains
+        // leave most of the GPU idle and stay on the barrier-free kernel)
+        const int32_t nsys = sys_ptr && sys_ptr->size() >= 2 ? (int32_t)sys_ptr->size() - 1 : 1;
+        if (auto_sched && nsys >= std::max(2, (dev.cus > 0 ? dev.cus : 256) / 2) && tu.max_nrhs <= 64) {
+            Tune q = tu;
+            q.schedule = HEC_SCHED_LEVEL_PERSISTENT;
+            q.variant = 7;
+            t.variant = 7;
+            attempt(q);
+            return t;
         }
         if (auto_sched) {
             // too large for LDS: the barrier-free kernel (its per-level cost

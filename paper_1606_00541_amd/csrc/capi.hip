@@ -145,9 +145,18 @@ void upload_tri(DevTri &d, const TriHost &t, int32_t max_nrhs)
             d.sysq = true;
             d.sq_global = s.sq_global;
             d.sq_lds_rows = s.sq_lds_rows;
+            d.sq_widths.clear();
+            for (size_t l = 0; l + 1 < s.sq_lvrow.size(); ++l) d.sq_widths.push_back(s.sq_lvrow[l + 1] - s.sq_lvrow[l]);
+            d.sq_median_rows = 0;
+            if (!d.sq_widths.empty()) {
+                std::vector<int32_t> w = d.sq_widths;
+                std::nth_element(w.begin(), w.begin() + w.size() / 2, w.end());
+                d.sq_median_rows = w[w.size() / 2];
+            }
             upload(d.sq_lvp, s.sq_lvp);
             upload(d.sq_lvrow, s.sq_lvrow);
             upload(d.sq_ring, s.sq_ring);
+            upload(d.sq_keep, s.sq_keep);
         }
     }
     // epoch, workgroups done, work counter (part queue / chunk batches)

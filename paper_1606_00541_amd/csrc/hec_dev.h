@@ -116,6 +116,7 @@ struct TriArgs {
     int32_t nparts;              // dataflow kernel: parts of the plan; system queue: systems
     int32_t queue;               // dataflow kernel: workgroups take parts from a counter (epoch[2])
     const int32_t *sq_lvp, *sq_lvrow, *sq_ring;  // system queue: levels per system, level rows, rings
+    const int8_t *sq_keep;                        // system queue: rows also stored to xw (read beyond a ring)
 };
 
 // Polls of a bounded device-side wait before it is declared hung (a plan may
@@ -145,7 +146,9 @@ struct DevTri {
     bool queue = false;            // dataflow parts taken from a counter (more parts than workgroups)
     bool sysq = false, sq_global = false;  // system queue kernel; some dependencies read from xw
     int32_t sq_lds_rows = 0;
-    DevMem sq_lvp, sq_lvrow, sq_ring;
+    std::vector<int32_t> sq_widths;  // rows of every level of every system
+    int32_t sq_median_rows = 0;      // their median
+    DevMem sq_lvp, sq_lvrow, sq_ring, sq_keep;
     int32_t chunk_rows = 0;
     bool max_lanes_one = true;     // every step runs one thread per (row, rhs)
     DevMem epoch, err, mbox;

@@ -103,6 +103,7 @@ struct Schedule {
     bool sq_global = false;          // some dependency is read from the global workspace
     int32_t sq_lds_rows = 0;         // largest ring plus the zero row, in rows
     std::vector<int32_t> sq_lvp, sq_lvrow, sq_ring;
+    std::vector<int8_t> sq_keep;     // rows read back from the global workspace
     int32_t nsteps() const { return (int32_t)step_lanes.size(); }
 };
 

@@ -27,6 +27,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
 
 #include "hec_dev.h"
 
@@ -1473,12 +1474,291 @@ __global__ void __launch_bounds__(1024) k_sysq(TriArgs a)
     }
 }
 
+// One item of the pipelined system queue: a row's G right-hand sides, with
+// the row's data loaded P levels before its level is solved and its
+// right-hand sides H levels before.
+template <typename T, typename TIn, int G, int MW> struct SqItem {
+    // integers, not bools: a bool becomes a lane mask as soon as it is
+    // formed, which would wait for the load it comes from
+    int ok;        // a real row of the level (else loads of a clamped row, unused)
+    int keep;      // also stored to xw (read beyond a ring)
+    int x, gi, dst;
+    int c[MW];
+    T v[MW];
+    T d;
+    TIn b[G];
+};
+
+// Row data of local row i of level lf (clamped into the system's levels and
+// into the level, so that every load stays inside the plan's arrays).
+template <typename T, typename TIn, int G, int MW>
+__device__ __forceinline__ void sq_rows(const TriArgs &a, const int32_t *__restrict__ lvrow,
+                                       SqItem<T, TIn, G, MW> &u, int lf, int l1, int i)
+{
+    const int lc = min(lf, l1 - 1);
+    const int rb = lvrow[lc], re = lvrow[lc + 1];
+    u.ok = lf < l1 && rb + i < re;
+    const int x = max(0, min(rb + i, re - 1));
+    u.x = x;
+    u.gi = a.gather[x];
+    const T *ev = static_cast<const T *>(a.ell_val);
+#pragma unroll
+    for (int e = 0; e < MW; ++e) {
+        const size_t o = (size_t)min(e, a.w - 1) * a.ld + x;
+        u.c[e] = a.ell_col[o];
+        u.v[e] = ev[o];
+    }
+    // unconditional loads (from a stand-in array when there is no diagonal
+    // or scatter), so that every set issues the same number of loads and
+    // the compiler's memory counters wait only for the set being solved
+    u.d = (a.dinv ? static_cast<const T *>(a.dinv) : ev)[x];
+    u.dst = (a.xout ? a.scatter : a.gather)[x];
+    u.keep = a.sq_keep[x];
+}
+
+template <typename T, typename TIn, int G, int MW>
+__device__ __forceinline__ void sq_rhs(const TriArgs &a, SqItem<T, TIn, G, MW> &u, int g0)
+{
+    const TIn *src = static_cast<const TIn *>(a.bin) + (size_t)u.gi * a.R + g0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) u.b[g] = src[g];
+}
+
+// The row's value for its G right-hand sides, computed as k_level does
+// (right-hand side, scaled by the reciprocal diagonal if any, then the ELL
+// slots in order; padding reads the ring's zero row, a dependency beyond the
+// ring the workspace, which this workgroup wrote before an earlier barrier).
+template <typename T, typename TIn, int G, int MW>
+__device__ __forceinline__ void sq_solve(const TriArgs &a, const SqItem<T, TIn, G, MW> &u, T *ring, int zrow,
+                                         int slots, int slotrow, int g0)
+{
+    if (!u.ok) return;
+    const int R = a.R;
+    T s[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        T sv = canon(static_cast<T>(u.b[g]));
+        if (a.dinv) sv = scale_rhs(sv, u.d);
+        s[g] = sv;
+    }
+    const int dst = a.xout ? u.dst : -1;
+#pragma unroll
+    for (int e = 0; e < MW; ++e) {
+        if (e < a.w) {
+            const int c = u.c[e];
+            const T v = u.v[e];
+            if (c >= 0) {
+                const T *dp = ring + (size_t)min(c, zrow) * R + g0;
+#pragma unroll
+                for (int g = 0; g < G; ++g) s[g] -= v * dp[g];
+            } else {
+                const T *dp = static_cast<const T *>(a.xw) + (size_t)(-2 - c) * R + g0;
+#pragma unroll
+                for (int g = 0; g < G; ++g) s[g] -= v * dp[g];
+            }
+        }
+    }
+    if (slots) {
+        T *o = ring + (size_t)slotrow * R + g0;
+#pragma unroll
+        for (int g = 0; g < G; ++g) o[g] = s[g];
+    }
+    if (a.write_xw || u.keep) {
+        T *w = static_cast<T *>(a.xw) + (size_t)u.x * R + g0;
+#pragma unroll
+        for (int g = 0; g < G; ++g) w[g] = s[g];
+    }
+    if (dst >= 0) {  // the output type is a launch argument (one instance serves both)
+        if (a.out_f64) {
+            double *w = static_cast<double *>(a.xout) + (size_t)dst * R + g0;
+#pragma unroll
+            for (int g = 0; g < G; ++g) w[g] = static_cast<double>(s[g]);
+        } else {
+            float *w = static_cast<float *>(a.xout) + (size_t)dst * R + g0;
+#pragma unroll
+            for (int g = 0; g < G; ++g) w[g] = static_cast<float>(s[g]);
+        }
+    }
+}
+
+// System queue with software pipelining: the same work and results as
+// k_sysq (workgroups take whole systems from a counter, a workgroup barrier
+// between levels, the last levels' values in an LDS ring), but the
+// wavefronts form k groups that take a system's levels in turn, and each
+// thread owns M items of its group's levels (item t = thread in group +
+// m * group size, G right-hand sides of one row), held in P register sets:
+// a set's row data is loaded P turns (P * k levels) before its level is
+// solved and its right-hand sides (whose address needs the row's gather
+// index) H = P / 2 turns before, so that the barrier-separated levels do
+// not wait on memory.  k is as large as the system's widest level allows.
+// Items beyond M * group size of a wide level are solved directly.  Needs no
+// CSR tail, ELL width 1..MW and R a multiple of G (checked by the host); rows
+// read beyond a ring are also stored to xw.  The level tables come as
+// separate restrict arguments, so that their uniform reads are scalar loads
+// (a vector load waited for inside a level would also wait for every
+// prefetch issued before it).
+template <typename T, typename TIn, int G, int MW, int M, int P>
+__global__ void __launch_bounds__(512) k_sysq_pipe(TriArgs a, const int32_t *__restrict__ lvp,
+                                                   const int32_t *__restrict__ lvrow,
+                                                   const int32_t *__restrict__ rings)
+{
+    constexpr int H = P / 2;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_q;
+    __shared__ unsigned s_epoch;
+    T *ring = reinterpret_cast<T *>(smem);
+    const int tid = threadIdx.x, nt = blockDim.x;
+    // the wavefront index as a uniform value: level numbers derived from it
+    // stay scalar, so the level table reads remain scalar loads
+    const int nw = nt >> 6, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int R = a.R, NG = R / G;
+    SqItem<T, TIn, G, MW> S[P][M];
+    if (tid == 0) s_epoch = __hip_atomic_load(a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (;;) {
+        if (tid == 0)
+            s_q = (int)__hip_atomic_fetch_add(&a.epoch[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const int q = s_q;
+        if (q >= a.nparts) break;
+        const int slots = rings[2 * q], W = rings[2 * q + 1];
+        const int zrow = slots * W;
+        // optional clocks per system: start, end
+        if (a.trace && tid == 0 && a.trace_stride > 0)
+            a.trace[2 * (size_t)q * a.trace_stride] = __builtin_amdgcn_s_memrealtime();
+        for (int t = tid; t < R; t += nt) ring[(size_t)zrow * R + t] = T(0);
+        const int l0 = lvp[q], l1 = lvp[q + 1];
+        // a Krylov solve's mask of unfinished (system, rhs) problems: a
+        // system whose right-hand sides have all finished is skipped (its
+        // rows feed only its own problems)
+        if (a.act && l1 > l0) {
+            const int sys = a.seg ? a.seg[lvrow[l0]] : 0;
+            int live = 0;
+            for (int k2 = 0; k2 < R; ++k2) live |= a.act[(size_t)sys * R + k2];
+            if (!live) {
+                __syncthreads();  // every thread has read s_q before it is reused
+                continue;
+            }
+        }
+        // wavefront groups: the system's widest level needs `need`
+        // wavefronts (M items per thread); k = nw / wpg groups take the
+        // levels in turn (group g solves levels l0 + g, l0 + g + k, ...), so
+        // a wavefront's P register sets reach P * k levels ahead
+        const int need = (W * NG + 64 * M - 1) / (64 * M);
+        int wpg = 1;
+        while (wpg < need && wpg < nw) wpg *= 2;
+        const int k = nw / wpg, grp = wave / wpg, ng = wpg * 64, tl = tid - grp * ng;
+        int im[M], gm[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int t = tl + m * ng;
+            im[m] = t / NG;
+            gm[m] = (t - im[m] * NG) * G;
+        }
+        if (l1 > l0) {
+            // each set's right-hand sides right after its row data, so that
+            // (as in the steady state) many loads follow them: the counter
+            // wait before the first level then covers that set alone
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+#pragma unroll
+                for (int m = 0; m < M; ++m) sq_rows(a, lvrow, S[p][m], l0 + grp + p * k, l1, im[m]);
+                if (p < H) {
+#pragma unroll
+                    for (int m = 0; m < M; ++m) sq_rhs(a, S[p][m], gm[m]);
+                }
+            }
+        }
+        __syncthreads();
+        // one barrier per level, for every wavefront: the levels of the
+        // other groups before and after this group's level of the round
+        const int nr = (l1 - l0 + k - 1) / k;
+        for (int r0 = 0; r0 < nr; r0 += P) {
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const int r = r0 + p;
+                if (r >= nr) break;
+                const int nlr = min(k, l1 - l0 - r * k);  // levels in this round
+                for (int g = 0; g < min(grp, nlr); ++g) __syncthreads();
+                // this group's level (past the system's end in a short last
+                // round: nothing is solved there, the loads are clamped)
+                const int l = l0 + r * k + grp;
+#pragma unroll
+                for (int m = 0; m < M; ++m) sq_rhs(a, S[(p + H) % P][m], gm[m]);
+                const int base = slots ? ((l - l0) % slots) * W : 0;
+#pragma unroll
+                for (int m = 0; m < M; ++m)
+                    sq_solve<T, TIn, G, MW>(a, S[p][m], ring, zrow, slots, base + im[m], gm[m]);
+                // items beyond the pipeline (two at a time per thread
+                // measured slower: more registers)
+                const int items = l < l1 ? (lvrow[l + 1] - lvrow[l]) * NG : 0;
+                for (int t = tl + M * ng; t < items; t += ng) {
+                    SqItem<T, TIn, G, MW> u;
+                    const int i = t / NG;
+                    sq_rows(a, lvrow, u, l, l1, i);
+                    sq_rhs(a, u, (t - i * NG) * G);
+                    sq_solve<T, TIn, G, MW>(a, u, ring, zrow, slots, base + i, (t - i * NG) * G);
+                }
+#pragma unroll
+                for (int m = 0; m < M; ++m) sq_rows(a, lvrow, S[p][m], l + P * k, l1, im[m]);
+                if (grp < nlr) __syncthreads();
+                for (int g = grp + 1; g < nlr; ++g) __syncthreads();
+            }
+        }
+        if (a.trace && tid == 0 && a.trace_stride > 0)
+            a.trace[2 * (size_t)q * a.trace_stride + 1] = __builtin_amdgcn_s_memrealtime();
+    }
+    if (tid == 0) {
+        const unsigned done = __hip_atomic_fetch_add(&a.epoch[1], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (done == gridDim.x - 1) {
+            // last workgroup out: every claim is over; reset the queue
+            __hip_atomic_store(&a.epoch[2], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.epoch[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.epoch[0], s_epoch + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_fill_sentinel(T *p, size_t count, unsigned *counter)
 {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) p[i] = sentinel<T>();
     if (counter && i == 0) *counter = 0u;  // the next launch's chunk counter
+}
+
+using SqKernel = void (*)(TriArgs, const int32_t *, const int32_t *, const int32_t *);
+
+// Pipelined system-queue instance for ELL width w: one item per thread and
+// four levels in flight (wider levels solve their items beyond 512
+// directly), or, when at least a quarter of the levels hold more than 512
+// items, two items per thread and two levels in flight (more items per
+// thread spill registers).
+template <typename T, typename TIn, int G, int MW>
+SqKernel sysq_pipe_width(bool wide)
+{
+    if (!wide) return k_sysq_pipe<T, TIn, G, MW, 1, 4>;
+    return k_sysq_pipe<T, TIn, G, MW, 2, 2>;
+}
+
+// Right-hand sides per thread: 4 (pairs of lanes share a row, so a
+// wavefront's right-hand-side loads and result stores touch half as many
+// scattered cache lines as with 8) when the median level then still fits one
+// item per thread, else 8.
+inline int sysq_group(int R, int median_rows)
+{
+    if (R % 4 == 0 && (R % 8 != 0 || (int64_t)median_rows * (R / 4) <= 512)) return 4;
+    return 8;
+}
+
+template <typename T, typename TIn>
+SqKernel sysq_pipe_kernel(int w, const std::vector<int32_t> &widths, int G, int R)
+{
+    const int groups = R / G;
+    size_t wide = 0;
+    for (const int32_t r : widths) wide += (size_t)r * groups > 512;
+    const bool many = 4 * wide >= widths.size();
+    if (G == 4) return w <= 4 ? sysq_pipe_width<T, TIn, 4, 4>(many) : sysq_pipe_width<T, TIn, 4, 8>(many);
+    return w <= 4 ? sysq_pipe_width<T, TIn, 8, 4>(many) : sysq_pipe_width<T, TIn, 8, 8>(many);
 }
 
 template <typename T, typename TIn, typename TOut>
@@ -1510,6 +1790,18 @@ void launch_typed(DevTri &d, TriArgs a, hipStream_t st)
         const size_t lds = (size_t)std::max(1, d.sq_lds_rows) * a.R * sizeof(T);
         if (lds > (size_t)device_max_lds())
             fail(HEC_ERR_CAPACITY, "system queue: the LDS ring exceeds the device limit at this nrhs");
+        a.nparts = d.groups;
+        // no CSR tail, ELL width 1..8 and right-hand sides in groups of
+        // 4 or 8: the pipelined kernel
+        if (!d.has_tail && d.w >= 1 && d.w <= 8 && a.R % 4 == 0) {
+            const SqKernel k =
+                sysq_pipe_kernel<T, TIn>(d.w, d.sq_widths, sysq_group(a.R, d.sq_median_rows), a.R);
+            const int32_t cap = capacity_of((const void *)k, 512, lds);
+            const int grid = std::max(1, std::min(d.groups, cap));
+            hipLaunchKernelGGL(k, dim3(grid), dim3(512), lds, st, a, a.sq_lvp, a.sq_lvrow, a.sq_ring);
+            hip_check(hipGetLastError(), "k_sysq_pipe launch");
+            return;
+        }
         const int block = std::max(64, std::min(1024, d.block));
         const int32_t cap = capacity_of((const void *)k_sysq<T, TIn, TOut>, block, lds);
         a.nparts = d.groups;
@@ -1748,6 +2040,7 @@ void launch_tri(DevTri &d, const void *bin, hec_dtype_t in_dt, const int32_t *ga
     a.sq_lvp = d.sq_lvp.as<int32_t>();
     a.sq_lvrow = d.sq_lvrow.as<int32_t>();
     a.sq_ring = d.sq_ring.as<int32_t>();
+    a.sq_keep = d.sq_keep.as<int8_t>();
     a.in_f64 = in_dt == HEC_F64 ? 1 : 0;
     a.out_f64 = out_dt == HEC_F64 ? 1 : 0;
     if (d.dt == HEC_F64) launch_in<double>(d, a, in_dt, out_dt, st);

@@ -334,7 +334,7 @@ def test_batch_krylov_rejects_coupling():
 
 
 @pytest.mark.parametrize("fdt", ["f64", "f32"])
-@pytest.mark.parametrize("R", [1, 8])
+@pytest.mark.parametrize("R", [1, 4, 8, 16])
 def test_system_queue_matches_level_launches(fdt, R):
     # kernel variant 7 computes every row as the per-level launches do: the
     # same bits, for batches (systems) and RAS (subdomains)
@@ -358,6 +358,29 @@ def test_system_queue_matches_level_launches(fdt, R):
     doms = oracle.ras_setup(B, owner, 8, overlap=1)
     ref = oracle.ras_apply(doms, r) if fdt == "f64" else oracle.ras_apply_f32(oracle.ras_to_f32(doms), r)
     assert relerr(apply(s1, r), ref) <= (FP64_TOL if fdt == "f64" else 1e-5)
+
+
+@pytest.mark.parametrize("fdt", ["f64", "f32"])
+def test_system_queue_wide_levels(fdt):
+    # 16 right-hand sides in two groups of 8 per row: levels of up to 520
+    # rows give 1040 items, more than the 512 threads hold in flight twice,
+    # so the widest levels also take the direct path
+    A = synth.poisson2d(520)
+    R = 16
+    tq = H.tune_default(schedule="level_persistent", kernel_variant=7, max_nrhs=R, block_threads=512)
+    tl = H.tune_default(schedule="level_launch", max_nrhs=R)
+    f = H.ilu_setup(A, "ilu0", factor_dtype=fdt, tune=tq)
+    g = H.ilu_setup(A, "ilu0", factor_dtype=fdt, tune=tl)
+    st = H.tri_plan_stats(H.ilu_plans(f)[0])
+    assert st["sysq"] == 1
+    r = synth.rhs(A.n, R, 49)
+    z = apply(f, r)
+    assert np.array_equal(z, apply(g, r))
+    L, U = oracle.ilu0(A)
+    if fdt == "f64":
+        assert relerr(z, oracle.ilu_apply(L, U, r)) <= FP64_TOL
+    else:
+        assert relerr(z, oracle.ilu_apply_f32(oracle.to_f32(L), oracle.to_f32(U), r)) <= 1e-5
 
 
 def test_system_queue_reads_beyond_its_ring():
