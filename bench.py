@@ -195,6 +195,12 @@ def _kernel_name(st):
         return "k_dataflow" + (" (part queue)" if st.get("queue") else "")
     if st["syncfree"]:
         return "k_syncfree"
+    if st["sysq"]:
+        # the pipelined system queue: no CSR tail, ELL width 1..8, RHS in
+        # groups of 4 or 8; otherwise the plain system queue
+        R = st.get("nrhs", 0)
+        ok = st["nnz_tail"] == 0 and 1 <= st["ell_width"] <= 8 and R % 4 == 0
+        return "k_sysq_pipe" if ok else "k_sysq"
     return "k_level" if st["schedule"] == 1 else "k_persistent"
 
 
@@ -341,7 +347,7 @@ def _cfg4(H, torch, np, synth, args):
     out = {"workload": "RAS on 128^3 Poisson (n=2097152): 64 seeded contiguous subdomains (8192..61440 rows), "
                        "overlap 1, ILU(0) per subdomain in FP32, 16 RHS; FP64 BiCGSTAB to 1e-10",
            "apply_ms": round(ms, 4), "apply_GBps": round(B / (ms * 1e-3) / 1e9, 3), "counted_bytes_per_apply": int(B),
-           "solves_per_s": round(1000.0 * R / ms, 2), "roofline": _roofline(stl, B, ms),
+           "solves_per_s": round(1000.0 * R / ms, 2), "roofline": _roofline(dict(stl, nrhs=R), B, ms),
            "extended_rows": int(tot), "nlev_L": stl["nlev"], "nlev_U": stu["nlev"], "setup_s": round(setup, 3),
            "parts_L": stl["num_groups"]}
     zg = torch.empty_like(r)
@@ -404,7 +410,7 @@ def _cfg5(H, torch, np, synth, args):
         reps = max(5, args.steps // 2)
         ms = _time_apply(H, torch, f, b, z, reps, 2)
         row = {"apply_ms": round(ms, 4), "apply_GBps": round(B / (ms * 1e-3) / 1e9, 3),
-               "counted_bytes_per_apply": int(B), "roofline": _roofline(stl, B, ms),
+               "counted_bytes_per_apply": int(B), "roofline": _roofline(dict(stl, nrhs=R), B, ms),
                "solves_per_s": round(1000.0 * len(mats) * R / ms, 1),
                "nlev_L": stl["nlev"], "nlev_U": stu["nlev"], "setup_s": round(setup, 3), "parts_L": stl["num_groups"]}
         zg = torch.empty_like(b)

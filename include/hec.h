@@ -60,8 +60,8 @@ typedef enum hec_uplo { HEC_LOWER = 0, HEC_UPPER = 1 } hec_uplo_t;
 typedef enum hec_schedule {
     HEC_SCHED_AUTO = 0,              /* the owner schedule on the dataflow kernel when its LDS
                                         holds every part for max_nrhs right-hand sides, else
-                                        the barrier-free kernel or one launch per level
-                                        (see kernel_variant) */
+                                        the system queue, the barrier-free kernel or one
+                                        launch per level (see kernel_variant) */
     HEC_SCHED_LEVEL_LAUNCH = 1,      /* one kernel launch per level (Algorithm 2 shape) */
     HEC_SCHED_LEVEL_PERSISTENT = 2,  /* one persistent launch; each level split into
                                         per-workgroup chunks; a chunk polls the values it
@@ -127,12 +127,16 @@ typedef struct hec_tune {
                                systems, RAS subdomains, or the whole matrix), largest first,
                                from a queue and solve each level by level with a workgroup
                                barrier between levels, the last levels of the system held in
-                               an LDS ring (no co-residency needed; block_threads sets the
-                               workgroup).
+                               an LDS ring (no co-residency needed).  Without a CSR tail, with
+                               ELL width 1..8 (the automatic width covers the longest row up
+                               to 8) and a multiple of 4 right-hand sides, a pipelined kernel of 512
+                               threads prefetches each level's rows several levels ahead;
+                               otherwise block_threads sets the workgroup.
                                Schedule AUTO picks the dataflow kernel when its LDS holds
-                               every part, else 5 unless the levels are very wide (2^20
-                               (row, rhs) items per level on average or more), else one
-                               launch per level */
+                               every part, else 7 for at least half as many independent
+                               systems as compute units, else 5 unless the levels are very
+                               wide (2^20 (row, rhs) items per level on average or more),
+                               else one launch per level */
 } hec_tune_t;
 
 /* Per-RHS outcome of krylov_solve. */
