@@ -408,3 +408,21 @@ def test_system_queue_layout():
     with pytest.raises(H.HecError):  # the system queue runs the level schedule only
         H.tri_analyze(synth.random_lower(50, 0.05, seed=1), tune=H.tune_default(
             host_only=1, schedule="owner_persistent", kernel_variant=7))
+
+
+@pytest.mark.parametrize("nsys,sysq", [(130, 1), (100, 0)])
+def test_automatic_system_queue_for_large_batches(nsys, sysq):
+    # a batch whose solutions exceed the LDS of all workgroups: with at least
+    # half as many systems as compute units (256 assumed without a device) the
+    # automatic schedule takes the system queue, with fewer the barrier-free
+    # kernel
+    import scipy.sparse as sp
+
+    P = synth.poisson2d(90)
+    m = sp.block_diag([P.to_scipy()] * nsys).tocsr()
+    m.sort_indices()
+    A = CSR(m.shape[0], m.indptr.astype(np.int32), m.indices.astype(np.int32), m.data.copy())
+    ptr = (np.arange(nsys + 1) * P.n).astype(np.int32)
+    f = H.batch_setup(A, ptr, "ilu0", tune=H.tune_default(host_only=1, max_nrhs=8))
+    st = H.tri_plan_stats(H.ilu_plans(f)[0])
+    assert st["sysq"] == sysq and st["syncfree"] == 1 - sysq and st["dataflow"] == 0
