@@ -1728,15 +1728,16 @@ __global__ void __launch_bounds__(256) k_fill_sentinel(T *p, size_t count, unsig
 
 using SqKernel = void (*)(TriArgs, const int32_t *, const int32_t *, const int32_t *);
 
-// Pipelined system-queue instance for ELL width w: one item per thread and
-// four levels in flight (wider levels solve their items beyond 512
-// directly), or, when at least a quarter of the levels hold more than 512
-// items, two items per thread and two levels in flight (more items per
-// thread spill registers).
+// Pipelined system-queue instance for ELL width w: one item per thread
+// (wider levels solve their items beyond 512 directly), or, when at least a
+// quarter of the levels hold more than 512 items, two items per thread; two
+// register sets either way (four sets measured 7% slower on 256 batched
+// systems: more loads in flight per wavefront; more items per thread spill
+// registers).
 template <typename T, typename TIn, int G, int MW>
 SqKernel sysq_pipe_width(bool wide)
 {
-    if (!wide) return k_sysq_pipe<T, TIn, G, MW, 1, 4>;
+    if (!wide) return k_sysq_pipe<T, TIn, G, MW, 1, 2>;
     return k_sysq_pipe<T, TIn, G, MW, 2, 2>;
 }
 
